@@ -1,0 +1,480 @@
+/*
+ * FP64 CPU oracle for contracting-grid event reconstruction (ANTS2,
+ * arXiv:1602.07247).  TEST INFRASTRUCTURE ONLY: the library under
+ * paper_1602_07247_amd/ never links, loads or calls this file.  Only the
+ * tests, the smoke check and the CPU-baseline leg of the benchmark use it.
+ *
+ * Everything is plain double precision, one event at a time, written to be
+ * checked against the paper by eye rather than to be fast.  Events are
+ * independent, so an OpenMP loop over events gives the same bits as a
+ * single thread.
+ *
+ * Passages followed:
+ *   - centroid start position ........... Sec. 5.1.1, the CoG equation
+ *   - start options (CoG / strongest) ... Sec. 5.1.2.1
+ *   - statistic (ML or least squares) ... Sec. 5.1.2
+ *   - contracting grid, energy ratio .... Sec. 5.1.2.2
+ *   - passive sensors ................... Sec. 5.3
+ *   - LRF as cubic B-splines (1-D axial, 2-D XY, r-z) ... Sec. 6, 6.1.1, 6.1.2
+ *   - one LRF shared by a group with per-sensor relative gains ... Sec. 6.2
+ *   - learned seed (fully connected ReLU net, trained by back-propagation)
+ *     ... Sec. 5.1.3
+ * Readings where the paper is silent are listed in the design notes; each
+ * is restated where it is used below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* status bits (same meaning as the library's; values restated here) */
+#define O_EMPTY 1
+#define O_BAD_INPUT 2
+#define O_NO_ACTIVE 4
+#define O_NO_VALID_NODE 8
+#define O_FALLBACK 16
+#define O_TIE 32
+
+#define O_AXIAL 1
+#define O_XY 2
+#define O_RZ 3
+
+typedef struct {
+  int kind;             /* 1 axial (r), 2 XY (x,y), 3 r-z (r,z)          */
+  int n_sensors;
+  const double* sxy;    /* [n][2] sensor centres (mm)                     */
+  const double* gain;   /* [n] relative gain                              */
+  const uint8_t* active;/* [n] 0 = passive                                */
+  int shared;           /* 1: one coefficient table for all sensors       */
+  int nb[2];            /* breakpoints per axis, both ends included       */
+  double lo[2], hi[2];  /* spline domain per axis                         */
+  const double* coef;   /* [n_lrf][nb[1]+2][nb[0]+2] (axis 1 unused = 1 row) */
+} o_lrf;
+
+typedef struct {
+  int nodes[3];
+  int iterations;
+  double shrink;
+  double step0[3];
+  double z_start;
+  int stat;             /* 0 ML, 1 chi2 */
+  int start;            /* 0 CoG, 1 strongest sensor, 2 seed */
+  double l_floor, v_floor;
+} o_cfg;
+
+/* ------------------------------------------------------------------ */
+/* Cubic B-spline on a uniform extended knot vector (Sec. 6, reading:   */
+/* breakpoints lo + m*d, m = 0..nb-1, and nb+2 coefficients; coefficient */
+/* j belongs to the B-spline centred on breakpoint j-1).                 */
+/* ------------------------------------------------------------------ */
+
+/* Uniform cubic B-spline basis on one interval, t in [0,1]. */
+void o_basis(double t, double b[4]) {
+  double s = 1.0 - t;
+  b[0] = s * s * s / 6.0;
+  b[1] = (3.0 * t * t * t - 6.0 * t * t + 4.0) / 6.0;
+  b[2] = (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;
+  b[3] = t * t * t / 6.0;
+}
+
+/* Derivative of the basis with respect to t. */
+static void o_basis_dt(double t, double b[4]) {
+  double s = 1.0 - t;
+  b[0] = -0.5 * s * s;
+  b[1] = (9.0 * t * t - 12.0 * t) / 6.0;
+  b[2] = (-9.0 * t * t + 6.0 * t + 3.0) / 6.0;
+  b[3] = 0.5 * t * t;
+}
+
+/* Locate u: returns 0 when u is outside [lo,hi] (with a relative slack of
+ * 1e-9 of the span, so grid nodes placed on a domain edge by floating-point
+ * arithmetic stay inside); else the interval m and local coordinate t. */
+static int o_locate(double u, int nb, double lo, double hi, int* m, double* t) {
+  double span = hi - lo;
+  double tol = 1e-9 * span;
+  if (!(u >= lo - tol && u <= hi + tol)) return 0;
+  int nint = nb - 1;
+  double d = span / nint;
+  double v = (u - lo) / d;
+  int k = (int)floor(v);
+  if (k < 0) k = 0;
+  if (k > nint - 1) k = nint - 1;
+  *m = k;
+  *t = v - k;
+  return 1;
+}
+
+/* 1-D spline value; 0 outside the domain. */
+double o_spline1(const double* c, int nb, double lo, double hi, double u) {
+  int m;
+  double t, b[4];
+  if (!o_locate(u, nb, lo, hi, &m, &t)) return 0.0;
+  o_basis(t, b);
+  return c[m] * b[0] + c[m + 1] * b[1] + c[m + 2] * b[2] + c[m + 3] * b[3];
+}
+
+/* 1-D spline derivative d/du; 0 outside the domain. */
+double o_spline1_du(const double* c, int nb, double lo, double hi, double u) {
+  int m;
+  double t, b[4];
+  if (!o_locate(u, nb, lo, hi, &m, &t)) return 0.0;
+  o_basis_dt(t, b);
+  double d = (hi - lo) / (nb - 1);
+  return (c[m] * b[0] + c[m + 1] * b[1] + c[m + 2] * b[2] + c[m + 3] * b[3]) / d;
+}
+
+/* 2-D tensor-product spline, coefficient table [nb1+2][nb0+2]; u on axis 0. */
+double o_spline2(const double* c, const int nb[2], const double lo[2], const double hi[2],
+                 double u, double w, double* du, double* dw) {
+  int m0, m1;
+  double t0, t1, b0[4], b1[4], d0[4], d1[4];
+  if (du) *du = 0.0;
+  if (dw) *dw = 0.0;
+  if (!o_locate(u, nb[0], lo[0], hi[0], &m0, &t0)) return 0.0;
+  if (!o_locate(w, nb[1], lo[1], hi[1], &m1, &t1)) return 0.0;
+  o_basis(t0, b0);
+  o_basis(t1, b1);
+  o_basis_dt(t0, d0);
+  o_basis_dt(t1, d1);
+  int ld = nb[0] + 2;
+  double v = 0.0, vu = 0.0, vw = 0.0;
+  for (int a = 0; a < 4; ++a)
+    for (int q = 0; q < 4; ++q) {
+      double cc = c[(m1 + a) * ld + (m0 + q)];
+      v += cc * b1[a] * b0[q];
+      vu += cc * b1[a] * d0[q];
+      vw += cc * d1[a] * b0[q];
+    }
+  if (du) *du = vu / ((hi[0] - lo[0]) / (nb[0] - 1));
+  if (dw) *dw = vw / ((hi[1] - lo[1]) / (nb[1] - 1));
+  return v;
+}
+
+/* Independent evaluator for the pins: Cox-de Boor recursion on the full
+ * extended knot vector knots[k] = lo + (k-3)*d, k = 0..nc+3.  Shares no
+ * arithmetic with o_basis. */
+double o_deboor1(const double* c, int nb, double lo, double hi, double u) {
+  int nc = nb + 2;
+  double d = (hi - lo) / (nb - 1);
+  int nk = nc + 4;
+  double knots[512];
+  if (nk > 512) return NAN;
+  for (int k = 0; k < nk; ++k) knots[k] = lo + (k - 3) * d;
+  if (u < lo || u > hi) return 0.0;
+  /* span index mu with knots[mu] <= u < knots[mu+1], restricted to the
+   * domain spans 3 .. nc-1 */
+  int mu = 3;
+  while (mu < nc - 1 && u >= knots[mu + 1]) ++mu;
+  /* degree-0 .. degree-3 basis via the recursion */
+  double N[4][4];
+  memset(N, 0, sizeof(N));
+  N[0][0] = 1.0; /* B_{mu,0} */
+  for (int p = 1; p <= 3; ++p) {
+    /* N[p][r] holds B_{mu-p+r, p} for r = 0..p */
+    for (int r = 0; r <= p; ++r) {
+      int j = mu - p + r;
+      double left = 0.0, right = 0.0;
+      if (r - 1 >= 0) {
+        double den = knots[j + p] - knots[j];
+        left = (u - knots[j]) / den * N[p - 1][r - 1];
+      }
+      if (r <= p - 1) {
+        double den = knots[j + p + 1] - knots[j + 1];
+        right = (knots[j + p + 1] - u) / den * N[p - 1][r];
+      }
+      N[p][r] = left + right;
+    }
+  }
+  double v = 0.0;
+  for (int r = 0; r <= 3; ++r) v += c[mu - 3 + r] * N[3][r];
+  return v;
+}
+
+/* ------------------------------------------------------------------ */
+/* LRF of sensor i at a source position (Sec. 6): max(spline, 0) inside */
+/* the domain, 0 outside (reading).                                     */
+/* ------------------------------------------------------------------ */
+static const double* o_table(const o_lrf* L, int i) {
+  size_t per = (size_t)(L->nb[0] + 2) * (size_t)(L->kind == O_AXIAL ? 1 : (L->nb[1] + 2));
+  return L->coef + (L->shared ? 0 : (size_t)i * per);
+}
+
+double o_lrf_value(const o_lrf* L, int i, double x, double y, double z) {
+  double dx = x - L->sxy[2 * i], dy = y - L->sxy[2 * i + 1];
+  double v;
+  if (L->kind == O_AXIAL) {
+    double r = sqrt(dx * dx + dy * dy);
+    v = o_spline1(o_table(L, i), L->nb[0], L->lo[0], L->hi[0], r);
+  } else if (L->kind == O_XY) {
+    v = o_spline2(o_table(L, i), L->nb, L->lo, L->hi, x, y, NULL, NULL);
+  } else {
+    double r = sqrt(dx * dx + dy * dy);
+    v = o_spline2(o_table(L, i), L->nb, L->lo, L->hi, r, z, NULL, NULL);
+  }
+  return v > 0.0 ? v : 0.0;
+}
+
+/* Gradient of the LRF with respect to (x, y, z); zero where the LRF is
+ * clamped to 0.  Used by the Cramer-Rao bound only. */
+static double o_lrf_grad(const o_lrf* L, int i, double x, double y, double z, double g[3]) {
+  double dx = x - L->sxy[2 * i], dy = y - L->sxy[2 * i + 1];
+  double v = 0.0;
+  g[0] = g[1] = g[2] = 0.0;
+  if (L->kind == O_AXIAL) {
+    double r = sqrt(dx * dx + dy * dy);
+    const double* c = o_table(L, i);
+    v = o_spline1(c, L->nb[0], L->lo[0], L->hi[0], r);
+    double dr = o_spline1_du(c, L->nb[0], L->lo[0], L->hi[0], r);
+    if (r > 0) { g[0] = dr * dx / r; g[1] = dr * dy / r; }
+  } else if (L->kind == O_XY) {
+    double du, dw;
+    v = o_spline2(o_table(L, i), L->nb, L->lo, L->hi, x, y, &du, &dw);
+    g[0] = du; g[1] = dw;
+  } else {
+    double r = sqrt(dx * dx + dy * dy), du, dw;
+    v = o_spline2(o_table(L, i), L->nb, L->lo, L->hi, r, z, &du, &dw);
+    if (r > 0) { g[0] = du * dx / r; g[1] = du * dy / r; }
+    g[2] = dw;
+  }
+  if (v <= 0.0) { g[0] = g[1] = g[2] = 0.0; return 0.0; }
+  return v;
+}
+
+/* ------------------------------------------------------------------ */
+/* Match statistic at one node (Sec. 5.1.2 and 5.1.2.2).                */
+/*   S  = sum over active sensors of g_i L_i                            */
+/*   A  = N / S          (the energy ratio of Sec. 5.1.2.2)             */
+/*   mu_i = A g_i L_i                                                   */
+/*   ML: l = sum [ n_i ln(A g_i max(L_i, l_floor)) - mu_i ] with the    */
+/*       n_i = 0 terms reduced to -mu_i (0 ln 0 = 0); the constant      */
+/*       -sum ln n_i! is dropped (reading).  Minimised quantity: -l.    */
+/*   chi2 = sum (n_i - mu_i)^2 / max(mu_i, v_floor)                     */
+/* Returns the minimised statistic, +inf when S <= 0 or not finite.     */
+/* ------------------------------------------------------------------ */
+typedef struct { double stat, S, A, lnl, chi2; } o_node;
+
+o_node o_node_eval(const o_lrf* L, const o_cfg* C, const double* n, double N,
+                   double x, double y, double z) {
+  o_node r;
+  double S = 0.0;
+  int ns = L->n_sensors;
+  double* Lv = (double*)malloc(sizeof(double) * (size_t)ns);
+  for (int i = 0; i < ns; ++i) {
+    if (!L->active[i]) { Lv[i] = 0.0; continue; }
+    Lv[i] = o_lrf_value(L, i, x, y, z);
+    S += L->gain[i] * Lv[i];
+  }
+  r.S = S;
+  if (!(S > 0.0) || !isfinite(S)) {
+    r.stat = INFINITY; r.A = NAN; r.lnl = NAN; r.chi2 = NAN;
+    free(Lv);
+    return r;
+  }
+  double A = N / S;
+  double lnl = 0.0, chi2 = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    if (!L->active[i]) continue;
+    double mu = A * L->gain[i] * Lv[i];
+    double Lt = Lv[i] > C->l_floor ? Lv[i] : C->l_floor;
+    if (n[i] > 0.0) lnl += n[i] * log(A * L->gain[i] * Lt);
+    lnl -= mu;
+    double var = mu > C->v_floor ? mu : C->v_floor;
+    chi2 += (n[i] - mu) * (n[i] - mu) / var;
+  }
+  free(Lv);
+  r.A = A; r.lnl = lnl; r.chi2 = chi2;
+  r.stat = (C->stat == 0) ? -lnl : chi2;
+  if (!isfinite(r.stat)) r.stat = INFINITY;
+  return r;
+}
+
+/* Node coordinates on the grid of one iteration (Sec. 5.1.2.2: a regular
+ * grid centred at the current centre).  Node index (jz*ny + jy)*nx + jx. */
+static void o_node_pos(const o_cfg* C, const double c[3], const double s[3], int j, double p[3]) {
+  int nx = C->nodes[0], ny = C->nodes[1];
+  int jx = j % nx, jy = (j / nx) % ny, jz = j / (nx * ny);
+  p[0] = c[0] + (double)(jx - (nx - 1) / 2) * s[0];
+  p[1] = c[1] + (double)(jy - (ny - 1) / 2) * s[1];
+  p[2] = c[2] + (double)(jz - (C->nodes[2] - 1) / 2) * s[2];
+}
+
+/* ------------------------------------------------------------------ */
+/* One event.  Outputs: x,y,z,E,lnl,chi2,ndf,status and per-iteration  */
+/* best node index and gap between the two best statistics.            */
+/* ------------------------------------------------------------------ */
+void o_event(const o_lrf* L, const o_cfg* C, const double* n, const double* seed,
+             double out[6], int* ndf, int* status, int* path, double* gaps) {
+  int ns = L->n_sensors;
+  int na = 0, bad = 0;
+  double N = 0.0;
+  *status = 0;
+  for (int i = 0; i < ns; ++i) {
+    if (!L->active[i]) continue;
+    ++na;
+    if (!isfinite(n[i]) || n[i] < 0.0) bad = 1;
+    else N += n[i];
+  }
+  int dim = (C->nodes[2] > 1) ? 3 : 2;
+  *ndf = na - (dim + 1);
+  for (int k = 0; k < 6; ++k) out[k] = NAN;
+  for (int k = 0; k < C->iterations; ++k) { if (path) path[k] = -1; if (gaps) gaps[k] = NAN; }
+  if (na == 0) { *status = O_NO_ACTIVE; return; }
+  if (bad) { *status = O_BAD_INPUT; return; }
+  if (!(N > 0.0)) { *status = O_EMPTY; return; }
+
+  /* start position (Sec. 5.1.1 centroid, or Sec. 5.1.2.1 strongest sensor) */
+  double c[3];
+  if (C->start == 2 && seed) {
+    c[0] = seed[0]; c[1] = seed[1]; c[2] = seed[2];
+  } else if (C->start == 1) {
+    int best = -1;
+    for (int i = 0; i < ns; ++i)
+      if (L->active[i] && (best < 0 || n[i] > n[best])) best = i;
+    c[0] = L->sxy[2 * best]; c[1] = L->sxy[2 * best + 1]; c[2] = C->z_start;
+  } else {
+    double sw = 0.0, sx = 0.0, sy = 0.0;
+    for (int i = 0; i < ns; ++i) {
+      if (!L->active[i]) continue;
+      double w = n[i] / L->gain[i];
+      sw += w; sx += L->sxy[2 * i] * w; sy += L->sxy[2 * i + 1] * w;
+    }
+    c[0] = sx / sw; c[1] = sy / sw; c[2] = C->z_start;
+  }
+  if (dim == 2) c[2] = C->z_start;
+
+  int nn = C->nodes[0] * C->nodes[1] * C->nodes[2];
+  double s[3] = {C->step0[0], C->step0[1], C->step0[2]};
+  for (int k = 0; k < C->iterations; ++k) {
+    double b1 = INFINITY, b2 = INFINITY;
+    int j1 = -1;
+    for (int j = 0; j < nn; ++j) {
+      double p[3];
+      o_node_pos(C, c, s, j, p);
+      o_node r = o_node_eval(L, C, n, N, p[0], p[1], p[2]);
+      /* lexicographic minimum of (statistic, node index) */
+      if (r.stat < b1) { b2 = b1; b1 = r.stat; j1 = j; }
+      else if (r.stat < b2) { b2 = r.stat; }
+    }
+    if (path) path[k] = j1;
+    if (gaps) gaps[k] = b2 - b1;
+    if (j1 < 0) {            /* every node invalid: keep the centre */
+      *status |= O_NO_VALID_NODE;
+    } else {
+      if (b1 == b2) *status |= O_TIE;   /* exact tie, resolved by index */
+      double p[3];
+      o_node_pos(C, c, s, j1, p);
+      c[0] = p[0]; c[1] = p[1]; c[2] = p[2];
+    }
+    s[0] *= C->shrink; s[1] *= C->shrink; s[2] *= C->shrink;
+  }
+  o_node r = o_node_eval(L, C, n, N, c[0], c[1], c[2]);
+  out[0] = c[0]; out[1] = c[1]; out[2] = c[2];
+  out[3] = r.A; out[4] = r.lnl; out[5] = r.chi2;
+}
+
+/* Batch over events; signals [n_ev][n_sensors] as double. */
+void o_reconstruct(const o_lrf* L, const o_cfg* C, int64_t n_ev, const double* sig,
+                   const double* seeds, double* out6, int* ndf, int* status,
+                   int* path, double* gaps, int n_threads) {
+  int K = C->iterations;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+  for (int64_t e = 0; e < n_ev; ++e) {
+    o_event(L, C, sig + e * L->n_sensors, seeds ? seeds + 4 * e : NULL, out6 + 6 * e,
+            ndf + e, status + e, path ? path + e * K : NULL, gaps ? gaps + e * K : NULL);
+  }
+}
+
+/* Statistic of every node of an arbitrary lattice (for brute-force pins). */
+void o_lattice_stats(const o_lrf* L, const o_cfg* C, const double* n, const double c[3],
+                     const double s[3], const int nodes[3], double* stats, int n_threads) {
+  double N = 0.0;
+  for (int i = 0; i < L->n_sensors; ++i) if (L->active[i]) N += n[i];
+  int64_t nn = (int64_t)nodes[0] * nodes[1] * nodes[2];
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+  for (int64_t j = 0; j < nn; ++j) {
+    int64_t jx = j % nodes[0], jy = (j / nodes[0]) % nodes[1], jz = j / ((int64_t)nodes[0] * nodes[1]);
+    double x = c[0] + (double)(jx - (nodes[0] - 1) / 2) * s[0];
+    double y = c[1] + (double)(jy - (nodes[1] - 1) / 2) * s[1];
+    double z = c[2] + (double)(jz - (nodes[2] - 1) / 2) * s[2];
+    stats[j] = o_node_eval(L, C, n, N, x, y, z).stat;
+  }
+}
+
+/* Node evaluation exposed for pins: returns stat and fills S, A, lnl, chi2. */
+void o_node_eval_ext(const o_lrf* L, const o_cfg* C, const double* n, double x, double y,
+                     double z, double res[5]) {
+  double N = 0.0;
+  for (int i = 0; i < L->n_sensors; ++i) if (L->active[i]) N += n[i];
+  o_node r = o_node_eval(L, C, n, N, x, y, z);
+  res[0] = r.stat; res[1] = r.S; res[2] = r.A; res[3] = r.lnl; res[4] = r.chi2;
+}
+
+/* LRF values for many positions: vals[p][i]. */
+void o_lrf_values(const o_lrf* L, int64_t n_pos, const double* pos3, double* vals, int n_threads) {
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+  for (int64_t p = 0; p < n_pos; ++p)
+    for (int i = 0; i < L->n_sensors; ++i)
+      vals[p * L->n_sensors + i] = o_lrf_value(L, i, pos3[3 * p], pos3[3 * p + 1], pos3[3 * p + 2]);
+}
+
+/* Expected counts for event generation: mu_i = A g_i L_i with
+ * A = E_tot / sum_active g_i L_i (the total expected photoelectrons over
+ * active sensors equals E_tot).  Passive sensors get 0. */
+void o_expected_counts(const o_lrf* L, int64_t n_pos, const double* pos3, const double* etot,
+                       double* mu, int n_threads) {
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+  for (int64_t p = 0; p < n_pos; ++p) {
+    double S = 0.0;
+    double* m = mu + p * L->n_sensors;
+    for (int i = 0; i < L->n_sensors; ++i) {
+      m[i] = L->active[i] ? L->gain[i] * o_lrf_value(L, i, pos3[3 * p], pos3[3 * p + 1], pos3[3 * p + 2]) : 0.0;
+      S += m[i];
+    }
+    double A = S > 0 ? etot[p] / S : 0.0;
+    for (int i = 0; i < L->n_sensors; ++i) m[i] *= A;
+  }
+}
+
+/* Cramer-Rao bound on (x, y[, z]) at the true position for Poisson counts
+ * with means mu_i = A g_i L_i(x,y,z); parameters theta = (x, y, [z], A).
+ * Fisher information I_jk = sum_i d_j mu_i d_k mu_i / mu_i.
+ * Writes the diagonal of I^-1 for the position parameters. */
+void o_crb(const o_lrf* L, int dim, int64_t n_pos, const double* pos3, const double* A,
+           double* var_out /* [n][dim] */) {
+  for (int64_t p = 0; p < n_pos; ++p) {
+    int np = dim + 1;
+    double I[4][4];
+    memset(I, 0, sizeof(I));
+    for (int i = 0; i < L->n_sensors; ++i) {
+      if (!L->active[i]) continue;
+      double g[3];
+      double v = o_lrf_grad(L, i, pos3[3 * p], pos3[3 * p + 1], pos3[3 * p + 2], g);
+      double mu = A[p] * L->gain[i] * v;
+      if (!(mu > 0)) continue;
+      double d[4];
+      for (int a = 0; a < dim; ++a) d[a] = A[p] * L->gain[i] * g[a];
+      d[dim] = L->gain[i] * v;
+      for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) I[a][b] += d[a] * d[b] / mu;
+    }
+    /* invert the small symmetric matrix by Gauss-Jordan */
+    double M[4][8];
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < 2 * np; ++b) M[a][b] = (b < np) ? I[a][b] : (b - np == a ? 1.0 : 0.0);
+    int ok = 1;
+    for (int col = 0; col < np; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < np; ++r) if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+      if (M[piv][col] == 0.0) { ok = 0; break; }
+      if (piv != col) for (int b = 0; b < 2 * np; ++b) { double t = M[col][b]; M[col][b] = M[piv][b]; M[piv][b] = t; }
+      double inv = 1.0 / M[col][col];
+      for (int b = 0; b < 2 * np; ++b) M[col][b] *= inv;
+      for (int r = 0; r < np; ++r) {
+        if (r == col) continue;
+        double f = M[r][col];
+        for (int b = 0; b < 2 * np; ++b) M[r][b] -= f * M[col][b];
+      }
+    }
+    for (int a = 0; a < dim; ++a) var_out[p * dim + a] = ok ? M[a][np + a] : NAN;
+  }
+}

@@ -1,0 +1,160 @@
+/*
+ * ants.h -- C ABI of the MI355X contracting-grid reconstruction library
+ * (statistical event reconstruction for Anger-camera detectors after the
+ * ANTS2 package, arXiv:1602.07247).
+ *
+ * Conventions for every entry point:
+ *   - Return value: ants_status, 0 = OK, < 0 = error.  No entry point aborts
+ *     or throws; after an error, ants_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Pointers named d_* are device pointers on the current HIP device;
+ *     all other pointers are host pointers.  Host arrays inside descriptors
+ *     are copied before the call returns; the caller keeps ownership.
+ *   - Event and output buffers belong to the caller; the library never
+ *     frees or reallocates them.
+ *   - Work is enqueued asynchronously on `hip_stream` (a hipStream_t, NULL
+ *     = the default stream); the caller synchronises.  Handles own their
+ *     device memory and may be used from one stream at a time.
+ *   - Floating-point layouts are row-major.
+ */
+#ifndef ANTS_H
+#define ANTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ANTS_OK = 0,
+  ANTS_E_ARG = -1,          /* invalid argument (NULL, size, range)          */
+  ANTS_E_FORMAT = -2,       /* malformed descriptor or file                  */
+  ANTS_E_DEVICE = -3,       /* HIP runtime error                             */
+  ANTS_E_NOMEM = -4,        /* device or host allocation failed              */
+  ANTS_E_UNSUPPORTED = -5,  /* valid but not supported combination           */
+  ANTS_E_STATE = -6         /* handle not ready (e.g. network not trained)   */
+} ants_status;
+
+/* Per-event status bits (ants_out.status).  Per-event problems never fail
+ * a call.  Events with EMPTY, BAD_INPUT or NO_ACTIVE get NaN outputs. */
+#define ANTS_EV_EMPTY 1          /* sum of active signals <= 0               */
+#define ANTS_EV_BAD_INPUT 2      /* an active signal is NaN, Inf or negative */
+#define ANTS_EV_NO_ACTIVE 4      /* every sensor is passive                  */
+#define ANTS_EV_NO_VALID_NODE 8  /* at some iteration no node had S > 0      */
+#define ANTS_EV_FALLBACK 16      /* seeded path re-ran the event on the full grid */
+#define ANTS_EV_TIE 32           /* an exact tie of the statistic was broken by node index */
+
+const char* ants_last_error(void);
+const char* ants_version(void);
+
+/* ------------------------------------------------------------------ */
+/* LRF sets (Sec. 6: light response functions as cubic B-splines;      */
+/* Sec. 6.1.1 "Axial" and "XY"; Sec. 6.1.2 r-z as a 2-D spline in the   */
+/* distance from the sensor axis and the depth; Sec. 6.2 one LRF shared */
+/* by a group with relative gains; Sec. 5.3 passive sensors).           */
+/*                                                                     */
+/* Spline convention: on each axis nb breakpoints lo + m*(hi-lo)/(nb-1) */
+/* (m = 0..nb-1) and nb+2 coefficients of the uniform cubic B-spline on */
+/* the extended knot vector; coefficient j belongs to the B-spline      */
+/* centred on breakpoint j-1.  LRF = max(spline, 0) inside the domain   */
+/* (with a relative slack of 1e-9 of the span), 0 outside.  For AXIAL   */
+/* and RZ the first axis is r (lo[0] must be 0); RZ's second axis is z; */
+/* XY's axes are global x and y.                                        */
+/* ------------------------------------------------------------------ */
+typedef enum { ANTS_LRF_AXIAL = 1, ANTS_LRF_XY = 2, ANTS_LRF_RZ = 3 } ants_lrf_kind;
+
+typedef struct {
+  int32_t n_sensors;          /* 1 .. 256                                       */
+  const double* sensor_xy;    /* [n_sensors][2] sensor centres, mm               */
+  const double* gain;         /* [n_sensors] relative gains g_i > 0; NULL = 1    */
+  const uint8_t* active;      /* [n_sensors] 0 = passive; NULL = all active      */
+  int32_t kind;               /* ants_lrf_kind                                   */
+  int32_t shared;             /* 1: one table for all sensors; 0: one per sensor
+                                 (RZ requires 1)                                  */
+  int32_t n_knots[2];         /* breakpoints per axis (>= 2, <= 256); axis 1
+                                 ignored for AXIAL                                */
+  double lo[2], hi[2];        /* spline domain per axis, mm                      */
+  const double* coef;         /* [n_tables][n_knots[1]+2][n_knots[0]+2] FP64;
+                                 AXIAL: [n_tables][n_knots[0]+2]                  */
+} ants_lrf_desc;
+
+typedef struct ants_lrfset ants_lrfset;   /* opaque; owns its device copies */
+
+/* Validates the descriptor, compacts the active sensors and uploads FP32
+ * piecewise-polynomial tables (for the screening pass) and the FP64
+ * coefficients (for decisions and reported values) to the current device.
+ * Errors: ANTS_E_ARG (NULL / sizes), ANTS_E_FORMAT (non-finite values,
+ * lo >= hi, gain <= 0), ANTS_E_UNSUPPORTED (lo[0] != 0 for r, RZ per
+ * sensor), ANTS_E_NOMEM, ANTS_E_DEVICE.  *out is NULL on error. */
+ants_status ants_lrfset_create(const ants_lrf_desc* desc, ants_lrfset** out);
+ants_status ants_lrfset_destroy(ants_lrfset* set);   /* NULL is a no-op */
+/* n_sensors (row length of the signal matrix), active count and kind. */
+ants_status ants_lrfset_info(const ants_lrfset* set, int32_t* n_sensors, int32_t* n_active,
+                             int32_t* kind);
+
+/* ------------------------------------------------------------------ */
+/* Contracting-grid search (Sec. 5.1.2.2).  Per event:                  */
+/*  - start at the gain-weighted centroid (Sec. 5.1.1), the strongest    */
+/*    active sensor (Sec. 5.1.2.1; lowest index on ties) or a seed;      */
+/*  - iteration k evaluates a regular nodes[0] x nodes[1] x nodes[2]     */
+/*    grid with step step0 * shrink^k centred on the current centre;     */
+/*    node j = (jz*ny + jy)*nx + jx sits at centre + (j_a - (n_a-1)/2)*s_a;*/
+/*  - at each node: S = sum_active g_i L_i, A = N/S with N = sum_active   */
+/*    n_i (energy as the ratio of the two sums, Sec. 5.1.2.2), and the    */
+/*    statistic (Sec. 5.1.2: maximum likelihood or least squares):       */
+/*      ML:   -lnL, lnL = sum[n_i ln(A g_i max(L_i,l_floor)) - A g_i L_i] */
+/*            (terms with n_i = 0 reduce to -A g_i L_i; -sum ln n_i!      */
+/*            dropped);                                                   */
+/*      CHI2: sum (n_i - A g_i L_i)^2 / max(A g_i L_i, v_floor);          */
+/*    S <= 0 makes a node invalid (+inf);                                 */
+/*  - the node with the smallest (statistic, index) becomes the centre.  */
+/* Outputs at the final centre: x, y, z (z = z_start for 2-D grids),     */
+/* E = A, lnl = lnL, chi2 (both always), ndf = n_active - (d+1) with     */
+/* d = 2 or 3.  Decisions between close nodes are taken in FP64, so the  */
+/* path matches an FP64 evaluation of the same definitions.             */
+/* ------------------------------------------------------------------ */
+typedef enum { ANTS_STAT_ML = 0, ANTS_STAT_CHI2 = 1 } ants_stat;
+typedef enum { ANTS_START_COG = 0, ANTS_START_MAXSENSOR = 1, ANTS_START_SEED = 2 } ants_start;
+
+typedef struct {
+  int32_t nodes[3];        /* odd, >= 1; nodes[2] = 1 for 2-D; product <= 512  */
+  int32_t iterations;      /* K grids evaluated, 0 .. 64 (0 returns the start) */
+  double shrink;           /* step factor per iteration, (0, 1]                */
+  double step0[3];         /* initial step per axis, mm (> 0 where nodes > 1)  */
+  double z_start;          /* z of the start for 3-D grids and z output of 2-D */
+  int32_t stat;            /* ants_stat                                        */
+  int32_t start;           /* ants_start                                       */
+  double l_floor;          /* floor of L inside the logarithm (default 1e-9)   */
+  double v_floor;          /* chi2 variance floor (default 1)                  */
+  double screen_scale;     /* multiplier (>= 1) on the error bound of the FP32
+                              screening pass; nodes within it of the best are
+                              re-decided in FP64.  0 = default (1).            */
+} ants_grid_cfg;
+
+/* Caller-owned device arrays of length n_events (path: [n][iterations]).
+ * x..status are required; path and n_fp64 may be NULL. */
+typedef struct {
+  float* x;
+  float* y;
+  float* z;
+  float* E;
+  float* lnl;
+  float* chi2;
+  int32_t* ndf;
+  int32_t* status;
+  int32_t* path;     /* optional: winning node index per iteration (-1 = none) */
+  int32_t* n_fp64;   /* optional: node evaluations re-done in FP64 per event   */
+} ants_out;
+
+/* Reconstruct d_signals [n_events][n_sensors] (FP32, row-major; counts or
+ * gain-corrected amplitudes).  d_seeds [n_events][4] = (x, y, z, unused) is
+ * read only when cfg->start == ANTS_START_SEED.  n_events may be 0. */
+ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t n_events,
+                             const float* d_signals, const float* d_seeds, ants_out out,
+                             void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ANTS_H */

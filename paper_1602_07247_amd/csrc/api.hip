@@ -1,0 +1,303 @@
+// Host side of the C ABI declared in include/ants.h: argument checking,
+// LRF-set upload (FP32 piecewise-polynomial tables for the screening pass,
+// FP64 B-spline coefficients for decisions and outputs) and kernel launch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ants_internal.h"
+
+using namespace ants;
+
+namespace {
+
+thread_local std::string g_err;
+
+ants_status fail(ants_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ants_status fail(ants_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+ants_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? ANTS_E_NOMEM : ANTS_E_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+template <class T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+  *dst = nullptr;
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// B-spline coefficients c[m..m+3] of one interval -> polynomial in t
+void to_poly(const double* c, double out[4]) {
+  out[0] = (c[0] + 4.0 * c[1] + c[2]) / 6.0;
+  out[1] = (c[2] - c[0]) / 2.0;
+  out[2] = (c[0] - 2.0 * c[1] + c[2]) / 2.0;
+  out[3] = (-c[0] + 3.0 * c[1] - 3.0 * c[2] + c[3]) / 6.0;
+}
+
+int g_num_cu = 0;
+
+}  // namespace
+
+struct ants_lrfset {
+  DevLrf d;
+  int device;
+  int ns;
+  std::vector<void*> allocs;
+};
+
+extern "C" {
+
+const char* ants_last_error(void) { return g_err.c_str(); }
+const char* ants_version(void) { return "ants-mi355x 0.1 (gfx950)"; }
+
+ants_status ants_lrfset_destroy(ants_lrfset* set) {
+  if (!set) return ANTS_OK;
+  for (void* p : set->allocs) (void)hipFree(p);
+  delete set;
+  return ANTS_OK;
+}
+
+ants_status ants_lrfset_info(const ants_lrfset* set, int32_t* n_sensors, int32_t* n_active,
+                             int32_t* kind) {
+  if (!set) return fail(ANTS_E_ARG, "ants_lrfset_info: NULL set");
+  if (n_sensors) *n_sensors = set->ns;
+  if (n_active) *n_active = set->d.na;
+  if (kind) *kind = set->d.kind;
+  return ANTS_OK;
+}
+
+ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
+  if (!out) return fail(ANTS_E_ARG, "ants_lrfset_create: NULL out");
+  *out = nullptr;
+  if (!D) return fail(ANTS_E_ARG, "ants_lrfset_create: NULL descriptor");
+  const int ns = D->n_sensors;
+  if (ns < 1 || ns > kMaxSensors)
+    return fail(ANTS_E_ARG, "n_sensors = %d outside 1..%d", ns, kMaxSensors);
+  if (!D->sensor_xy || !D->coef) return fail(ANTS_E_ARG, "sensor_xy and coef are required");
+  const int kind = D->kind;
+  if (kind != ANTS_LRF_AXIAL && kind != ANTS_LRF_XY && kind != ANTS_LRF_RZ)
+    return fail(ANTS_E_ARG, "unknown LRF kind %d", kind);
+  const int nb0 = D->n_knots[0];
+  const int nb1 = kind == ANTS_LRF_AXIAL ? 1 : D->n_knots[1];
+  if (nb0 < 2 || nb0 > 256 || (kind != ANTS_LRF_AXIAL && (nb1 < 2 || nb1 > 256)))
+    return fail(ANTS_E_ARG, "n_knots (%d, %d) outside 2..256", D->n_knots[0], D->n_knots[1]);
+  const int naxes = kind == ANTS_LRF_AXIAL ? 1 : 2;
+  for (int a = 0; a < naxes; ++a)
+    if (!(isfinite(D->lo[a]) && isfinite(D->hi[a]) && D->lo[a] < D->hi[a]))
+      return fail(ANTS_E_FORMAT, "axis %d domain [%g, %g] invalid", a, D->lo[a], D->hi[a]);
+  if (kind != ANTS_LRF_XY && D->lo[0] != 0.0)
+    return fail(ANTS_E_UNSUPPORTED, "the r axis must start at 0 (lo[0] = %g)", D->lo[0]);
+  if (kind == ANTS_LRF_RZ && !D->shared)
+    return fail(ANTS_E_UNSUPPORTED, "r-z LRFs must be shared by all sensors");
+  const int nc0 = nb0 + 2, nc1 = kind == ANTS_LRF_AXIAL ? 1 : nb1 + 2;
+  const int ntab = D->shared ? 1 : ns;
+  const size_t per = (size_t)nc0 * nc1;
+  for (size_t i = 0; i < per * ntab; ++i)
+    if (!isfinite(D->coef[i])) return fail(ANTS_E_FORMAT, "coef[%zu] is not finite", i);
+  for (int i = 0; i < 2 * ns; ++i)
+    if (!isfinite(D->sensor_xy[i])) return fail(ANTS_E_FORMAT, "sensor_xy[%d] not finite", i);
+  if (D->gain)
+    for (int i = 0; i < ns; ++i)
+      if (!(D->gain[i] > 0.0 && isfinite(D->gain[i])))
+        return fail(ANTS_E_FORMAT, "gain[%d] = %g must be positive", i, D->gain[i]);
+
+  // active sensors in their original order
+  std::vector<int32_t> col, tab;
+  std::vector<double> X, Y, g;
+  for (int i = 0; i < ns; ++i) {
+    if (D->active && !D->active[i]) continue;
+    col.push_back(i);
+    tab.push_back(D->shared ? 0 : i);
+    X.push_back(D->sensor_xy[2 * i]);
+    Y.push_back(D->sensor_xy[2 * i + 1]);
+    g.push_back(D->gain ? D->gain[i] : 1.0);
+  }
+  const int na = (int)col.size();
+
+  const int nint0 = nb0 - 1;
+  const int nintp = nint0 + 1;  // one all-zero interval past the domain end
+  std::vector<float> pp, c32;
+  if (kind == ANTS_LRF_AXIAL || kind == ANTS_LRF_RZ) {
+    const int rows = kind == ANTS_LRF_AXIAL ? ntab : nc1;
+    pp.assign((size_t)rows * nintp * 4, 0.f);
+    for (int r = 0; r < rows; ++r)
+      for (int m = 0; m < nint0; ++m) {
+        double p[4];
+        to_poly(D->coef + (size_t)r * nc0 + m, p);
+        for (int k = 0; k < 4; ++k) pp[((size_t)r * nintp + m) * 4 + k] = (float)p[k];
+      }
+    if (kind == ANTS_LRF_AXIAL && (size_t)ntab * nintp * 16 > 48 * 1024)
+      return fail(ANTS_E_UNSUPPORTED, "per-sensor axial tables exceed 48 KiB of LDS");
+  } else {
+    c32.resize(per * ntab);
+    for (size_t i = 0; i < c32.size(); ++i) c32[i] = (float)D->coef[i];
+  }
+
+  ants_lrfset* S = new ants_lrfset();
+  hipGetDevice(&S->device);
+  S->ns = ns;
+  DevLrf& d = S->d;
+  memset(&d, 0, sizeof(d));
+  d.kind = kind;
+  d.shared = D->shared ? 1 : 0;
+  d.ns = ns;
+  d.na = na;
+  d.nb0 = nb0;
+  d.nb1 = nb1;
+  d.nc0 = nc0;
+  d.nc1 = nc1;
+  d.nintp = nintp;
+  d.ntab = ntab;
+  d.lo0 = D->lo[0];
+  d.hi0 = D->hi[0];
+  d.lo1 = kind == ANTS_LRF_AXIAL ? 0.0 : D->lo[1];
+  d.hi1 = kind == ANTS_LRF_AXIAL ? 1.0 : D->hi[1];
+  d.d0 = (d.hi0 - d.lo0) / (nb0 - 1);
+  d.d1 = kind == ANTS_LRF_AXIAL ? 1.0 : (d.hi1 - d.lo1) / (nb1 - 1);
+  d.finv0 = (float)(1.0 / d.d0);
+
+  hipError_t e = hipSuccess;
+  int32_t *dcol = nullptr, *dtab = nullptr;
+  double *dX = nullptr, *dY = nullptr, *dg = nullptr, *dc64 = nullptr;
+  float *dpp = nullptr, *dc32 = nullptr;
+  if (e == hipSuccess) e = upload(&dcol, col.data(), col.size());
+  if (dcol) S->allocs.push_back(dcol);
+  if (e == hipSuccess) e = upload(&dtab, tab.data(), tab.size());
+  if (dtab) S->allocs.push_back(dtab);
+  if (e == hipSuccess) e = upload(&dX, X.data(), X.size());
+  if (dX) S->allocs.push_back(dX);
+  if (e == hipSuccess) e = upload(&dY, Y.data(), Y.size());
+  if (dY) S->allocs.push_back(dY);
+  if (e == hipSuccess) e = upload(&dg, g.data(), g.size());
+  if (dg) S->allocs.push_back(dg);
+  if (e == hipSuccess) e = upload(&dc64, D->coef, per * ntab);
+  if (dc64) S->allocs.push_back(dc64);
+  if (e == hipSuccess) e = upload(&dpp, pp.data(), pp.size());
+  if (dpp) S->allocs.push_back(dpp);
+  if (e == hipSuccess) e = upload(&dc32, c32.data(), c32.size());
+  if (dc32) S->allocs.push_back(dc32);
+  if (e != hipSuccess) {
+    ants_lrfset_destroy(S);
+    return hip_fail(e, "ants_lrfset_create upload");
+  }
+  d.col = dcol;
+  d.tab = dtab;
+  d.X = dX;
+  d.Y = dY;
+  d.g = dg;
+  d.pp = dpp;
+  d.c32 = dc32;
+  d.c64 = dc64;
+  *out = S;
+  return ANTS_OK;
+}
+
+ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t n_events,
+                             const float* d_signals, const float* d_seeds, ants_out out,
+                             void* hip_stream) {
+  if (!set || !cfg) return fail(ANTS_E_ARG, "ants_reconstruct: NULL set or cfg");
+  if (n_events < 0) return fail(ANTS_E_ARG, "n_events = %lld < 0", (long long)n_events);
+  if (n_events > ((int64_t)1 << 31) - 1)
+    return fail(ANTS_E_ARG, "n_events = %lld exceeds 2^31-1", (long long)n_events);
+  const DevLrf& L = set->d;
+  GridP G;
+  memset(&G, 0, sizeof(G));
+  G.nx = cfg->nodes[0];
+  G.ny = cfg->nodes[1];
+  G.nz = cfg->nodes[2];
+  for (int a = 0; a < 3; ++a)
+    if (cfg->nodes[a] < 1 || cfg->nodes[a] % 2 == 0)
+      return fail(ANTS_E_ARG, "nodes[%d] = %d must be odd and >= 1", a, cfg->nodes[a]);
+  if ((int64_t)G.nx * G.ny * G.nz > kMaxNodes)
+    return fail(ANTS_E_ARG, "grid of %d x %d x %d exceeds %d nodes", G.nx, G.ny, G.nz,
+                kMaxNodes);
+  if (L.kind != ANTS_LRF_RZ && G.nz != 1)
+    return fail(ANTS_E_ARG, "a 2-D LRF needs nodes[2] = 1");
+  G.nn = G.nx * G.ny * G.nz;
+  G.hx = (G.nx - 1) / 2;
+  G.hy = (G.ny - 1) / 2;
+  G.hz = (G.nz - 1) / 2;
+  G.K = cfg->iterations;
+  if (G.K < 0 || G.K > 64) return fail(ANTS_E_ARG, "iterations = %d outside 0..64", G.K);
+  if (!(cfg->shrink > 0.0 && cfg->shrink <= 1.0))
+    return fail(ANTS_E_ARG, "shrink = %g outside (0, 1]", cfg->shrink);
+  for (int a = 0; a < 3; ++a)
+    if (cfg->nodes[a] > 1 && !(cfg->step0[a] > 0.0 && isfinite(cfg->step0[a])))
+      return fail(ANTS_E_ARG, "step0[%d] = %g must be positive", a, cfg->step0[a]);
+  if (!(cfg->l_floor > 0.0) || !(cfg->v_floor > 0.0))
+    return fail(ANTS_E_ARG, "l_floor and v_floor must be positive");
+  if (cfg->stat != ANTS_STAT_ML && cfg->stat != ANTS_STAT_CHI2)
+    return fail(ANTS_E_ARG, "unknown statistic %d", cfg->stat);
+  if (cfg->start < ANTS_START_COG || cfg->start > ANTS_START_SEED)
+    return fail(ANTS_E_ARG, "unknown start option %d", cfg->start);
+  if (cfg->start == ANTS_START_SEED && !d_seeds)
+    return fail(ANTS_E_ARG, "start = SEED needs d_seeds");
+  if (!(cfg->screen_scale == 0.0 || cfg->screen_scale >= 1.0))
+    return fail(ANTS_E_ARG, "screen_scale = %g must be 0 or >= 1", cfg->screen_scale);
+  if (!isfinite(cfg->z_start)) return fail(ANTS_E_ARG, "z_start not finite");
+  G.dim = G.nz > 1 ? 3 : 2;
+  G.stat = cfg->stat;
+  G.start = cfg->start;
+  G.shrink = cfg->shrink;
+  G.s0x = G.nx > 1 ? cfg->step0[0] : 0.0;
+  G.s0y = G.ny > 1 ? cfg->step0[1] : 0.0;
+  G.s0z = G.nz > 1 ? cfg->step0[2] : 0.0;
+  G.z_start = cfg->z_start;
+  G.lfloor = cfg->l_floor;
+  G.vfloor = cfg->v_floor;
+  double sc = cfg->screen_scale == 0.0 ? 1.0 : cfg->screen_scale;
+  G.margin_scale = sc > 3e38 ? 3e38f : (float)sc;
+  if (n_events == 0) return ANTS_OK;
+  if (!d_signals) return fail(ANTS_E_ARG, "d_signals is NULL");
+  if (!out.x || !out.y || !out.z || !out.E || !out.lnl || !out.chi2 || !out.ndf || !out.status)
+    return fail(ANTS_E_ARG, "an ants_out field other than path/n_fp64 is NULL");
+
+  IoP io;
+  memset(&io, 0, sizeof(io));
+  io.sig = d_signals;
+  io.ld = set->ns;
+  io.seeds = d_seeds;
+  io.x = out.x;
+  io.y = out.y;
+  io.z = out.z;
+  io.E = out.E;
+  io.lnl = out.lnl;
+  io.chi2 = out.chi2;
+  io.ndf = out.ndf;
+  io.status = out.status;
+  io.path = out.path;
+  io.nfp = out.n_fp64;
+  io.n = n_events;
+
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != set->device)
+    return fail(ANTS_E_ARG, "LRF set lives on device %d, current device is %d", set->device,
+                dev);
+  if (g_num_cu == 0) {
+    if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || g_num_cu <= 0)
+      g_num_cu = 256;
+  }
+  hipError_t e = launch_grid(L, G, io, (hipStream_t)hip_stream, g_num_cu * 8);
+  if (e != hipSuccess) return hip_fail(e, "ants_reconstruct launch");
+  return ANTS_OK;
+}
+
+}  // extern "C"

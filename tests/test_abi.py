@@ -1,0 +1,97 @@
+"""C ABI checks that need no GPU: every function declared in include/ants.h
+is exported by the library, and argument errors are reported with the
+documented codes before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(ants_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+@pytest.fixture(scope="module")
+def ants():
+    from paper_1602_07247_amd import ants as A
+    return A
+
+
+def test_every_declared_symbol_is_exported(ants):
+    lib = C.CDLL(ants.LIB_PATH)
+    declared = _declared()
+    assert declared, "no declarations found"
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(ants.EXPORTED) <= declared
+
+
+def test_version_string(ants):
+    assert "gfx950" in ants.version()
+
+
+def _desc(ants, model, **over):
+    d = ants.LrfDesc()
+    keep = []
+    sxy = np.ascontiguousarray(model.sxy, np.float64)
+    coef = np.ascontiguousarray(model.coef, np.float64)
+    keep += [sxy, coef]
+    d.n_sensors = sxy.shape[0]
+    d.sensor_xy = sxy.ctypes.data_as(C.POINTER(C.c_double))
+    d.gain = None
+    d.active = None
+    d.kind = model.kind
+    d.shared = model.shared
+    d.n_knots[0], d.n_knots[1] = model.nb
+    d.lo[0], d.lo[1] = model.lo
+    d.hi[0], d.hi[1] = model.hi
+    d.coef = coef.ctypes.data_as(C.POINTER(C.c_double))
+    for k, v in over.items():
+        if k in ("lo", "hi", "n_knots"):
+            getattr(d, k)[0] = v
+        else:
+            setattr(d, k, v)
+    return d, keep
+
+
+@pytest.mark.parametrize("over,code", [
+    ({"n_sensors": 0}, -1), ({"n_sensors": 1000}, -1), ({"kind": 9}, -1),
+    ({"n_knots": 1}, -1), ({"lo": 5.0}, -5), ({"hi": -1.0}, -2)])
+def test_descriptor_errors(ants, over, code):
+    d, keep = _desc(ants, W.axial_lrf(W.hex_array(2, 30.0)), **over)
+    h = C.c_void_p()
+    assert ants._lib.ants_lrfset_create(C.byref(d), C.byref(h)) == code
+    assert not h.value
+    assert ants._lib.ants_last_error()
+
+
+def test_non_finite_coefficient_and_rz_per_sensor(ants):
+    m = W.rz_lrf(W.hex_array(1, 30.0))
+    m.coef = m.coef.copy()
+    m.coef[0, 3, 3] = np.nan
+    d, keep = _desc(ants, m)
+    h = C.c_void_p()
+    assert ants._lib.ants_lrfset_create(C.byref(d), C.byref(h)) == ants.E_FORMAT
+    m = W.rz_lrf(W.hex_array(1, 30.0))
+    d, keep = _desc(ants, m, shared=0)
+    assert ants._lib.ants_lrfset_create(C.byref(d), C.byref(h)) == ants.E_UNSUPPORTED
+
+
+def test_reconstruct_argument_errors(ants):
+    cfg = ants.grid_cfg(W.workload(0).grid)
+    out = ants.Out()
+    assert ants._lib.ants_reconstruct(None, C.byref(cfg), 10, None, None, out, None) == ants.E_ARG
+    assert ants._lib.ants_lrfset_create(None, C.byref(C.c_void_p())) == ants.E_ARG
+    assert ants._lib.ants_lrfset_destroy(None) == ants.OK

@@ -154,6 +154,36 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
                              const float* d_signals, const float* d_seeds, ants_out out,
                              void* hip_stream);
 
+/* ------------------------------------------------------------------ */
+/* Event generator: flood-field events drawn from the LRF model itself  */
+/* (Sec. 4.1.1 "flood field"; Sec. 5.1.1 relative gains).  For event    */
+/* index i = first_event + e: position uniform over a disc of radius    */
+/* `extent` (region 0: r = extent*sqrt(u1), phi = 2*pi*u2) or a square  */
+/* of half-width `extent` (region 1), depth z = z_lo + (z_hi-z_lo)*u3   */
+/* (z_lo when z_hi <= z_lo), E_tot = e_lo + (e_hi-e_lo)*u4; expected    */
+/* counts mu_i = A g_i L_i with sum over active sensors = E_tot; counts */
+/* ~ Poisson(mu_i) (or mu_i when noiseless), passive sensors 0.          */
+/* Uniforms come from Philox4x32-10 (Salmon et al., SC'11) with key =   */
+/* seed and counter (i, stream, call): position/energy stream          */
+/* 0xFFFFFFFF calls 0 and 1; sensor column c uses stream c.  Two 32-bit */
+/* words (a, b) give u = ((a:b) >> 11 + 0.5) * 2^-53.  Poisson: below  */
+/* mu = 10 sequential-search inversion of one uniform; otherwise the    */
+/* transformed rejection method of Hoermann (1993), call t for trial t. */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t region;      /* 0 disc, 1 square                                 */
+  double extent;       /* disc radius or square half-width, mm             */
+  double z_lo, z_hi;   /* depth range, mm                                  */
+  double e_lo, e_hi;   /* total expected photoelectrons                    */
+  int32_t noiseless;   /* 1: write the means instead of Poisson draws      */
+} ants_gen_cfg;
+
+/* d_signals [n_events][n_sensors] FP32 (caller-owned device memory);
+ * d_truth [n_events][4] = (x, y, z, E_tot) or NULL. */
+ants_status ants_generate(ants_lrfset* set, const ants_gen_cfg* cfg, int64_t n_events,
+                          uint64_t seed, uint64_t first_event, float* d_signals, float* d_truth,
+                          void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

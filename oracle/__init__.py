@@ -72,6 +72,12 @@ def lib():
         _lib.o_lrf_values.argtypes = [P(_Lrf), i64, P(d), P(d), C.c_int]
         _lib.o_expected_counts.argtypes = [P(_Lrf), i64, P(d), P(d), P(d), C.c_int]
         _lib.o_crb.argtypes = [P(_Lrf), C.c_int, i64, P(d), P(d), P(d)]
+        u32 = C.c_uint32
+        _lib.o_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        _lib.o_poisson.restype = d
+        _lib.o_poisson.argtypes = [d, C.c_uint64, u32, P(u32)]
+        _lib.o_generate.argtypes = [P(_Lrf), C.c_int, d, d, d, d, d, C.c_int, C.c_uint64,
+                                    C.c_uint64, i64, P(d), P(d), C.c_int]
     return _lib
 
 
@@ -253,3 +259,30 @@ def make_events(lrf, recipe, n, rngs, noiseless=False, threads=None):
     S = (lrf_values(lrf, pos, threads) * np.asarray(lrf.gain)[None, :]
          * np.asarray(lrf.active)[None, :]).sum(1)
     return sig, {"pos": pos, "etot": etot, "A": etot / S, "mu": mu}
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: four 32-bit counter words, two key words."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().o_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def poisson(mu, event, stream, seed):
+    k = (C.c_uint32 * 2)(seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    return lib().o_poisson(float(mu), int(event), int(stream), k)
+
+
+def generate(lrf, region, extent, z_lo, z_hi, e_lo, e_hi, n, seed, first=0, noiseless=False,
+             threads=None):
+    """Reference flood-field events (see the generator's definition in the
+    library header).  Returns (signals [n][ns] float64, truth [n][4])."""
+    m = lrf if isinstance(lrf, Model) else Model(lrf)
+    truth = np.empty((n, 4), np.float64)
+    sig = np.empty((n, m.n_sensors), np.float64)
+    lib().o_generate(C.byref(m.c), int(region), float(extent), float(z_lo), float(z_hi),
+                     float(e_lo), float(e_hi), int(bool(noiseless)), int(seed), int(first), int(n),
+                     _dp(truth), _dp(sig), _threads(threads))
+    return sig, truth

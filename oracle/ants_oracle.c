@@ -22,6 +22,7 @@
  * Readings where the paper is silent are listed in the design notes; each
  * is restated where it is used below.
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -476,5 +477,106 @@ void o_crb(const o_lrf* L, int dim, int64_t n_pos, const double* pos3, const dou
       }
     }
     for (int a = 0; a < dim; ++a) var_out[p * dim + a] = ok ? M[a][np + a] : NAN;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Reference for the flood-field generator (Sec. 4.1.1 flood field):     */
+/* Philox4x32-10 as published by Salmon, Moraes, Dror and Shaw (SC'11),  */
+/* and Poisson draws by sequential-search inversion (mean < 10) or the   */
+/* transformed rejection method with squeeze of Hoermann (1993).         */
+/* ------------------------------------------------------------------ */
+void o_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k[2] = {key[0], key[1]};
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t n[4];
+    n[0] = (uint32_t)(p1 >> 32) ^ c[1] ^ k[0];
+    n[1] = (uint32_t)p1;
+    n[2] = (uint32_t)(p0 >> 32) ^ c[3] ^ k[1];
+    n[3] = (uint32_t)p0;
+    memcpy(c, n, sizeof(c));
+    k[0] += 0x9E3779B9u;
+    k[1] += 0xBB67AE85u;
+  }
+  memcpy(out, c, sizeof(c));
+}
+
+static double o_u53(uint32_t a, uint32_t b) {
+  uint64_t bits = (((uint64_t)a << 32) | b) >> 11;
+  return ((double)bits + 0.5) / 9007199254740992.0; /* 2^53 */
+}
+
+static void o_draw(uint64_t ev, uint32_t stream, uint32_t call, const uint32_t key[2], uint32_t w[4]) {
+  uint32_t ctr[4] = {(uint32_t)ev, (uint32_t)(ev >> 32), stream, call};
+  o_philox4x32_10(ctr, key, w);
+}
+
+double o_poisson(double mu, uint64_t ev, uint32_t stream, const uint32_t key[2]) {
+  uint32_t w[4];
+  if (!(mu > 0.0)) return 0.0;
+  if (mu < 10.0) {
+    o_draw(ev, stream, 0, key, w);
+    double u = o_u53(w[0], w[1]);
+    double p = exp(-mu), cdf = p;
+    int k = 0;
+    while (u > cdf && k < 1000) { ++k; p = p * (mu / k); cdf += p; }
+    return (double)k;
+  }
+  double sq = sqrt(mu), lmu = log(mu);
+  double b = 0.931 + 2.53 * sq;
+  double a = -0.059 + 0.02483 * b;
+  double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
+  double v_r = 0.9277 - 3.6224 / (b - 2.0);
+  for (uint32_t t = 0; t < 64; ++t) {
+    o_draw(ev, stream, t, key, w);
+    double U = o_u53(w[0], w[1]) - 0.5;
+    double V = o_u53(w[2], w[3]);
+    double us = 0.5 - fabs(U);
+    double k = floor((2.0 * a / us + b) * U + mu + 0.43);
+    if (us >= 0.07 && V <= v_r) return k;
+    if (k < 0.0 || (us < 0.013 && V > us)) continue;
+    if (log(V) + log(inv_alpha) - log(a / (us * us) + b) <= -mu + k * lmu - lgamma(k + 1.0)) return k;
+  }
+  return floor(mu + 0.5);
+}
+
+/* Events first..first+n-1: truth4 [n][4] = (x, y, z, E_tot), signals [n][ns]. */
+void o_generate(const o_lrf* L, int region, double extent, double z_lo, double z_hi, double e_lo,
+                double e_hi, int noiseless, uint64_t seed, uint64_t first, int64_t n,
+                double* truth4, double* sig, int n_threads) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+  for (int64_t e = 0; e < n; ++e) {
+    uint64_t ev = first + (uint64_t)e;
+    uint32_t wa[4], wb[4];
+    o_draw(ev, 0xFFFFFFFFu, 0, key, wa);
+    o_draw(ev, 0xFFFFFFFFu, 1, key, wb);
+    double u1 = o_u53(wa[0], wa[1]), u2 = o_u53(wa[2], wa[3]);
+    double u3 = o_u53(wb[0], wb[1]), u4 = o_u53(wb[2], wb[3]);
+    double x, y;
+    if (region == 0) {
+      double r = extent * sqrt(u1), phi = 2.0 * M_PI * u2;
+      x = r * cos(phi); y = r * sin(phi);
+    } else {
+      x = -extent + 2.0 * extent * u1; y = -extent + 2.0 * extent * u2;
+    }
+    double z = z_hi > z_lo ? z_lo + (z_hi - z_lo) * u3 : z_lo;
+    double E = e_lo + (e_hi - e_lo) * u4;
+    double* row = sig + e * L->n_sensors;
+    double S = 0.0;
+    for (int i = 0; i < L->n_sensors; ++i) {
+      row[i] = L->active[i] ? L->gain[i] * o_lrf_value(L, i, x, y, z) : 0.0;
+      S += row[i];
+    }
+    double A = S > 0.0 ? E / S : 0.0;
+    for (int i = 0; i < L->n_sensors; ++i) {
+      if (!L->active[i]) continue;
+      double mu = A * row[i];
+      row[i] = noiseless ? mu : o_poisson(mu, ev, (uint32_t)i, key);
+    }
+    truth4[4 * e] = x; truth4[4 * e + 1] = y; truth4[4 * e + 2] = z; truth4[4 * e + 3] = E;
   }
 }

@@ -48,6 +48,12 @@ class GridCfg(C.Structure):
                 ("screen_scale", C.c_double)]
 
 
+class GenCfg(C.Structure):
+    _fields_ = [("region", C.c_int32), ("extent", C.c_double), ("z_lo", C.c_double),
+                ("z_hi", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double),
+                ("noiseless", C.c_int32)]
+
+
 class Out(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in
                 ("x", "y", "z", "E", "lnl", "chi2", "ndf", "status", "path", "n_fp64")]
@@ -62,8 +68,11 @@ _lib.ants_lrfset_info.argtypes = [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32
                                   C.POINTER(C.c_int32)]
 _lib.ants_reconstruct.argtypes = [_vp, C.POINTER(GridCfg), C.c_int64, _vp, _vp, Out, _vp]
 
+_lib.ants_generate.argtypes = [_vp, C.POINTER(GenCfg), C.c_int64, C.c_uint64, C.c_uint64, _vp,
+                               _vp, _vp]
+
 EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfset_destroy",
-            "ants_lrfset_info", "ants_reconstruct")
+            "ants_lrfset_info", "ants_reconstruct", "ants_generate")
 
 
 def _check(code):
@@ -185,3 +194,30 @@ def reconstruct(lrfset: LrfSet, cfg: GridCfg, signals, seeds=None, out=None, str
     _check(_lib.ants_reconstruct(lrfset.handle, C.byref(cfg), n, signals.data_ptr(), sp,
                                  _out_struct(out), _stream_handle(stream)))
     return out
+
+
+def gen_cfg(recipe, noiseless=False) -> GenCfg:
+    """GenCfg from an event recipe (region, extent, e_lo, e_hi, z_lo, z_hi,
+    three_d; see workloads.EventRecipe)."""
+    c = GenCfg()
+    c.region = 0 if recipe.region == "disc" else 1
+    c.extent = float(recipe.extent)
+    c.z_lo = float(recipe.z_lo)
+    c.z_hi = float(recipe.z_hi) if recipe.three_d else float(recipe.z_lo)
+    c.e_lo = float(recipe.e_lo)
+    c.e_hi = float(recipe.e_hi)
+    c.noiseless = 1 if noiseless else 0
+    return c
+
+
+def generate(lrfset: LrfSet, cfg: GenCfg, n: int, seed: int, first: int = 0, signals=None,
+             truth=True, stream=None):
+    """Draw n flood-field events on the GPU.  Returns (signals [n][ns],
+    truth [n][4] = x, y, z, E_tot or None)."""
+    import torch
+    if signals is None:
+        signals = torch.empty((n, lrfset.n_sensors), dtype=torch.float32, device="cuda")
+    t = torch.empty((n, 4), dtype=torch.float32, device=signals.device) if truth else None
+    _check(_lib.ants_generate(lrfset.handle, C.byref(cfg), n, seed, first, signals.data_ptr(),
+                              t.data_ptr() if t is not None else None, _stream_handle(stream)))
+    return signals, t

@@ -63,6 +63,19 @@ struct IoP {
   const int32_t* list_n;   // optional: device count of list entries
 };
 
+struct GenP {
+  int64_t n;           // events
+  uint64_t first;      // global index of the first event (Philox counter)
+  uint32_t k0, k1;     // Philox key (seed)
+  int region;          // 0 disc, 1 square
+  int noiseless;
+  double extent, z_lo, z_hi, e_lo, e_hi;
+  float* sig;          // [n][ns]
+  float* truth;        // [n][4] or NULL
+};
+
+hipError_t launch_gen(const DevLrf& L, const GenP& P, hipStream_t stream, int max_blocks);
+
 // Launch the contracting-grid kernel; returns a hipError_t.
 hipError_t launch_grid(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t stream,
                        int max_blocks);

@@ -300,4 +300,44 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
   return ANTS_OK;
 }
 
+ants_status ants_generate(ants_lrfset* set, const ants_gen_cfg* cfg, int64_t n_events,
+                          uint64_t seed, uint64_t first_event, float* d_signals, float* d_truth,
+                          void* hip_stream) {
+  if (!set || !cfg) return fail(ANTS_E_ARG, "ants_generate: NULL set or cfg");
+  if (n_events < 0) return fail(ANTS_E_ARG, "n_events = %lld < 0", (long long)n_events);
+  if (cfg->region != 0 && cfg->region != 1)
+    return fail(ANTS_E_ARG, "region = %d must be 0 (disc) or 1 (square)", cfg->region);
+  if (!(cfg->extent > 0.0 && isfinite(cfg->extent)))
+    return fail(ANTS_E_ARG, "extent = %g must be positive", cfg->extent);
+  if (!(cfg->e_lo >= 0.0 && cfg->e_hi >= cfg->e_lo && isfinite(cfg->e_hi)))
+    return fail(ANTS_E_ARG, "energy range [%g, %g] invalid", cfg->e_lo, cfg->e_hi);
+  if (!isfinite(cfg->z_lo) || !isfinite(cfg->z_hi))
+    return fail(ANTS_E_ARG, "depth range not finite");
+  if (n_events == 0) return ANTS_OK;
+  if (!d_signals) return fail(ANTS_E_ARG, "d_signals is NULL");
+  GenP P;
+  memset(&P, 0, sizeof(P));
+  P.n = n_events;
+  P.first = first_event;
+  P.k0 = (uint32_t)seed;
+  P.k1 = (uint32_t)(seed >> 32);
+  P.region = cfg->region;
+  P.noiseless = cfg->noiseless ? 1 : 0;
+  P.extent = cfg->extent;
+  P.z_lo = cfg->z_lo;
+  P.z_hi = cfg->z_hi;
+  P.e_lo = cfg->e_lo;
+  P.e_hi = cfg->e_hi;
+  P.sig = d_signals;
+  P.truth = d_truth;
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != set->device)
+    return fail(ANTS_E_ARG, "LRF set lives on device %d, current device is %d", set->device,
+                dev);
+  hipError_t e = launch_gen(set->d, P, (hipStream_t)hip_stream, 256 * 16);
+  if (e != hipSuccess) return hip_fail(e, "ants_generate launch");
+  return ANTS_OK;
+}
+
 }  // extern "C"

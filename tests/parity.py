@@ -18,7 +18,8 @@ def compare(ref, gpu, signals, stat=0, three_d=False):
     iteration where the two paths diverge is within REL_TOL of the scale,
     'other' otherwise."""
     n = len(ref["x"])
-    N = np.asarray(signals, np.float64).sum(1)
+    sg = np.asarray(signals, np.float64)
+    N = np.where(np.isfinite(sg), sg, 0.0).sum(1)   # passive columns may hold NaN
     st_ref = ref["status"] & ~32
     st_gpu = gpu["status"] & ~32
     bad = (st_ref & 7) != 0

@@ -40,7 +40,22 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=24_000,
                     help="events for the oracle CPU baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=160207247)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_copy": a.numel() * 4,
+                      "copy_probe_bytes_written_per_copy": a.numel() * 4}))
 
 
 def cpu_baseline(wl, sig_host):
@@ -60,6 +75,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
     import torch
     import workloads as W
     from paper_1602_07247_amd import ants

@@ -130,6 +130,19 @@ typedef struct {
   double screen_scale;     /* multiplier (>= 1) on the error bound of the FP32
                               screening pass; nodes within it of the best are
                               re-decided in FP64.  0 = default (1).            */
+  /* Per-event steps for refining a seed (start == SEED only; seed_steps = 0
+   * keeps step0 and iterations).  With seed_steps = 1 the seed row is
+   * (x, y, z, s) with s a log-variance: sigma_a = seed_scale[a] * exp(s/2)
+   * per axis; the final step is s_f = step0 * shrink^(iterations-1) (per
+   * axis, iterated products) and the event runs K in [seed_kmin, seed_kmax]
+   * iterations from s_f * shrink^-(K-1) (iterated quotients), K the
+   * smallest with s_f * shrink^-(K-1) >= seed_kappa * sigma_a on every axis
+   * with nodes > 1 (seed_kmax when s is not finite).  Requires
+   * 1 <= seed_kmin <= seed_kmax <= iterations. */
+  int32_t seed_steps;
+  double seed_kappa;
+  int32_t seed_kmin, seed_kmax;
+  double seed_scale[3];
 } ants_grid_cfg;
 
 /* Caller-owned device arrays of length n_events (path: [n][iterations]).
@@ -183,6 +196,92 @@ typedef struct {
 ants_status ants_generate(ants_lrfset* set, const ants_gen_cfg* cfg, int64_t n_events,
                           uint64_t seed, uint64_t first_event, float* d_signals, float* d_truth,
                           void* hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Learned seed (Sec. 5.1.3: neural-network reconstruction trained on   */
+/* events with known positions; here a fully connected ReLU network     */
+/* n_in -> hidden x n_layers -> 4 maps the normalised signals           */
+/* x_a = n_a * n_active / N of the active sensors to (p_x, p_y, p_z, s):*/
+/* position p = (pos - pos_offset) / pos_scale and log-variance s).     */
+/* Weights: FP32 master copy and BF16 copy; activations BF16; products  */
+/* accumulate in FP32 on the matrix cores.  Training loss per event:    */
+/* 0.5 exp(-s) |p - t|^2 + 1.5 s, averaged over the batch; Adam.        */
+/* Flat parameter order: W1 [hidden][n_in_pad], b1, W2 [hidden][hidden], */
+/* b2, ..., W_out [4][hidden], b_out; n_in_pad = n_in rounded up to 32   */
+/* (padding columns are zero).                                          */
+/* ------------------------------------------------------------------ */
+typedef struct ants_mlp ants_mlp;   /* opaque; owns parameters, optimiser state, workspace */
+
+typedef struct {
+  int32_t n_in;            /* inputs = active sensors of the LRF set used, 1..64 */
+  int32_t hidden;          /* 256                                               */
+  int32_t n_layers;        /* hidden layers, 1..4                               */
+  uint64_t seed;           /* initialisation: He-uniform weights, zero biases   */
+  double pos_scale[3];     /* mm per output unit                                */
+  double pos_offset[3];    /* mm                                                */
+} ants_mlp_cfg;
+
+typedef struct {
+  double lr, beta1, beta2, eps;   /* Adam step size and decay rates            */
+} ants_adam_cfg;
+
+typedef struct {
+  int64_t n_train, n_val;   /* events drawn with ants_generate                    */
+  int32_t batch, epochs;
+  ants_adam_cfg adam;
+  double lr_decay;          /* step size multiplied by this after every epoch     */
+  uint64_t seed;            /* generator seed (training events start at index 0,  */
+                            /* validation events at index n_train)               */
+  ants_gen_cfg events;      /* event recipe                                       */
+} ants_train_cfg;
+
+ants_status ants_mlp_create(const ants_mlp_cfg* cfg, ants_mlp** out);
+ants_status ants_mlp_destroy(ants_mlp* mlp);     /* NULL is a no-op */
+int64_t ants_mlp_num_params(const ants_mlp* mlp);
+/* Copy the FP32 master parameters to / from host memory (n = num_params).
+ * Setting parameters refreshes the BF16 copy and clears the Adam state. */
+ants_status ants_mlp_get_params(const ants_mlp* mlp, float* host, int64_t n);
+ants_status ants_mlp_set_params(ants_mlp* mlp, const float* host, int64_t n);
+/* Network outputs d_pred [n][4] = (p_x, p_y, p_z, s) for d_signals
+ * [n][n_sensors] of `set` (its active sensors are the inputs). */
+ants_status ants_mlp_forward(ants_mlp* mlp, const ants_lrfset* set, int64_t n,
+                             const float* d_signals, float* d_pred, void* hip_stream);
+/* Gradient of the mean loss over the batch (n <= 65536) with respect to the
+ * flat parameters (d_grad, FP32) and the mean loss (d_loss, one float);
+ * d_target [n][3] true positions in mm.  No update. */
+ants_status ants_mlp_grad(ants_mlp* mlp, const ants_lrfset* set, int64_t n,
+                          const float* d_signals, const float* d_target, float* d_grad,
+                          float* d_loss, void* hip_stream);
+/* One Adam step on a batch (n <= 65536); d_loss may be NULL. */
+ants_status ants_mlp_train_step(ants_mlp* mlp, const ants_lrfset* set, int64_t n,
+                                const float* d_signals, const float* d_target,
+                                const ants_adam_cfg* adam, float* d_loss, void* hip_stream);
+/* Whole training run on events drawn from `set`'s own LRF model
+ * (ants_generate): epochs over n_train events, validation loss on n_val
+ * held-out events after each epoch; the parameters of the best validation
+ * epoch are kept.  host_losses [epochs][2] = (train, validation) mean loss
+ * or NULL.  Synchronises the stream. */
+ants_status ants_mlp_train(ants_mlp* mlp, const ants_lrfset* set, const ants_train_cfg* cfg,
+                           double* host_losses, void* hip_stream);
+/* Binary file: magic "ANTSMLP1", the ants_mlp_cfg fields, then the FP32
+ * parameters (little endian). */
+ants_status ants_mlp_save(const ants_mlp* mlp, const char* path);
+ants_status ants_mlp_load(const char* path, ants_mlp** out);
+
+/* Seeded reconstruction: seeds from the network (or from d_seeds [n][4] =
+ * (x, y, z, log-variance) in mm when d_seeds is not NULL, and then mlp may be
+ * NULL), a refinement grid `refine` started at the seed (start = SEED,
+ * normally seed_steps = 1), and events whose refined chi2/ndf exceeds
+ * chi2ndf_max (or is not finite, or ndf <= 0) run again with `fallback`
+ * (normally the plain grid from the centroid) and get ANTS_EV_FALLBACK.
+ * d_n_fallback (one int32, device) receives the number of such events.
+ * The library keeps a workspace of 16 bytes per event in the mlp handle
+ * (or the LRF set when mlp is NULL) and of 4 bytes per event for the list. */
+ants_status ants_reconstruct_seeded(ants_lrfset* set, ants_mlp* mlp,
+                                    const ants_grid_cfg* refine, const ants_grid_cfg* fallback,
+                                    double chi2ndf_max, int64_t n_events, const float* d_signals,
+                                    const float* d_seeds, ants_out out, int32_t* d_n_fallback,
+                                    void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -43,7 +43,9 @@ class _Lrf(C.Structure):
 class _Cfg(C.Structure):
     _fields_ = [("nodes", C.c_int * 3), ("iterations", C.c_int), ("shrink", C.c_double),
                 ("step0", C.c_double * 3), ("z_start", C.c_double), ("stat", C.c_int),
-                ("start", C.c_int), ("l_floor", C.c_double), ("v_floor", C.c_double)]
+                ("start", C.c_int), ("l_floor", C.c_double), ("v_floor", C.c_double),
+                ("seed_steps", C.c_int), ("seed_kappa", C.c_double), ("seed_kmin", C.c_int),
+                ("seed_kmax", C.c_int), ("seed_scale", C.c_double * 3)]
 
 
 _lib = None
@@ -72,6 +74,8 @@ def lib():
         _lib.o_lrf_values.argtypes = [P(_Lrf), i64, P(d), P(d), C.c_int]
         _lib.o_expected_counts.argtypes = [P(_Lrf), i64, P(d), P(d), P(d), C.c_int]
         _lib.o_crb.argtypes = [P(_Lrf), C.c_int, i64, P(d), P(d), P(d)]
+        _lib.o_reconstruct_seeded.argtypes = [P(_Lrf), P(_Cfg), P(_Cfg), d, i64, P(d), P(d),
+                                              P(d), P(C.c_int), P(C.c_int), C.c_int]
         u32 = C.c_uint32
         _lib.o_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
         _lib.o_poisson.restype = d
@@ -127,6 +131,12 @@ def _cfg(g):
     c.start = int(g.start)
     c.l_floor = float(g.l_floor)
     c.v_floor = float(g.v_floor)
+    c.seed_steps = int(getattr(g, "seed_steps", 0))
+    c.seed_kappa = float(getattr(g, "seed_kappa", 1.0))
+    c.seed_kmin = int(getattr(g, "seed_kmin", 1))
+    c.seed_kmax = int(getattr(g, "seed_kmax", 1))
+    for k, v in enumerate(getattr(g, "seed_scale", (0.0, 0.0, 0.0))):
+        c.seed_scale[k] = float(v)
     return c
 
 
@@ -286,3 +296,21 @@ def generate(lrf, region, extent, z_lo, z_hi, e_lo, e_hi, n, seed, first=0, nois
                      float(e_lo), float(e_hi), int(bool(noiseless)), int(seed), int(first), int(n),
                      _dp(truth), _dp(sig), _threads(threads))
     return sig, truth
+
+
+def reconstruct_seeded(lrf, refine, fallback, chi2ndf_max, signals, seeds, threads=None):
+    """Seeded reconstruction: refine from seeds [n][4] = (x, y, z, log-variance)
+    and re-run events with chi2/ndf above the threshold on the fallback grid."""
+    m = lrf if isinstance(lrf, Model) else Model(lrf)
+    sig = np.ascontiguousarray(signals, dtype=np.float64)
+    sd = np.ascontiguousarray(seeds, dtype=np.float64)
+    n = sig.shape[0]
+    out6 = np.empty((n, 6), np.float64)
+    ndf = np.empty(n, np.int32)
+    status = np.empty(n, np.int32)
+    r, f = _cfg(refine), _cfg(fallback)
+    lib().o_reconstruct_seeded(C.byref(m.c), C.byref(r), C.byref(f), float(chi2ndf_max), n,
+                               _dp(sig), _dp(sd), _dp(out6), _ip(ndf), _ip(status),
+                               _threads(threads))
+    return {"x": out6[:, 0], "y": out6[:, 1], "z": out6[:, 2], "E": out6[:, 3],
+            "lnl": out6[:, 4], "chi2": out6[:, 5], "ndf": ndf, "status": status}

@@ -61,6 +61,11 @@ typedef struct {
   int stat;             /* 0 ML, 1 chi2 */
   int start;            /* 0 CoG, 1 strongest sensor, 2 seed */
   double l_floor, v_floor;
+  /* seed refinement: per-event steps from the seed's log-variance */
+  int seed_steps;
+  double seed_kappa;
+  int seed_kmin, seed_kmax;
+  double seed_scale[3];
 } o_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -345,7 +350,39 @@ void o_event(const o_lrf* L, const o_cfg* C, const double* n, const double* seed
 
   int nn = C->nodes[0] * C->nodes[1] * C->nodes[2];
   double s[3] = {C->step0[0], C->step0[1], C->step0[2]};
-  for (int k = 0; k < C->iterations; ++k) {
+  int K = C->iterations;
+  if (C->start == 2 && seed && C->seed_steps) {
+    /* Refinement of a seed (x, y, z, log-variance): the grid ends on the
+     * configured final step s_f = step0 * shrink^(K-1); the event runs the
+     * smallest number of iterations in [kmin, kmax] whose first step
+     * s_f / shrink^(k-1) reaches kappa * sigma on every searched axis, with
+     * sigma = seed_scale * exp(log-variance / 2). */
+    double sf[3];
+    for (int a = 0; a < 3; ++a) {
+      sf[a] = C->step0[a];
+      for (int k = 1; k < C->iterations; ++k) sf[a] *= C->shrink;
+    }
+    double need = exp(0.5 * seed[3]) * C->seed_kappa;
+    int k = 0;
+    for (; k < C->seed_kmin - 1; ++k)
+      for (int a = 0; a < 3; ++a) sf[a] = sf[a] / C->shrink;
+    if (!isfinite(need)) {
+      for (; k < C->seed_kmax - 1; ++k)
+        for (int a = 0; a < 3; ++a) sf[a] = sf[a] / C->shrink;
+    } else {
+      for (;;) {
+        int short_ = 0;
+        for (int a = 0; a < 3; ++a)
+          if (C->nodes[a] > 1 && sf[a] < need * C->seed_scale[a]) short_ = 1;
+        if (!short_ || k >= C->seed_kmax - 1) break;
+        for (int a = 0; a < 3; ++a) sf[a] = sf[a] / C->shrink;
+        ++k;
+      }
+    }
+    K = k + 1;
+    for (int a = 0; a < 3; ++a) s[a] = sf[a];
+  }
+  for (int k = 0; k < K; ++k) {
     double b1 = INFINITY, b2 = INFINITY;
     int j1 = -1;
     for (int j = 0; j < nn; ++j) {
@@ -578,5 +615,23 @@ void o_generate(const o_lrf* L, int region, double extent, double z_lo, double z
       row[i] = noiseless ? mu : o_poisson(mu, ev, (uint32_t)i, key);
     }
     truth4[4 * e] = x; truth4[4 * e + 1] = y; truth4[4 * e + 2] = z; truth4[4 * e + 3] = E;
+  }
+}
+
+/* Seeded reconstruction: refine from the seed; events whose chi2/ndf at the
+ * refined node exceeds chi2ndf_max (or is not finite, or ndf <= 0) are
+ * reconstructed again with the fallback grid and flagged (status bit 16). */
+void o_reconstruct_seeded(const o_lrf* L, const o_cfg* R, const o_cfg* F, double chi2ndf_max,
+                          int64_t n_ev, const double* sig, const double* seeds, double* out6,
+                          int* ndf, int* status, int n_threads) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+  for (int64_t e = 0; e < n_ev; ++e) {
+    const double* row = sig + e * L->n_sensors;
+    o_event(L, R, row, seeds + 4 * e, out6 + 6 * e, ndf + e, status + e, NULL, NULL);
+    if (status[e] & (O_EMPTY | O_BAD_INPUT | O_NO_ACTIVE)) continue;
+    double q = out6[6 * e + 5];
+    if (ndf[e] > 0 && q / ndf[e] <= chi2ndf_max) continue;
+    o_event(L, F, row, NULL, out6 + 6 * e, ndf + e, status + e, NULL, NULL);
+    status[e] |= O_FALLBACK;
   }
 }

@@ -45,13 +45,32 @@ class GridCfg(C.Structure):
     _fields_ = [("nodes", C.c_int32 * 3), ("iterations", C.c_int32), ("shrink", C.c_double),
                 ("step0", C.c_double * 3), ("z_start", C.c_double), ("stat", C.c_int32),
                 ("start", C.c_int32), ("l_floor", C.c_double), ("v_floor", C.c_double),
-                ("screen_scale", C.c_double)]
+                ("screen_scale", C.c_double), ("seed_steps", C.c_int32),
+                ("seed_kappa", C.c_double), ("seed_kmin", C.c_int32), ("seed_kmax", C.c_int32),
+                ("seed_scale", C.c_double * 3)]
 
 
 class GenCfg(C.Structure):
     _fields_ = [("region", C.c_int32), ("extent", C.c_double), ("z_lo", C.c_double),
                 ("z_hi", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double),
                 ("noiseless", C.c_int32)]
+
+
+class MlpCfg(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("hidden", C.c_int32), ("n_layers", C.c_int32),
+                ("seed", C.c_uint64), ("pos_scale", C.c_double * 3),
+                ("pos_offset", C.c_double * 3)]
+
+
+class AdamCfg(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("n_train", C.c_int64), ("n_val", C.c_int64), ("batch", C.c_int32),
+                ("epochs", C.c_int32), ("adam", AdamCfg), ("lr_decay", C.c_double),
+                ("seed", C.c_uint64), ("events", GenCfg)]
 
 
 class Out(C.Structure):
@@ -71,8 +90,26 @@ _lib.ants_reconstruct.argtypes = [_vp, C.POINTER(GridCfg), C.c_int64, _vp, _vp, 
 _lib.ants_generate.argtypes = [_vp, C.POINTER(GenCfg), C.c_int64, C.c_uint64, C.c_uint64, _vp,
                                _vp, _vp]
 
+_lib.ants_mlp_create.argtypes = [C.POINTER(MlpCfg), C.POINTER(_vp)]
+_lib.ants_mlp_destroy.argtypes = [_vp]
+_lib.ants_mlp_num_params.argtypes = [_vp]
+_lib.ants_mlp_num_params.restype = C.c_int64
+_lib.ants_mlp_get_params.argtypes = [_vp, C.POINTER(C.c_float), C.c_int64]
+_lib.ants_mlp_set_params.argtypes = [_vp, C.POINTER(C.c_float), C.c_int64]
+_lib.ants_mlp_forward.argtypes = [_vp, _vp, C.c_int64, _vp, _vp, _vp]
+_lib.ants_mlp_grad.argtypes = [_vp, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.ants_mlp_train_step.argtypes = [_vp, _vp, C.c_int64, _vp, _vp, C.POINTER(AdamCfg), _vp, _vp]
+_lib.ants_mlp_train.argtypes = [_vp, _vp, C.POINTER(TrainCfg), C.POINTER(C.c_double), _vp]
+_lib.ants_mlp_save.argtypes = [_vp, C.c_char_p]
+_lib.ants_mlp_load.argtypes = [C.c_char_p, C.POINTER(_vp)]
+_lib.ants_reconstruct_seeded.argtypes = [_vp, _vp, C.POINTER(GridCfg), C.POINTER(GridCfg),
+                                         C.c_double, C.c_int64, _vp, _vp, Out, _vp, _vp]
+
 EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfset_destroy",
-            "ants_lrfset_info", "ants_reconstruct", "ants_generate")
+            "ants_lrfset_info", "ants_reconstruct", "ants_generate", "ants_mlp_create",
+            "ants_mlp_destroy", "ants_mlp_num_params", "ants_mlp_get_params",
+            "ants_mlp_set_params", "ants_mlp_forward", "ants_mlp_grad", "ants_mlp_train_step",
+            "ants_mlp_train", "ants_mlp_save", "ants_mlp_load", "ants_reconstruct_seeded")
 
 
 def _check(code):
@@ -145,6 +182,12 @@ def grid_cfg(g, screen_scale: float = 0.0) -> GridCfg:
     c.l_floor = float(g.l_floor)
     c.v_floor = float(g.v_floor)
     c.screen_scale = float(screen_scale)
+    c.seed_steps = int(getattr(g, "seed_steps", 0))
+    c.seed_kappa = float(getattr(g, "seed_kappa", 1.0))
+    c.seed_kmin = int(getattr(g, "seed_kmin", 1))
+    c.seed_kmax = int(getattr(g, "seed_kmax", 1))
+    for k, v in enumerate(getattr(g, "seed_scale", (0.0, 0.0, 0.0))):
+        c.seed_scale[k] = float(v)
     return c
 
 
@@ -221,3 +264,121 @@ def generate(lrfset: LrfSet, cfg: GenCfg, n: int, seed: int, first: int = 0, sig
     _check(_lib.ants_generate(lrfset.handle, C.byref(cfg), n, seed, first, signals.data_ptr(),
                               t.data_ptr() if t is not None else None, _stream_handle(stream)))
     return signals, t
+
+
+def adam_cfg(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> AdamCfg:
+    return AdamCfg(lr, beta1, beta2, eps)
+
+
+class Mlp:
+    """Learned-seed network handle (parameters, optimiser state, workspace)."""
+
+    def __init__(self, n_in=37, hidden=256, layers=3, seed=1, pos_scale=(90.0, 90.0, 25.0),
+                 pos_offset=(0.0, 0.0, 25.0), _handle=None):
+        self._h = _vp()
+        if _handle is not None:
+            self._h = _handle
+        else:
+            c = MlpCfg()
+            c.n_in, c.hidden, c.n_layers, c.seed = n_in, hidden, layers, seed
+            for k in range(3):
+                c.pos_scale[k] = pos_scale[k]
+                c.pos_offset[k] = pos_offset[k]
+            _check(_lib.ants_mlp_create(C.byref(c), C.byref(self._h)))
+        self.n_params = int(_lib.ants_mlp_num_params(self._h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def load(cls, path):
+        h = _vp()
+        _check(_lib.ants_mlp_load(str(path).encode(), C.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path):
+        _check(_lib.ants_mlp_save(self._h, str(path).encode()))
+
+    def get_params(self):
+        out = np.empty(self.n_params, np.float32)
+        _check(_lib.ants_mlp_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                        self.n_params))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        _check(_lib.ants_mlp_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                        self.n_params))
+
+    def forward(self, lrfset, signals, stream=None):
+        import torch
+        pred = torch.empty((signals.shape[0], 4), dtype=torch.float32, device=signals.device)
+        _check(_lib.ants_mlp_forward(self._h, lrfset.handle, signals.shape[0], signals.data_ptr(),
+                                     pred.data_ptr(), _stream_handle(stream)))
+        return pred
+
+    def grad(self, lrfset, signals, targets, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=signals.device)
+        loss = torch.empty(1, dtype=torch.float32, device=signals.device)
+        t = targets.contiguous()
+        _check(_lib.ants_mlp_grad(self._h, lrfset.handle, signals.shape[0], signals.data_ptr(),
+                                  t.data_ptr(), g.data_ptr(), loss.data_ptr(),
+                                  _stream_handle(stream)))
+        return g, loss
+
+    def train_step(self, lrfset, signals, targets, adam, stream=None):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=signals.device)
+        t = targets.contiguous()
+        _check(_lib.ants_mlp_train_step(self._h, lrfset.handle, signals.shape[0],
+                                        signals.data_ptr(), t.data_ptr(), C.byref(adam),
+                                        loss.data_ptr(), _stream_handle(stream)))
+        return loss
+
+    def train(self, lrfset, recipe, n_train, n_val, batch=4096, epochs=4, lr=1e-3,
+              lr_decay=0.7, seed=11, stream=None):
+        c = TrainCfg()
+        c.n_train, c.n_val, c.batch, c.epochs = n_train, n_val, batch, epochs
+        c.adam = adam_cfg(lr)
+        c.lr_decay = lr_decay
+        c.seed = seed
+        c.events = gen_cfg(recipe)
+        losses = np.zeros(2 * epochs, np.float64)
+        _check(_lib.ants_mlp_train(self._h, lrfset.handle, C.byref(c),
+                                   losses.ctypes.data_as(C.POINTER(C.c_double)),
+                                   _stream_handle(stream)))
+        return losses.reshape(epochs, 2)
+
+    def close(self):
+        if self._h:
+            _lib.ants_mlp_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reconstruct_seeded(lrfset, mlp, refine: GridCfg, fallback: GridCfg, chi2ndf_max, signals,
+                       seeds=None, out=None, stream=None, n_fp64=False):
+    """Seeded reconstruction (network seeds, or explicit seeds [n][4] in mm
+    with a log-variance).  Returns (outputs, device tensor with the number of
+    fallback events)."""
+    import torch
+    n = signals.shape[0]
+    if out is None:
+        out = alloc_out(n, refine.iterations, signals.device, False, n_fp64)
+    nfb = torch.zeros(1, dtype=torch.int32, device=signals.device)
+    sp = None
+    if seeds is not None:
+        assert seeds.shape == (n, 4) and seeds.dtype == torch.float32 and seeds.is_contiguous()
+        sp = seeds.data_ptr()
+    _check(_lib.ants_reconstruct_seeded(lrfset.handle, mlp.handle if mlp is not None else None,
+                                        C.byref(refine), C.byref(fallback), float(chi2ndf_max), n,
+                                        signals.data_ptr(), sp, _out_struct(out), nfb.data_ptr(),
+                                        _stream_handle(stream)))
+    return out, nfb

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ants.h"
 
 namespace ants {
@@ -50,6 +52,14 @@ struct GridP {
   double z_start;
   double lfloor, vfloor;
   float margin_scale;  // multiplier on the screening error bound
+  // per-event steps from a seed's log-variance (refinement of a learned seed)
+  int seed_steps;
+  double kappa;        // initial step >= kappa * predicted sigma
+  int kmin, kmax;      // iteration count range
+  double sscale[3];    // mm per unit of the seed's standard deviation, per axis
+  double sfinal[3];    // final step per axis (= step0 * shrink^(iterations-1))
+  double fb_thr;       // > 0: events with chi2/ndf above it go to the fallback list
+  int or_status;       // status bits OR-ed into every processed event
 };
 
 struct IoP {
@@ -61,6 +71,8 @@ struct IoP {
   int64_t n;           // events (work items when list == NULL)
   const int32_t* list;     // optional: event indices to process
   const int32_t* list_n;   // optional: device count of list entries
+  int32_t* fb_list;        // fallback list (when G.fb_thr > 0)
+  int32_t* fb_count;       // its device counter
 };
 
 struct GenP {
@@ -76,8 +88,73 @@ struct GenP {
 
 hipError_t launch_gen(const DevLrf& L, const GenP& P, hipStream_t stream, int max_blocks);
 
+// ------------------------------------------------------------ learned seed
+struct GemmP {
+  int M, N, K;
+  const __bf16* A;
+  int64_t sa_m, sa_k;  // A(m, k) = A[m * sa_m + k * sa_k]
+  const __bf16* B;
+  int64_t sb_n, sb_k;  // B(n, k)
+  const float* bias;   // [N] or NULL
+  int relu;
+  const __bf16* mask;  // zero C where mask(m, n) <= 0 (ReLU derivative) or NULL
+  int64_t ldmask;
+  float* Cf;           // FP32 result or NULL
+  int64_t ldcf;
+  __bf16* Cb;          // BF16 result or NULL
+  int64_t ldcb;
+};
+struct HeadP {
+  float scale[3], inv_scale[3], offset[3];
+  float inv_batch;
+};
+struct AdamP {
+  float lr, b1, b2, eps, c1, c2;   // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+};
+hipError_t launch_gemm(const GemmP& P, hipStream_t s);
+hipError_t launch_normalize(const float* sig, int64_t ld, const int32_t* col, int na, int64_t n,
+                            int kin, __bf16* X, hipStream_t s);
+hipError_t launch_head_loss(const float* Y, const float* target, int64_t ldt, int64_t n,
+                            const HeadP& H, float* dY, __bf16* dYb, float* loss, hipStream_t s);
+hipError_t launch_head_back(const float* dY, const float* W4, const __bf16* H3, int64_t n,
+                            int hidden, __bf16* dH, hipStream_t s);
+hipError_t launch_colsum_bf16(const __bf16* D, int64_t n, int ld, int cols, float* out,
+                              hipStream_t s);
+hipError_t launch_colsum_f32(const float* D, int64_t n, int ld, int cols, float* out,
+                             hipStream_t s);
+hipError_t launch_sum_f32(const float* v, int64_t n, float scale, float* out, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, __bf16* pb, int64_t n,
+                       const AdamP& A, hipStream_t s);
+hipError_t launch_to_bf16(const float* p, __bf16* pb, int64_t n, hipStream_t s);
+hipError_t launch_seeds(const float* Y, int64_t n, const HeadP& H, float* seeds, hipStream_t s);
+
 // Launch the contracting-grid kernel; returns a hipError_t.
 hipError_t launch_grid(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t stream,
                        int max_blocks);
 
+// ------------------------------------------------------------ host side
+// error reporting (message kept for ants_last_error)
+ants_status set_error(ants_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ants_status hip_error(hipError_t e, const char* what);
+// ants_grid_cfg -> kernel parameters (validated against the LRF set)
+ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* G);
+int num_cu();
+// grow-only device buffer
+hipError_t ensure(void** p, size_t* have, size_t need);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t s);
+
 }  // namespace ants
+
+struct ants_lrfset {
+  ants::DevLrf d;
+  int device;
+  int ns;
+  std::vector<void*> allocs;
+  // workspace of the seeded reconstruction (seeds, fallback list, counter)
+  void* ws_seeds = nullptr;
+  size_t ws_seeds_bytes = 0;
+  void* ws_list = nullptr;
+  size_t ws_list_bytes = 0;
+  int32_t* ws_count = nullptr;
+};

@@ -11,26 +11,23 @@
 
 #include "ants_internal.h"
 
-using namespace ants;
+using ants::DevLrf;
+using ants::GenP;
+using ants::GridP;
+using ants::IoP;
+using ants::kMaxNodes;
+using ants::kMaxSensors;
 
 namespace {
 
 thread_local std::string g_err;
 
-ants_status fail(ants_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-ants_status fail(ants_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return st;
-}
-
-ants_status hip_fail(hipError_t e, const char* what) {
-  return fail(e == hipErrorOutOfMemory ? ANTS_E_NOMEM : ANTS_E_DEVICE, "%s: %s", what,
-              hipGetErrorString(e));
+// B-spline coefficients c[m..m+3] of one interval -> polynomial in t
+void to_poly(const double* c, double out[4]) {
+  out[0] = (c[0] + 4.0 * c[1] + c[2]) / 6.0;
+  out[1] = (c[2] - c[0]) / 2.0;
+  out[2] = (c[0] - 2.0 * c[1] + c[2]) / 2.0;
+  out[3] = (-c[0] + 3.0 * c[1] - 3.0 * c[2] + c[3]) / 6.0;
 }
 
 template <class T>
@@ -42,24 +39,145 @@ hipError_t upload(T** dst, const T* src, size_t n) {
   return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// B-spline coefficients c[m..m+3] of one interval -> polynomial in t
-void to_poly(const double* c, double out[4]) {
-  out[0] = (c[0] + 4.0 * c[1] + c[2]) / 6.0;
-  out[1] = (c[2] - c[0]) / 2.0;
-  out[2] = (c[0] - 2.0 * c[1] + c[2]) / 2.0;
-  out[3] = (-c[0] + 3.0 * c[1] - 3.0 * c[2] + c[3]) / 6.0;
-}
-
 int g_num_cu = 0;
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void copy_i32_kernel(const int32_t* a, int32_t* b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
 
 }  // namespace
 
-struct ants_lrfset {
-  DevLrf d;
-  int device;
-  int ns;
-  std::vector<void*> allocs;
-};
+namespace ants {
+
+ants_status set_error(ants_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+ants_status hip_error(hipError_t e, const char* what) {
+  return set_error(e == hipErrorOutOfMemory ? ANTS_E_NOMEM : ANTS_E_DEVICE, "%s: %s", what,
+                   hipGetErrorString(e));
+}
+
+int num_cu() {
+  if (g_num_cu == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess ||
+        g_num_cu <= 0)
+      g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
+hipError_t ensure(void** p, size_t* have, size_t need) {
+  if (*p && *have >= need) return hipSuccess;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  hipError_t e = hipMalloc(p, need);
+  if (e == hipSuccess) *have = need;
+  return e;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
+  GridP& G = *Gp;
+  memset(&G, 0, sizeof(G));
+  G.nx = cfg->nodes[0];
+  G.ny = cfg->nodes[1];
+  G.nz = cfg->nodes[2];
+  for (int a = 0; a < 3; ++a)
+    if (cfg->nodes[a] < 1 || cfg->nodes[a] % 2 == 0)
+      return set_error(ANTS_E_ARG, "nodes[%d] = %d must be odd and >= 1", a, cfg->nodes[a]);
+  if ((int64_t)G.nx * G.ny * G.nz > kMaxNodes)
+    return set_error(ANTS_E_ARG, "grid of %d x %d x %d exceeds %d nodes", G.nx, G.ny, G.nz,
+                     kMaxNodes);
+  if (L.kind != ANTS_LRF_RZ && G.nz != 1)
+    return set_error(ANTS_E_ARG, "a 2-D LRF needs nodes[2] = 1");
+  G.nn = G.nx * G.ny * G.nz;
+  G.hx = (G.nx - 1) / 2;
+  G.hy = (G.ny - 1) / 2;
+  G.hz = (G.nz - 1) / 2;
+  G.K = cfg->iterations;
+  if (G.K < 0 || G.K > 64) return set_error(ANTS_E_ARG, "iterations = %d outside 0..64", G.K);
+  if (!(cfg->shrink > 0.0 && cfg->shrink <= 1.0))
+    return set_error(ANTS_E_ARG, "shrink = %g outside (0, 1]", cfg->shrink);
+  for (int a = 0; a < 3; ++a)
+    if (cfg->nodes[a] > 1 && !(cfg->step0[a] > 0.0 && isfinite(cfg->step0[a])))
+      return set_error(ANTS_E_ARG, "step0[%d] = %g must be positive", a, cfg->step0[a]);
+  if (!(cfg->l_floor > 0.0) || !(cfg->v_floor > 0.0))
+    return set_error(ANTS_E_ARG, "l_floor and v_floor must be positive");
+  if (cfg->stat != ANTS_STAT_ML && cfg->stat != ANTS_STAT_CHI2)
+    return set_error(ANTS_E_ARG, "unknown statistic %d", cfg->stat);
+  if (cfg->start < ANTS_START_COG || cfg->start > ANTS_START_SEED)
+    return set_error(ANTS_E_ARG, "unknown start option %d", cfg->start);
+  if (!(cfg->screen_scale == 0.0 || cfg->screen_scale >= 1.0))
+    return set_error(ANTS_E_ARG, "screen_scale = %g must be 0 or >= 1", cfg->screen_scale);
+  if (!isfinite(cfg->z_start)) return set_error(ANTS_E_ARG, "z_start not finite");
+  G.dim = G.nz > 1 ? 3 : 2;
+  G.stat = cfg->stat;
+  G.start = cfg->start;
+  G.shrink = cfg->shrink;
+  G.s0x = G.nx > 1 ? cfg->step0[0] : 0.0;
+  G.s0y = G.ny > 1 ? cfg->step0[1] : 0.0;
+  G.s0z = G.nz > 1 ? cfg->step0[2] : 0.0;
+  G.z_start = cfg->z_start;
+  G.lfloor = cfg->l_floor;
+  G.vfloor = cfg->v_floor;
+  double sc = cfg->screen_scale == 0.0 ? 1.0 : cfg->screen_scale;
+  G.margin_scale = sc > 3e38 ? 3e38f : (float)sc;
+  G.seed_steps = 0;
+  if (cfg->start == ANTS_START_SEED && cfg->seed_steps) {
+    if (!(cfg->seed_kmin >= 1 && cfg->seed_kmin <= cfg->seed_kmax && cfg->seed_kmax <= G.K))
+      return set_error(ANTS_E_ARG, "need 1 <= seed_kmin (%d) <= seed_kmax (%d) <= iterations (%d)",
+                       cfg->seed_kmin, cfg->seed_kmax, G.K);
+    if (!(cfg->seed_kappa > 0.0 && isfinite(cfg->seed_kappa)))
+      return set_error(ANTS_E_ARG, "seed_kappa = %g must be positive", cfg->seed_kappa);
+    for (int a = 0; a < 3; ++a)
+      if (!(cfg->seed_scale[a] >= 0.0 && isfinite(cfg->seed_scale[a])))
+        return set_error(ANTS_E_ARG, "seed_scale[%d] = %g invalid", a, cfg->seed_scale[a]);
+    G.seed_steps = 1;
+    G.kappa = cfg->seed_kappa;
+    G.kmin = cfg->seed_kmin;
+    G.kmax = cfg->seed_kmax;
+    const double s0[3] = {G.s0x, G.s0y, G.s0z};
+    for (int a = 0; a < 3; ++a) {
+      G.sscale[a] = cfg->seed_scale[a];
+      double f = s0[a];
+      for (int k = 1; k < G.K; ++k) f *= cfg->shrink;
+      G.sfinal[a] = f;
+    }
+  }
+  return ANTS_OK;
+}
+
+}  // namespace ants
+
+using ants::set_error;
+#define fail set_error
+#define hip_fail ants::hip_error
 
 extern "C" {
 
@@ -69,6 +187,9 @@ const char* ants_version(void) { return "ants-mi355x 0.1 (gfx950)"; }
 ants_status ants_lrfset_destroy(ants_lrfset* set) {
   if (!set) return ANTS_OK;
   for (void* p : set->allocs) (void)hipFree(p);
+  if (set->ws_seeds) (void)hipFree(set->ws_seeds);
+  if (set->ws_list) (void)hipFree(set->ws_list);
+  if (set->ws_count) (void)hipFree(set->ws_count);
   delete set;
   return ANTS_OK;
 }
@@ -217,52 +338,10 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
     return fail(ANTS_E_ARG, "n_events = %lld exceeds 2^31-1", (long long)n_events);
   const DevLrf& L = set->d;
   GridP G;
-  memset(&G, 0, sizeof(G));
-  G.nx = cfg->nodes[0];
-  G.ny = cfg->nodes[1];
-  G.nz = cfg->nodes[2];
-  for (int a = 0; a < 3; ++a)
-    if (cfg->nodes[a] < 1 || cfg->nodes[a] % 2 == 0)
-      return fail(ANTS_E_ARG, "nodes[%d] = %d must be odd and >= 1", a, cfg->nodes[a]);
-  if ((int64_t)G.nx * G.ny * G.nz > kMaxNodes)
-    return fail(ANTS_E_ARG, "grid of %d x %d x %d exceeds %d nodes", G.nx, G.ny, G.nz,
-                kMaxNodes);
-  if (L.kind != ANTS_LRF_RZ && G.nz != 1)
-    return fail(ANTS_E_ARG, "a 2-D LRF needs nodes[2] = 1");
-  G.nn = G.nx * G.ny * G.nz;
-  G.hx = (G.nx - 1) / 2;
-  G.hy = (G.ny - 1) / 2;
-  G.hz = (G.nz - 1) / 2;
-  G.K = cfg->iterations;
-  if (G.K < 0 || G.K > 64) return fail(ANTS_E_ARG, "iterations = %d outside 0..64", G.K);
-  if (!(cfg->shrink > 0.0 && cfg->shrink <= 1.0))
-    return fail(ANTS_E_ARG, "shrink = %g outside (0, 1]", cfg->shrink);
-  for (int a = 0; a < 3; ++a)
-    if (cfg->nodes[a] > 1 && !(cfg->step0[a] > 0.0 && isfinite(cfg->step0[a])))
-      return fail(ANTS_E_ARG, "step0[%d] = %g must be positive", a, cfg->step0[a]);
-  if (!(cfg->l_floor > 0.0) || !(cfg->v_floor > 0.0))
-    return fail(ANTS_E_ARG, "l_floor and v_floor must be positive");
-  if (cfg->stat != ANTS_STAT_ML && cfg->stat != ANTS_STAT_CHI2)
-    return fail(ANTS_E_ARG, "unknown statistic %d", cfg->stat);
-  if (cfg->start < ANTS_START_COG || cfg->start > ANTS_START_SEED)
-    return fail(ANTS_E_ARG, "unknown start option %d", cfg->start);
+  ants_status st = ants::grid_params(L, cfg, &G);
+  if (st != ANTS_OK) return st;
   if (cfg->start == ANTS_START_SEED && !d_seeds)
     return fail(ANTS_E_ARG, "start = SEED needs d_seeds");
-  if (!(cfg->screen_scale == 0.0 || cfg->screen_scale >= 1.0))
-    return fail(ANTS_E_ARG, "screen_scale = %g must be 0 or >= 1", cfg->screen_scale);
-  if (!isfinite(cfg->z_start)) return fail(ANTS_E_ARG, "z_start not finite");
-  G.dim = G.nz > 1 ? 3 : 2;
-  G.stat = cfg->stat;
-  G.start = cfg->start;
-  G.shrink = cfg->shrink;
-  G.s0x = G.nx > 1 ? cfg->step0[0] : 0.0;
-  G.s0y = G.ny > 1 ? cfg->step0[1] : 0.0;
-  G.s0z = G.nz > 1 ? cfg->step0[2] : 0.0;
-  G.z_start = cfg->z_start;
-  G.lfloor = cfg->l_floor;
-  G.vfloor = cfg->v_floor;
-  double sc = cfg->screen_scale == 0.0 ? 1.0 : cfg->screen_scale;
-  G.margin_scale = sc > 3e38 ? 3e38f : (float)sc;
   if (n_events == 0) return ANTS_OK;
   if (!d_signals) return fail(ANTS_E_ARG, "d_signals is NULL");
   if (!out.x || !out.y || !out.z || !out.E || !out.lnl || !out.chi2 || !out.ndf || !out.status)
@@ -290,12 +369,7 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
   if (dev != set->device)
     return fail(ANTS_E_ARG, "LRF set lives on device %d, current device is %d", set->device,
                 dev);
-  if (g_num_cu == 0) {
-    if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
-        hipSuccess || g_num_cu <= 0)
-      g_num_cu = 256;
-  }
-  hipError_t e = launch_grid(L, G, io, (hipStream_t)hip_stream, g_num_cu * 8);
+  hipError_t e = ants::launch_grid(L, G, io, (hipStream_t)hip_stream, ants::num_cu() * 8);
   if (e != hipSuccess) return hip_fail(e, "ants_reconstruct launch");
   return ANTS_OK;
 }
@@ -335,7 +409,7 @@ ants_status ants_generate(ants_lrfset* set, const ants_gen_cfg* cfg, int64_t n_e
   if (dev != set->device)
     return fail(ANTS_E_ARG, "LRF set lives on device %d, current device is %d", set->device,
                 dev);
-  hipError_t e = launch_gen(set->d, P, (hipStream_t)hip_stream, 256 * 16);
+  hipError_t e = ants::launch_gen(set->d, P, (hipStream_t)hip_stream, ants::num_cu() * 16);
   if (e != hipSuccess) return hip_fail(e, "ants_generate launch");
   return ANTS_OK;
 }

@@ -331,8 +331,38 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
     const float N32 = (float)N;
 
     double sx = G.s0x, sy = G.s0y, sz = G.s0z;
+    int Kev = G.K;
+    if (G.seed_steps && io.seeds) {
+      // steps from the seed's predicted spread: the smallest iteration count
+      // in [kmin, kmax] whose first step covers kappa * sigma on every axis,
+      // ending on the configured final step
+      const double lv = io.seeds[e * 4 + 3];
+      const double sg = exp(0.5 * lv) * G.kappa;
+      double s3[3] = {G.sfinal[0], G.sfinal[1], G.sfinal[2]};
+      const int nn3[3] = {G.nx, G.ny, G.nz};
+      int kk = 0;
+      for (; kk < G.kmin - 1; ++kk)
+        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+      if (!(sg < __builtin_huge_val())) {
+        for (; kk < G.kmax - 1; ++kk)
+          for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+      } else {
+        for (;;) {
+          bool short_ = false;
+          for (int a = 0; a < 3; ++a)
+            if (nn3[a] > 1 && s3[a] < sg * G.sscale[a]) short_ = true;
+          if (!short_ || kk >= G.kmax - 1) break;
+          for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+          ++kk;
+        }
+      }
+      Kev = uni(kk + 1);
+      sx = uni(G.nx > 1 ? s3[0] : 0.0);
+      sy = uni(G.ny > 1 ? s3[1] : 0.0);
+      sz = uni(G.nz > 1 ? s3[2] : 0.0);
+    }
     int nfp = 0;
-    for (int k = 0; k < G.K; ++k) {
+    for (int k = 0; k < Kev; ++k) {
       const int lk = opaque(lane);
       // ---- r-z: collapse the table along z for this iteration's planes
       if constexpr (KIND == ANTS_LRF_RZ) {
@@ -631,7 +661,7 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
         win = bestd < __builtin_huge_val() ? jd : -1;
         win = uni(win);
       }
-      if (io.path && lane == 0) io.path[e * G.K + k] = win;
+      if (io.path && lane == 0 && k < G.K) io.path[e * G.K + k] = win;
       if (win < 0) {
         status |= ANTS_EV_NO_VALID_NODE;
       } else {
@@ -679,7 +709,13 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
       ll = wsum_d(ll);
       q2 = wsum_d(q2);
     }
+    if (io.path && Kev < G.K && lane >= Kev && lane < G.K) io.path[e * G.K + lane] = -1;
+    status |= G.or_status;
     if (lane == 0) {
+      if (G.fb_thr > 0.0 && !(okS && ndf > 0 && q2 / ndf <= G.fb_thr)) {
+        int slot = atomicAdd(io.fb_count, 1);
+        io.fb_list[slot] = (int32_t)e;
+      }
       float nan = __builtin_nanf("");
       io.x[e] = (float)cx;
       io.y[e] = (float)cy;

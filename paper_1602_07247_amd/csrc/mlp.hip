@@ -1,0 +1,296 @@
+// Learned seed for the contracting grid: a fully connected ReLU network
+// (in the spirit of the artificial-neural-network reconstruction of
+// Sec. 5.1.3, trained by back-propagation on events with known positions)
+// mapping normalised sensor signals to a position seed and a log-variance.
+//
+// Storage: FP32 master weights, BF16 copies for the products; activations
+// stored in BF16; every product accumulates in FP32 on the matrix cores
+// (v_mfma_f32_16x16x32_bf16).
+//
+// GEMM convention: C[m][n] = sum_k A(m,k) * B(n,k), operands addressed with
+// arbitrary element strides so the same kernel serves the forward product
+// (A = activations, B = weights), the input gradient (B = weights seen
+// transposed) and the weight gradient (A and B = batch-transposed views).
+#include <math.h>
+
+#include "ants_internal.h"
+
+namespace ants {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;   // LDS row pitch (bf16 elements)
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }   // round to nearest even
+
+__global__ void __launch_bounds__(256) gemm_kernel(GemmP P) {
+  __shared__ __align__(16) __bf16 As[BM * LDK];
+  __shared__ __align__(16) __bf16 Bs[BN * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  // each thread stages 8 consecutive k of one row of A and of B
+  const int lr = tid >> 2, lk = (tid & 3) * 8;
+  const bool a_vec = P.sa_k == 1 && (P.sa_m % 8) == 0 && (P.K % 8) == 0;
+  const bool b_vec = P.sb_k == 1 && (P.sb_n % 8) == 0 && (P.K % 8) == 0;
+  for (int k0 = 0; k0 < P.K; k0 += BK) {
+    {
+      const int m = m0 + lr, k = k0 + lk;
+      bf16x8 v;
+      if (a_vec && m < P.M && k + 7 < P.K) {
+        v = *(const bf16x8*)(P.A + (int64_t)m * P.sa_m + k);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          v[e] = (m < P.M && k + e < P.K) ? P.A[(int64_t)m * P.sa_m + (int64_t)(k + e) * P.sa_k]
+                                          : (__bf16)0.f;
+      }
+      *(bf16x8*)(As + lr * LDK + lk) = v;
+    }
+    {
+      const int n = n0 + lr, k = k0 + lk;
+      bf16x8 v;
+      if (b_vec && n < P.N && k + 7 < P.K) {
+        v = *(const bf16x8*)(P.B + (int64_t)n * P.sb_n + k);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          v[e] = (n < P.N && k + e < P.K) ? P.B[(int64_t)n * P.sb_n + (int64_t)(k + e) * P.sb_k]
+                                          : (__bf16)0.f;
+      }
+      *(bf16x8*)(Bs + lr * LDK + lk) = v;
+    }
+    __syncthreads();
+    // operand fragments: lane l holds row (l % 16) and k = 8*(l / 16) .. +7,
+    // the same k assignment for A and B
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)(As + (wr + i * 16 + fr) * LDK + fk);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)(Bs + (wc + j * 16 + fr) * LDK + fk);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // result layout: lane l holds C[4*(l/16) + r][l % 16], r = 0..3
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + r;
+        const int n = n0 + wc + j * 16 + (lane & 15);
+        if (m < P.M && n < P.N) {
+          float v = acc[i][j][r];
+          if (P.bias) v += P.bias[n];
+          if (P.relu) v = fmaxf(v, 0.f);
+          if (P.mask && !((float)P.mask[(int64_t)m * P.ldmask + n] > 0.f)) v = 0.f;
+          if (P.Cf) P.Cf[(int64_t)m * P.ldcf + n] = v;
+          if (P.Cb) P.Cb[(int64_t)m * P.ldcb + n] = to_bf16(v);
+        }
+      }
+}
+
+// x_hat = bf16(n_a * (n_active / N)) for the active sensors, zero padding
+__global__ void normalize_kernel(const float* sig, int64_t ld, const int32_t* col, int na,
+                                 int64_t n, int kin, __bf16* X) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float* row = sig + e * ld;
+  float N = 0.f;
+  bool ok = true;
+  for (int a = 0; a < na; ++a) {
+    float v = row[col[a]];
+    if (!(v >= 0.f) || !(v < __builtin_huge_valf())) ok = false;
+    N += v;
+  }
+  ok = ok && N > 0.f;
+  const float s = ok ? (float)na / N : 0.f;
+  __bf16* out = X + e * kin;
+  for (int a = 0; a < kin; ++a) out[a] = (ok && a < na) ? to_bf16(row[col[a]] * s) : (__bf16)0.f;
+}
+
+// Gaussian negative log-likelihood with one log-variance s per event:
+//   loss = 0.5 exp(-s) |p - t|^2 + 1.5 s, targets t = (pos - offset) / scale.
+// Writes dY = dloss/dY / batch (FP32 and BF16) and the per-event loss.
+__global__ void head_loss_kernel(const float* Y, const float* target, int64_t ldt, int64_t n,
+                                 HeadP H, float* dY, __bf16* dYb, float* loss) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float* y = Y + e * 4;
+  float r2 = 0.f, r[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float t = (target[e * ldt + c] - H.offset[c]) * H.inv_scale[c];
+    r[c] = y[c] - t;
+    r2 = fmaf(r[c], r[c], r2);
+  }
+  const float s = y[3], es = expf(-s), w = H.inv_batch;
+  float g[4] = {es * r[0] * w, es * r[1] * w, es * r[2] * w, (1.5f - 0.5f * es * r2) * w};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    dY[e * 4 + c] = g[c];
+    dYb[e * 4 + c] = to_bf16(g[c]);
+  }
+  loss[e] = 0.5f * es * r2 + 1.5f * s;
+}
+
+// dH3 = (dY W4) * [H3 > 0], FP32 sums of four products, stored in BF16
+__global__ void head_back_kernel(const float* dY, const float* W4, const __bf16* H3, int64_t n,
+                                 int hidden, __bf16* dH) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * hidden) return;
+  const int64_t e = i / hidden;
+  const int j = (int)(i - e * hidden);
+  float v = 0.f;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) v = fmaf(dY[e * 4 + o], (float)(__bf16)W4[o * hidden + j], v);
+  dH[i] = ((float)H3[i] > 0.f) ? to_bf16(v) : (__bf16)0.f;
+}
+
+// column sums (bias gradients), deterministic: one block per column
+__global__ void __launch_bounds__(256) colsum_bf16_kernel(const __bf16* D, int64_t n, int ld,
+                                                          float* out) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int64_t e = threadIdx.x; e < n; e += 256) s += (float)D[e * ld + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+__global__ void __launch_bounds__(256) colsum_f32_kernel(const float* D, int64_t n, int ld,
+                                                         float* out) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int64_t e = threadIdx.x; e < n; e += 256) s += D[e * ld + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+__global__ void sum_f32_kernel(const float* v, int64_t n, float scale, float* out) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int64_t e = threadIdx.x; e < n; e += 256) s += v[e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+// Adam (Kingma and Ba) on the FP32 master copy; refreshes the BF16 copy
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, __bf16* pb, int64_t n,
+                            AdamP A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = A.b1 * m[i] + (1.f - A.b1) * gi;
+  const float vi = A.b2 * v[i] + (1.f - A.b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float upd = A.lr * (mi * A.c1) / (sqrtf(vi * A.c2) + A.eps);
+  const float pn = p[i] - upd;
+  p[i] = pn;
+  pb[i] = to_bf16(pn);
+}
+
+__global__ void to_bf16_kernel(const float* p, __bf16* pb, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pb[i] = to_bf16(p[i]);
+}
+
+// network output (normalised) -> seed in mm: pos = offset + scale * y, s kept
+__global__ void seeds_kernel(const float* Y, int64_t n, HeadP H, float* seeds) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) seeds[e * 4 + c] = H.offset[c] + H.scale[c] * Y[e * 4 + c];
+  seeds[e * 4 + 3] = Y[e * 4 + 3];
+}
+
+inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmP& P, hipStream_t s) {
+  if (P.M <= 0 || P.N <= 0) return hipSuccess;
+  dim3 g((unsigned)((P.N + BN - 1) / BN), (unsigned)((P.M + BM - 1) / BM));
+  hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_normalize(const float* sig, int64_t ld, const int32_t* col, int na, int64_t n,
+                            int kin, __bf16* X, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(normalize_kernel, dim3(nb(n)), dim3(256), 0, s, sig, ld, col, na, n, kin, X);
+  return hipGetLastError();
+}
+hipError_t launch_head_loss(const float* Y, const float* target, int64_t ldt, int64_t n,
+                            const HeadP& H, float* dY, __bf16* dYb, float* loss, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(head_loss_kernel, dim3(nb(n)), dim3(256), 0, s, Y, target, ldt, n, H, dY,
+                     dYb, loss);
+  return hipGetLastError();
+}
+hipError_t launch_head_back(const float* dY, const float* W4, const __bf16* H3, int64_t n,
+                            int hidden, __bf16* dH, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(head_back_kernel, dim3(nb(n * hidden)), dim3(256), 0, s, dY, W4, H3, n,
+                     hidden, dH);
+  return hipGetLastError();
+}
+hipError_t launch_colsum_bf16(const __bf16* D, int64_t n, int ld, int cols, float* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(colsum_bf16_kernel, dim3(cols), dim3(256), 0, s, D, n, ld, out);
+  return hipGetLastError();
+}
+hipError_t launch_colsum_f32(const float* D, int64_t n, int ld, int cols, float* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(colsum_f32_kernel, dim3(cols), dim3(256), 0, s, D, n, ld, out);
+  return hipGetLastError();
+}
+hipError_t launch_sum_f32(const float* v, int64_t n, float scale, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_f32_kernel, dim3(1), dim3(256), 0, s, v, n, scale, out);
+  return hipGetLastError();
+}
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, __bf16* pb, int64_t n,
+                       const AdamP& A, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3(nb(n)), dim3(256), 0, s, p, g, m, v, pb, n, A);
+  return hipGetLastError();
+}
+hipError_t launch_to_bf16(const float* p, __bf16* pb, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(nb(n)), dim3(256), 0, s, p, pb, n);
+  return hipGetLastError();
+}
+hipError_t launch_seeds(const float* Y, int64_t n, const HeadP& H, float* seeds, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(seeds_kernel, dim3(nb(n)), dim3(256), 0, s, Y, n, H, seeds);
+  return hipGetLastError();
+}
+
+}  // namespace ants

@@ -1,0 +1,138 @@
+"""Learned seed on the GPU: forward and gradient of the BF16-MFMA network
+against the FP64 reference (with BF16 storage emulated), training on events
+drawn from the LRF model, and the seeded reconstruction against the oracle."""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import mlp as R
+
+from parity import compare, summary, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ants():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_07247_amd import ants as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def det(ants):
+    wl = W.workload(2)
+    sig, truth = oracle.make_events(wl.lrf, wl.events, 4096, W.streams(2 + 5000))
+    return wl, ants.LrfSet(wl.lrf), sig, truth
+
+
+def _net(ants, seed=3):
+    lay = R.Layout(37, 256, 3)
+    net = ants.Mlp(37, 256, 3, seed=1, pos_scale=W.SEED_POS_SCALE, pos_offset=W.SEED_POS_OFFSET)
+    assert net.n_params == lay.n_params
+    p = lay.random(seed).astype(np.float32)
+    net.set_params(p)
+    return lay, net, p.astype(np.float64)
+
+
+def test_params_roundtrip_and_init(ants):
+    net = ants.Mlp(37, 256, 3, seed=7)
+    p = net.get_params()
+    lay = R.Layout(37, 256, 3)
+    Ws, bs = lay.unpack(p)
+    assert np.all(Ws[0][:, 37:] == 0) and all(np.all(b == 0) for b in bs)
+    assert abs(Ws[1].std() - math.sqrt(6 / 256) / math.sqrt(3)) < 0.01
+    q = lay.random(2).astype(np.float32)
+    net.set_params(q)
+    np.testing.assert_array_equal(net.get_params(), q)
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "net.bin")
+        net.save(f)
+        net2 = ants.Mlp.load(f)
+        np.testing.assert_array_equal(net2.get_params(), q)
+
+
+def test_forward_matches_reference(ants, det):
+    wl, L, sig, truth = det
+    lay, net, p = _net(ants)
+    print("[gpu] mlp forward 4096", flush=True)
+    pred = net.forward(L, torch.from_numpy(sig).cuda())
+    torch.cuda.synchronize()
+    got = pred.cpu().numpy()
+    ref, _ = R.forward(lay, p, sig, emulate=True)
+    err = np.abs(got - ref)
+    scale = 1 + np.abs(ref)
+    print("forward max rel", (err / scale).max(), "median", np.median(err / scale))
+    assert np.median(err / scale) < 1e-3
+    assert (err / scale).max() < 5e-2
+
+
+def test_gradient_matches_reference(ants, det):
+    wl, L, sig, truth = det
+    lay, net, p = _net(ants, seed=4)
+    n = 2048
+    print("[gpu] mlp grad 2048", flush=True)
+    g, loss = net.grad(L, torch.from_numpy(sig[:n]).cuda(),
+                       torch.from_numpy(truth["pos"][:n].astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    ref_loss, ref_g = R.loss_and_grad(lay, p, sig[:n], truth["pos"][:n], W.SEED_POS_SCALE,
+                                      W.SEED_POS_OFFSET, emulate=True)
+    assert abs(loss.item() - ref_loss) < 1e-3 * (1 + abs(ref_loss))
+    for l, (off, do, di) in enumerate(lay.shapes):
+        for a, b in ((off, off + do * di), (off + do * di, off + do * di + do)):
+            x, y = g[a:b], ref_g[a:b]
+            cos = x @ y / (np.linalg.norm(x) * np.linalg.norm(y) + 1e-30)
+            rel = np.linalg.norm(x - y) / (np.linalg.norm(y) + 1e-30)
+            print(f"layer {l} block [{a}:{b}] cos {cos:.6f} rel {rel:.2e}")
+            assert cos > 0.999 and rel < 0.03
+
+
+def test_training_reduces_loss_and_seeds_the_grid(ants, det):
+    wl, L, sig, truth = det
+    net = ants.Mlp(37, 256, 3, seed=5, pos_scale=W.SEED_POS_SCALE, pos_offset=W.SEED_POS_OFFSET)
+    print("[gpu] mlp train 400k events, 3 epochs", flush=True)
+    losses = net.train(L, wl.events, 400_000, 20_000, batch=2048, epochs=3, lr=2e-3)
+    print("losses", losses.tolist())
+    assert losses[-1, 1] < losses[0, 1] and np.isfinite(losses).all()
+    pred = net.forward(L, torch.from_numpy(sig).cuda()).cpu().numpy()
+    pos = np.array(W.SEED_POS_OFFSET) + np.array(W.SEED_POS_SCALE) * pred[:, :3]
+    d = pos - truth["pos"]
+    rms_xy = math.sqrt(0.5 * np.mean(d[:, 0] ** 2 + d[:, 1] ** 2))
+    print("seed rms xy", rms_xy)
+    assert rms_xy < 10.0
+
+
+def test_seeded_refinement_matches_oracle(ants, det):
+    # explicit seeds (truth displaced by 2 mm, predicted sigma 2 mm): the
+    # refinement grid and the chi2/ndf fallback against the oracle
+    wl, L, sig, truth = det
+    n = 2000
+    rng = np.random.default_rng(12)
+    seeds = np.zeros((n, 4), np.float32)
+    seeds[:, :3] = truth["pos"][:n] + rng.normal(0, 2.0, (n, 3))
+    seeds[:, 3] = 2 * np.log(2.0 / 90.0)
+    seeds[:50, :2] += 40.0                         # some far-off seeds to force fallbacks
+    seeds = seeds.astype(np.float32)
+    refine = W.seeded_refine_grid(kappa=2.0)
+    print("[gpu] seeded refinement 2000", flush=True)
+    out, nfb = ants.reconstruct_seeded(L, None, ants.grid_cfg(refine), ants.grid_cfg(wl.grid),
+                                       2.0, torch.from_numpy(sig[:n]).cuda(),
+                                       seeds=torch.from_numpy(seeds).cuda())
+    torch.cuda.synchronize()
+    got = to_np(out)
+    ref = oracle.reconstruct_seeded(wl.lrf, refine, wl.grid, 2.0, sig[:n],
+                                    seeds.astype(np.float64))
+    res = compare(ref, got, sig[:n], three_d=True)
+    fb_ref = int(((ref["status"] & 16) != 0).sum())
+    print(summary(res), "fallbacks", nfb.item(), fb_ref)
+    assert res["frac"] >= 0.998, summary(res)
+    assert abs(nfb.item() - fb_ref) <= 2
+    assert fb_ref >= 40

@@ -121,6 +121,11 @@ class GridCfg:
     start: int = 0             # 0 CoG, 1 strongest sensor, 2 seed
     l_floor: float = 1e-9
     v_floor: float = 1.0
+    seed_steps: int = 0
+    seed_kappa: float = 1.0
+    seed_kmin: int = 1
+    seed_kmax: int = 1
+    seed_scale: tuple = (0.0, 0.0, 0.0)
 
     @property
     def final_step(self):
@@ -264,3 +269,17 @@ def chunk_stream(total: int, seed_offset: int = 0, median=1e4, sigma_ln=1.0,
         geoms.append(int(rng.integers(0, n_geom)))
         acc += s
     return np.asarray(sizes, np.int64), np.asarray(geoms, np.int32)
+
+
+def seeded_refine_grid(kappa: float = 2.0, kmin: int = 2, kmax: int = 8) -> GridCfg:
+    """Refinement grid of the learned-seed path: 3 x 3 x 3 nodes started at
+    the seed, ending on the plain grid's final step (workload 2: 10, 10,
+    50/6 mm halved over 8 iterations), with the iteration count chosen per
+    event from the seed's predicted spread (kappa * sigma)."""
+    return GridCfg((3, 3, 3), 8, 0.5, (10.0, 10.0, 50.0 / 6.0), 25.0, stat=0, start=2,
+                   seed_steps=1, seed_kappa=kappa, seed_kmin=kmin, seed_kmax=kmax,
+                   seed_scale=(90.0, 90.0, 25.0))
+
+
+SEED_POS_SCALE = (90.0, 90.0, 25.0)
+SEED_POS_OFFSET = (0.0, 0.0, 25.0)

@@ -168,6 +168,48 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
                              void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* One persistent launch over event chunks from several detectors (one  */
+/* LRF set and grid configuration per detector; every set must have the */
+/* same LRF kind and the same statistic).  Chunk c holds n_events rows   */
+/* of its set's n_sensors signals and writes output rows out_offset ..   */
+/* out_offset + n_events - 1.  Results equal ants_reconstruct of each   */
+/* chunk with its set and configuration, for every plan.                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t set;              /* index into sets / cfgs                        */
+  int64_t n_events;
+  const float* d_signals;   /* [n_events][n_sensors of the set]              */
+  int64_t out_offset;
+} ants_chunk;
+
+/* Launch plan: events per work item, resident blocks per compute unit,
+ * and whether the LRF tables are staged in LDS (1) or read through the
+ * cache (0).  NULL plan = {32, 8, 1}. */
+typedef struct {
+  int32_t events_per_item;   /* 1 .. 4096 */
+  int32_t blocks_per_cu;     /* 1 .. 32   */
+  int32_t table_in_lds;      /* 0 or 1    */
+} ants_plan;
+
+/* ants_out.path is ignored (n_fp64 likewise).  Up to 64 sets and 2^24 chunks.
+ * The library keeps descriptor workspace in sets[0]; calls sharing
+ * sets[0] must not overlap. */
+ants_status ants_reconstruct_multi(ants_lrfset* const* sets, const ants_grid_cfg* cfgs,
+                                   int32_t n_sets, const ants_chunk* chunks, int32_t n_chunks,
+                                   const ants_plan* plan, ants_out out, void* hip_stream);
+
+/* Autotuner: times every candidate plan (events per item 8/32/128, blocks
+ * per CU 4/8/16, tables in LDS or not) on the first `sample_events` events
+ * of the chunk stream, writing into `scratch` (rows 0 .. sample_events-1),
+ * and returns the fastest in *best; host_ms [18] receives each candidate's
+ * time in the order above (table outermost) or NULL.  Synchronises the
+ * stream.  The choice depends on timing; the reconstructed values do not. */
+ants_status ants_autotune_multi(ants_lrfset* const* sets, const ants_grid_cfg* cfgs,
+                                int32_t n_sets, const ants_chunk* chunks, int32_t n_chunks,
+                                int64_t sample_events, ants_out scratch, ants_plan* best,
+                                double* host_ms, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* Event generator: flood-field events drawn from the LRF model itself  */
 /* (Sec. 4.1.1 "flood field"; Sec. 5.1.1 relative gains).  For event    */
 /* index i = first_event + e: position uniform over a disc of radius    */

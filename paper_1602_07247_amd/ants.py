@@ -73,6 +73,16 @@ class TrainCfg(C.Structure):
                 ("seed", C.c_uint64), ("events", GenCfg)]
 
 
+class Chunk(C.Structure):
+    _fields_ = [("set", C.c_int32), ("n_events", C.c_int64), ("d_signals", C.c_void_p),
+                ("out_offset", C.c_int64)]
+
+
+class Plan(C.Structure):
+    _fields_ = [("events_per_item", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("table_in_lds", C.c_int32)]
+
+
 class Out(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in
                 ("x", "y", "z", "E", "lnl", "chi2", "ndf", "status", "path", "n_fp64")]
@@ -105,11 +115,18 @@ _lib.ants_mlp_load.argtypes = [C.c_char_p, C.POINTER(_vp)]
 _lib.ants_reconstruct_seeded.argtypes = [_vp, _vp, C.POINTER(GridCfg), C.POINTER(GridCfg),
                                          C.c_double, C.c_int64, _vp, _vp, Out, _vp, _vp]
 
+_lib.ants_reconstruct_multi.argtypes = [C.POINTER(_vp), C.POINTER(GridCfg), C.c_int32,
+                                        C.POINTER(Chunk), C.c_int32, C.POINTER(Plan), Out, _vp]
+_lib.ants_autotune_multi.argtypes = [C.POINTER(_vp), C.POINTER(GridCfg), C.c_int32,
+                                     C.POINTER(Chunk), C.c_int32, C.c_int64, Out, C.POINTER(Plan),
+                                     C.POINTER(C.c_double), _vp]
+
 EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfset_destroy",
             "ants_lrfset_info", "ants_reconstruct", "ants_generate", "ants_mlp_create",
             "ants_mlp_destroy", "ants_mlp_num_params", "ants_mlp_get_params",
             "ants_mlp_set_params", "ants_mlp_forward", "ants_mlp_grad", "ants_mlp_train_step",
-            "ants_mlp_train", "ants_mlp_save", "ants_mlp_load", "ants_reconstruct_seeded")
+            "ants_mlp_train", "ants_mlp_save", "ants_mlp_load", "ants_reconstruct_seeded",
+            "ants_reconstruct_multi", "ants_autotune_multi")
 
 
 def _check(code):
@@ -382,3 +399,41 @@ def reconstruct_seeded(lrfset, mlp, refine: GridCfg, fallback: GridCfg, chi2ndf_
                                         signals.data_ptr(), sp, _out_struct(out), nfb.data_ptr(),
                                         _stream_handle(stream)))
     return out, nfb
+
+
+def _multi_args(sets, cfgs, chunks):
+    hs = (_vp * len(sets))(*[x.handle.value for x in sets])
+    cs = (GridCfg * len(cfgs))(*cfgs)
+    ch = (Chunk * len(chunks))()
+    for i, (si, sig, off) in enumerate(chunks):
+        ch[i].set = si
+        ch[i].n_events = sig.shape[0]
+        ch[i].d_signals = sig.data_ptr() if sig.shape[0] else None
+        ch[i].out_offset = off
+    return hs, cs, ch
+
+
+def reconstruct_multi(sets, cfgs, chunks, n_out, plan=None, out=None, stream=None):
+    """One persistent launch over chunks [(set index, signals tensor,
+    output offset)] of several detectors."""
+    if out is None:
+        out = alloc_out(n_out, 0, chunks[0][1].device if chunks else "cuda")
+    hs, cs, ch = _multi_args(sets, cfgs, chunks)
+    _check(_lib.ants_reconstruct_multi(hs, cs, len(sets), ch, len(chunks),
+                                       C.byref(plan) if plan is not None else None,
+                                       _out_struct(out), _stream_handle(stream)))
+    return out
+
+
+def autotune_multi(sets, cfgs, chunks, sample_events, stream=None):
+    """Time the candidate plans on the first sample_events events; returns
+    (best Plan, per-candidate milliseconds)."""
+    hs, cs, ch = _multi_args(sets, cfgs, chunks)
+    scratch = alloc_out(sample_events, 0, chunks[0][1].device)
+    best = Plan()
+    ms = np.zeros(18, np.float64)
+    _check(_lib.ants_autotune_multi(hs, cs, len(sets), ch, len(chunks), sample_events,
+                                    _out_struct(scratch), C.byref(best),
+                                    ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                    _stream_handle(stream)))
+    return best, ms

@@ -88,6 +88,37 @@ struct GenP {
 
 hipError_t launch_gen(const DevLrf& L, const GenP& P, hipStream_t stream, int max_blocks);
 
+// ------------------------------------------------- persistent multi-detector
+struct SetDesc {
+  DevLrf L;
+  GridP G;
+  int tab_off;         // float4 offset of the set's table in the block's LDS
+  int pad_;
+};
+struct ChunkDesc {
+  const float* sig;    // [n][ns of its set]
+  int64_t n;
+  int64_t out_off;     // first output row
+  int32_t set;
+  int32_t pad_;
+};
+struct MultiP {
+  const SetDesc* sets;
+  int n_sets;
+  const ChunkDesc* chunks;
+  const int32_t* prefix;   // [n_chunks + 1] first work item of each chunk
+  int n_chunks;
+  int n_items;
+  int T;                   // events per work item
+  int* counter;            // work counter (zeroed before the launch)
+  IoP out;                 // output arrays (offset per chunk)
+  int per_wave_bytes;
+  int btab_n;
+  int tab_in_lds;
+};
+hipError_t launch_multi(const MultiP& P, int kind, int stat, int max_nn, int max_na, int blocks,
+                        hipStream_t s);
+
 // ------------------------------------------------------------ learned seed
 struct GemmP {
   int M, N, K;
@@ -157,4 +188,7 @@ struct ants_lrfset {
   void* ws_list = nullptr;
   size_t ws_list_bytes = 0;
   int32_t* ws_count = nullptr;
+  // workspace of the multi-detector launch (descriptors, counter)
+  void* ws_multi = nullptr;
+  size_t ws_multi_bytes = 0;
 };

@@ -214,6 +214,508 @@ __device__ __forceinline__ float log2_1p(float x) {
 
 // --------------------------------------------------------------- kernel
 
+// One event on one wavefront.  btab: block-shared tables (LDS); wbase: this
+// wave's LDS region (sensor records, r-z plane tables, candidate list).
+template <int KIND, int STAT, int NT, int SL>
+__device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, const IoP& io,
+                                              const int64_t e, const float4* btab,
+                                              unsigned char* wbase, const int lane) {
+  float4* recA = (float4*)wbase;
+  float4* recB = recA + L.na;
+  float4* ztab = recB + L.na;
+  int* cand = (int*)(ztab + (KIND == ANTS_LRF_RZ ? G.nz * L.nintp : 0));
+  const int na = L.na;
+  const int nlast = L.nintp - 1;
+  const float finv = L.finv0;
+  const float flf = (float)G.lfloor;
+  const float fvf = (float)G.vfloor;
+  const float* row = io.sig + e * io.ld;
+
+  // ---------------- event set-up: signals of the active sensors
+  float nq[SL];
+  int posq[SL];
+  double N = 0.0, cw = 0.0, cxs = 0.0, cys = 0.0;
+  bool bad = false;
+  float best_n = -1.0f;
+  int best_a = 1 << 30;
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    int a = lane + 64 * q;
+    nq[q] = 0.f;
+    if (a < na) {
+      float n = row[L.col[a]];
+      nq[q] = n;
+      if (!(n >= 0.f) || !(n < kInf)) {
+        bad = true;
+      } else {
+        double wgt = (double)n / L.g[a];
+        N += (double)n;
+        cw += wgt;
+        cxs += L.X[a] * wgt;
+        cys += L.Y[a] * wgt;
+        if (n > best_n) { best_n = n; best_a = a; }
+      }
+    }
+  }
+  bool any_bad = __ballot(bad) != 0ull;
+  N = uni(wsum_d(N));
+  const int ndf = na - (G.dim + 1);
+  int status = 0;
+  if (na == 0) status = ANTS_EV_NO_ACTIVE;
+  else if (any_bad) status = ANTS_EV_BAD_INPUT;
+  else if (!(N > 0.0)) status = ANTS_EV_EMPTY;
+  if (status) {
+    if (lane == 0) {
+      float nan = __builtin_nanf("");
+      io.x[e] = nan; io.y[e] = nan; io.z[e] = nan; io.E[e] = nan;
+      io.lnl[e] = nan; io.chi2[e] = nan; io.ndf[e] = ndf; io.status[e] = status;
+      if (io.nfp) io.nfp[e] = 0;
+    }
+    if (io.path && lane < G.K) io.path[e * G.K + lane] = -1;
+    return;
+  }
+  cw = wsum_d(cw);
+  cxs = wsum_d(cxs);
+  cys = wsum_d(cys);
+
+  double cx, cy, cz = G.z_start;
+  if (G.start == ANTS_START_SEED && io.seeds) {
+    cx = io.seeds[e * 4 + 0];
+    cy = io.seeds[e * 4 + 1];
+    if (G.dim == 3) cz = io.seeds[e * 4 + 2];
+  } else if (G.start == ANTS_START_MAXSENSOR) {
+    wargmax_f(best_n, best_a);
+    best_a = uni(best_a);
+    cx = L.X[best_a];
+    cy = L.Y[best_a];
+  } else {
+    cx = cxs / cw;
+    cy = cys / cw;
+  }
+  cx = uni(cx);
+  cy = uni(cy);
+  cz = uni(cz);
+
+  // sensor records in LDS: sensors with n > 0 first, then n == 0
+  int npos = 0;
+  {
+    uint64_t mpos[SL], mzero[SL];
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      int a = lane + 64 * q;
+      mpos[q] = __ballot(a < na && nq[q] > 0.f);
+      mzero[q] = __ballot(a < na && !(nq[q] > 0.f));
+      npos += __popcll(mpos[q]);
+    }
+    int bp = 0, bz = npos;
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      posq[q] = nq[q] > 0.f ? bp + prefix_count(mpos[q]) : bz + prefix_count(mzero[q]);
+      bp += __popcll(mpos[q]);
+      bz += __popcll(mzero[q]);
+    }
+  }
+  const float N32 = (float)N;
+
+  double sx = G.s0x, sy = G.s0y, sz = G.s0z;
+  int Kev = G.K;
+  if (G.seed_steps && io.seeds) {
+    // steps from the seed's predicted spread: the smallest iteration count
+    // in [kmin, kmax] whose first step covers kappa * sigma on every axis,
+    // ending on the configured final step
+    const double lv = io.seeds[e * 4 + 3];
+    const double sg = exp(0.5 * lv) * G.kappa;
+    double s3[3] = {G.sfinal[0], G.sfinal[1], G.sfinal[2]};
+    const int nn3[3] = {G.nx, G.ny, G.nz};
+    int kk = 0;
+    for (; kk < G.kmin - 1; ++kk)
+      for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+    if (!(sg < __builtin_huge_val())) {
+      for (; kk < G.kmax - 1; ++kk)
+        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+    } else {
+      for (;;) {
+        bool short_ = false;
+        for (int a = 0; a < 3; ++a)
+          if (nn3[a] > 1 && s3[a] < sg * G.sscale[a]) short_ = true;
+        if (!short_ || kk >= G.kmax - 1) break;
+        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+        ++kk;
+      }
+    }
+    Kev = uni(kk + 1);
+    sx = uni(G.nx > 1 ? s3[0] : 0.0);
+    sy = uni(G.ny > 1 ? s3[1] : 0.0);
+    sz = uni(G.nz > 1 ? s3[2] : 0.0);
+  }
+  int nfp = 0;
+  for (int k = 0; k < Kev; ++k) {
+    const int lk = opaque(lane);
+    // ---- r-z: collapse the table along z for this iteration's planes
+    if constexpr (KIND == ANTS_LRF_RZ) {
+      const int ntot = G.nz * L.nintp;
+      for (int i = lane; i < ntot; i += 64) {
+        int jz = i / L.nintp, m = i - jz * L.nintp;
+        double zz = cz + (double)(jz - G.hz) * sz;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        int mz;
+        double tz, bz[4];
+        if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
+          bweights64(tz, bz);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float wq = (float)bz[q];
+            float4 P = btab[(mz + q) * L.nintp + m];
+            acc.x = fmaf(wq, P.x, acc.x);
+            acc.y = fmaf(wq, P.y, acc.y);
+            acc.z = fmaf(wq, P.z, acc.z);
+            acc.w = fmaf(wq, P.w, acc.w);
+          }
+        }
+        ztab[i] = acc;
+      }
+      wave_sync_lds();
+    }
+
+    // ---- reference at the centre, per sensor (lane-parallel)
+    NodeF<KIND> ndc;
+    {
+      double xx, yy, zz;
+      int jc = (G.hz * G.ny + G.hy) * G.nx + G.hx;
+      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jc, ztab, ndc, xx, yy, zz);
+    }
+    float Sc = 0.f;
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      int a = lane + 64 * q;
+      if (a < na) {
+        float dX = (float)(L.X[a] - cx), dY = (float)(L.Y[a] - cy);
+        int tofs = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
+        float Lc = lrf32<KIND>(ndc, dX, dY, tofs, btab, L.c32, L.nc0, finv, nlast);
+        float g = (float)L.g[a];
+        Sc = fmaf(g, Lc, Sc);
+        recA[posq[q]] = make_float4(dX, dY, nq[q], 1.0f / fmaxf(Lc, flf));
+        recB[posq[q]] = make_float4(g, Lc, __int_as_float(tofs), __int_as_float(a));
+      }
+    }
+    Sc = uni(wsum_f(Sc));
+    const bool rel = Sc > 0.f;   // centre-relative form available
+    if (!rel) {
+      // absolute form: L_c = 0 and 1/L_c = 1 make dS = S and the log terms absolute
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        int a = lane + 64 * q;
+        if (a < na) {
+          recA[posq[q]].w = 1.f;
+          recB[posq[q]].y = 0.f;
+        }
+      }
+    }
+    const float iSc = rel ? 1.0f / Sc : 1.0f;
+    wave_sync_lds();
+
+    // ---- node set-up
+    NodeF<KIND> nd[NT];
+    bool valid[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double xx, yy, zz;
+      valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, t * 64 + lk, ztab, nd[t], xx,
+                                 yy, zz);
+    }
+
+    // ---- FP32 screen
+    float D[NT], Snode[NT];
+    if constexpr (STAT == ANTS_STAT_ML) {
+      float dS[NT], T[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { dS[t] = 0.f; T[t] = 0.f; }
+      for (int p = 0; p < npos; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+          T[t] = fmaf(A.z, __builtin_amdgcn_logf(fmaxf(Lv, flf) * A.w), T[t]);
+        }
+      }
+      for (int p = npos; p < na; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        float S = rel ? Sc + dS[t] : dS[t];
+        float lS = rel ? log2_1p(dS[t] * iSc) : __builtin_amdgcn_logf(dS[t]);
+        float d = N32 * lS - T[t];
+        Snode[t] = S;
+        D[t] = (valid[t] && S > 0.f && d < kInf && d > -kInf) ? d : kInf;
+      }
+    } else {
+      float S[NT], Q[NT], Ag[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { S[t] = 0.f; Q[t] = 0.f; }
+      for (int p = 0; p < na; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          S[t] = fmaf(B.x, Lv, S[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) Ag[t] = S[t] > 0.f ? N32 / S[t] : 0.f;
+      for (int p = 0; p < na; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          float mu = Ag[t] * B.x * Lv;
+          float dd = A.z - mu;
+          float v = fmaxf(mu, fvf);
+          Q[t] = fmaf(dd * dd, __builtin_amdgcn_rcpf(v), Q[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        Snode[t] = S[t];
+        D[t] = (valid[t] && S[t] > 0.f && Q[t] < kInf) ? Q[t] : kInf;
+      }
+    }
+
+    // ---- trusted screen values; best screened node
+    // (centre-relative ML values of nodes with S far below S_c suffer
+    //  cancellation; such nodes are always re-decided in FP64)
+    bool trusted[NT];
+    float best = kInf;
+    int jb = 1 << 30;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      trusted[t] = (STAT == ANTS_STAT_ML && rel) ? (Snode[t] >= 0.01f * Sc) : true;
+      float v = trusted[t] ? D[t] : kInf;
+      int j = t * 64 + lane;
+      if (v < best || (v == best && j < jb)) { best = v; jb = j; }
+    }
+    wargmin_f(best, jb);
+    best = uni(best);
+    jb = uni(jb);
+
+    // ---- error bound of the screen at the best node (lane-parallel over sensors)
+    float margin = 0.f;
+    if (best < kInf) {
+      NodeF<KIND> ndb;
+      double xx, yy, zz;
+      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, ndb, xx, yy, zz);
+      float Lb[SL];
+      float4 RA[SL], RB[SL];
+      float Sb = 0.f;
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        int a = lane + 64 * q;
+        Lb[q] = 0.f;
+        RA[q] = make_float4(0.f, 0.f, 0.f, 1.f);
+        RB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (a < na) {
+          RA[q] = recA[posq[q]];
+          RB[q] = recB[posq[q]];
+          Lb[q] = lrf32<KIND>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab, L.c32,
+                              L.nc0, finv, nlast);
+          Sb = fmaf(RB[q].x, Lb[q], Sb);
+        }
+      }
+      Sb = wsum_f(Sb);
+      if (STAT == ANTS_STAT_ML) {
+        float A1 = 0.f, A2 = 0.f, A3 = 0.f;
+        float iSb = Sb > 0.f ? 1.0f / Sb : 0.f;
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+          int a = lane + 64 * q;
+          if (a < na) {
+            float mu = N32 * RB[q].x * Lb[q] * iSb;
+            A1 += fabsf(mu - RA[q].z);
+            A2 += fabsf(RA[q].z * __builtin_amdgcn_logf(fmaxf(Lb[q], flf) * RA[q].w));
+            A3 += RB[q].x * fabsf(Lb[q] - RB[q].y);
+          }
+        }
+        A1 = wsum_f(A1);
+        A2 = wsum_f(A2);
+        A3 = wsum_f(A3);
+        float lsr = (rel && Sb > 0.f) ? fabsf(__builtin_amdgcn_logf(Sb * iSc)) : 0.f;
+        float E = kU * (kLog2e * (24.f * A1 + 2.f * N32 + (float)(na + 2) * N32 * A3 * iSb) +
+                        (float)(na + 4) * A2 + 4.f * N32 * lsr);
+        margin = 4.f * G.margin_scale * E;
+      } else {
+        float A1 = 0.f;
+        float Ab = Sb > 0.f ? N32 / Sb : 0.f;
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+          int a = lane + 64 * q;
+          if (a < na) {
+            float mu = Ab * RB[q].x * Lb[q];
+            float dd = RA[q].z - mu;
+            float v = fmaxf(mu, fvf);
+            A1 += 2.f * fabsf(dd) + dd * dd / v;
+          }
+        }
+        A1 = wsum_f(A1);
+        float E = kU * (float)(24 + na + 4) * A1;
+        margin = 4.f * G.margin_scale * E;
+      }
+      margin = uni(margin);
+      if (!(margin < kInf)) margin = kInf;
+    }
+
+    // ---- candidates: trusted nodes within the bound, and untrusted valid nodes
+    int ncand = 0;
+    bool only_trusted = true;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bool c = trusted[t] ? (D[t] < kInf && D[t] <= best + margin)
+                          : (valid[t] && Snode[t] > -kInf);
+      uint64_t m = __ballot(c);
+      if (c) cand[ncand + prefix_count(m)] = t * 64 + lane;
+      ncand += __popcll(m);
+      if (__ballot(c && !trusted[t])) only_trusted = false;
+    }
+    wave_sync_lds();
+
+    int win = -1;
+    bool tie = false;
+    if (ncand == 1 && only_trusted) {
+      win = jb;
+    } else if (ncand > 0) {
+      double bestd = __builtin_huge_val();
+      int jd = 1 << 30;
+      for (int base = 0; base < ncand; base += 64) {
+        double Dv = __builtin_huge_val();
+        int j = 1 << 30;
+        if (base + lane < ncand) {
+          j = cand[base + lane];
+          NodeF<KIND> ndd;
+          double xx, yy, zz;
+          bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, ndd, xx, yy, zz);
+          if (ok) {
+            double S = 0.0, T = 0.0;
+            for (int p = 0; p < na; ++p) {
+              float4 A = recA[p];
+              int a = __float_as_int(recB[p].w);
+              double Lv = lrf64<KIND>(L, a, xx, yy, zz);
+              S += L.g[a] * Lv;
+              if (A.z > 0.f) T += (double)A.z * log(Lv > G.lfloor ? Lv : G.lfloor);
+            }
+            if (S > 0.0) {
+              if (STAT == ANTS_STAT_ML) {
+                Dv = N * log(S) - T;
+              } else {
+                double Aa = N / S, Q = 0.0;
+                for (int p = 0; p < na; ++p) {
+                  float4 A = recA[p];
+                  int a = __float_as_int(recB[p].w);
+                  double mu = Aa * L.g[a] * lrf64<KIND>(L, a, xx, yy, zz);
+                  double dd = (double)A.z - mu;
+                  Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+                }
+                Dv = Q;
+              }
+              if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
+            }
+          }
+        }
+        double v1 = Dv;
+        int j1 = j;
+        wargmin_d(v1, j1);
+        const bool fin = v1 < __builtin_huge_val();
+        // candidates are listed in increasing node index, so an earlier
+        // chunk's winner keeps priority on equal values
+        int nsame = __popcll(__ballot(fin && Dv == v1));
+        if (v1 < bestd) {
+          bestd = v1;
+          jd = j1;
+          tie = nsame > 1;
+        } else if (fin && v1 == bestd) {
+          tie = true;
+        }
+      }
+      nfp += ncand;
+      win = bestd < __builtin_huge_val() ? jd : -1;
+      win = uni(win);
+    }
+    if (io.path && lane == 0 && k < G.K) io.path[e * G.K + k] = win;
+    if (win < 0) {
+      status |= ANTS_EV_NO_VALID_NODE;
+    } else {
+      if (tie) status |= ANTS_EV_TIE;
+      int jx = win % G.nx, jy = (win / G.nx) % G.ny, jz = win / (G.nx * G.ny);
+      cx = uni(cx + (double)(jx - G.hx) * sx);
+      cy = uni(cy + (double)(jy - G.hy) * sy);
+      cz = uni(cz + (double)(jz - G.hz) * sz);
+    }
+    sx = uni(sx * G.shrink);
+    sy = uni(sy * G.shrink);
+    sz = uni(sz * G.shrink);
+    wave_sync_lds();
+  }
+
+  // ---------------- outputs at the final centre, FP64, lane-parallel over sensors
+  double S = 0.0;
+  double Lf[SL];
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    int a = lane + 64 * q;
+    Lf[q] = 0.0;
+    if (a < na) {
+      Lf[q] = lrf64<KIND>(L, a, cx, cy, cz);
+      S += L.g[a] * Lf[q];
+    }
+  }
+  S = wsum_d(S);
+  double Aa = N / S, ll = 0.0, q2 = 0.0;
+  bool okS = S > 0.0 && S < __builtin_huge_val();
+  if (okS) {
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      int a = lane + 64 * q;
+      if (a < na) {
+        double mu = Aa * L.g[a] * Lf[q];
+        double Lt = Lf[q] > G.lfloor ? Lf[q] : G.lfloor;
+        double n = (double)nq[q];
+        if (n > 0.0) ll += n * log(Aa * L.g[a] * Lt);
+        ll -= mu;
+        double dd = n - mu;
+        q2 += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+      }
+    }
+    ll = wsum_d(ll);
+    q2 = wsum_d(q2);
+  }
+  if (io.path && Kev < G.K && lane >= Kev && lane < G.K) io.path[e * G.K + lane] = -1;
+  status |= G.or_status;
+  if (lane == 0) {
+    if (G.fb_thr > 0.0 && !(okS && ndf > 0 && q2 / ndf <= G.fb_thr)) {
+      int slot = atomicAdd(io.fb_count, 1);
+      io.fb_list[slot] = (int32_t)e;
+    }
+    float nan = __builtin_nanf("");
+    io.x[e] = (float)cx;
+    io.y[e] = (float)cy;
+    io.z[e] = (float)cz;
+    io.E[e] = okS ? (float)Aa : nan;
+    io.lnl[e] = okS ? (float)ll : nan;
+    io.chi2[e] = okS ? (float)q2 : nan;
+    io.ndf[e] = ndf;
+    io.status[e] = status;
+    if (io.nfp) io.nfp[e] = nfp;
+  }
+}
+
 template <int KIND, int STAT, int NT, int SL>
 __global__ void __launch_bounds__(256)
 cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, int btab_n) {
@@ -222,511 +724,14 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
   float4* btab = smem4;
   for (int i = threadIdx.x; i < btab_n; i += blockDim.x) btab[i] = ((const float4*)L.pp)[i];
   __syncthreads();
-
   const int lane0 = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwb = blockDim.x >> 6;
   unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
-  float4* recA = (float4*)wbase;
-  float4* recB = recA + L.na;
-  float4* ztab = recB + L.na;
-  int* cand = (int*)(ztab + (KIND == ANTS_LRF_RZ ? G.nz * L.nintp : 0));
-
-  const int na = L.na;
-  const int nlast = L.nintp - 1;
-  const float finv = L.finv0;
-  const float flf = (float)G.lfloor;
-  const float fvf = (float)G.vfloor;
-
   int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
   for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
     const int64_t e = io.list ? (int64_t)io.list[w] : w;
-    const int lane = opaque(lane0);
-    const float* row = io.sig + e * io.ld;
-
-    // ---------------- event set-up: signals of the active sensors
-    float nq[SL];
-    int posq[SL];
-    double N = 0.0, cw = 0.0, cxs = 0.0, cys = 0.0;
-    bool bad = false;
-    float best_n = -1.0f;
-    int best_a = 1 << 30;
-#pragma unroll
-    for (int q = 0; q < SL; ++q) {
-      int a = lane + 64 * q;
-      nq[q] = 0.f;
-      if (a < na) {
-        float n = row[L.col[a]];
-        nq[q] = n;
-        if (!(n >= 0.f) || !(n < kInf)) {
-          bad = true;
-        } else {
-          double wgt = (double)n / L.g[a];
-          N += (double)n;
-          cw += wgt;
-          cxs += L.X[a] * wgt;
-          cys += L.Y[a] * wgt;
-          if (n > best_n) { best_n = n; best_a = a; }
-        }
-      }
-    }
-    bool any_bad = __ballot(bad) != 0ull;
-    N = uni(wsum_d(N));
-    const int ndf = na - (G.dim + 1);
-    int status = 0;
-    if (na == 0) status = ANTS_EV_NO_ACTIVE;
-    else if (any_bad) status = ANTS_EV_BAD_INPUT;
-    else if (!(N > 0.0)) status = ANTS_EV_EMPTY;
-    if (status) {
-      if (lane == 0) {
-        float nan = __builtin_nanf("");
-        io.x[e] = nan; io.y[e] = nan; io.z[e] = nan; io.E[e] = nan;
-        io.lnl[e] = nan; io.chi2[e] = nan; io.ndf[e] = ndf; io.status[e] = status;
-        if (io.nfp) io.nfp[e] = 0;
-      }
-      if (io.path && lane < G.K) io.path[e * G.K + lane] = -1;
-      continue;
-    }
-    cw = wsum_d(cw);
-    cxs = wsum_d(cxs);
-    cys = wsum_d(cys);
-
-    double cx, cy, cz = G.z_start;
-    if (G.start == ANTS_START_SEED && io.seeds) {
-      cx = io.seeds[e * 4 + 0];
-      cy = io.seeds[e * 4 + 1];
-      if (G.dim == 3) cz = io.seeds[e * 4 + 2];
-    } else if (G.start == ANTS_START_MAXSENSOR) {
-      wargmax_f(best_n, best_a);
-      best_a = uni(best_a);
-      cx = L.X[best_a];
-      cy = L.Y[best_a];
-    } else {
-      cx = cxs / cw;
-      cy = cys / cw;
-    }
-    cx = uni(cx);
-    cy = uni(cy);
-    cz = uni(cz);
-
-    // sensor records in LDS: sensors with n > 0 first, then n == 0
-    int npos = 0;
-    {
-      uint64_t mpos[SL], mzero[SL];
-#pragma unroll
-      for (int q = 0; q < SL; ++q) {
-        int a = lane + 64 * q;
-        mpos[q] = __ballot(a < na && nq[q] > 0.f);
-        mzero[q] = __ballot(a < na && !(nq[q] > 0.f));
-        npos += __popcll(mpos[q]);
-      }
-      int bp = 0, bz = npos;
-#pragma unroll
-      for (int q = 0; q < SL; ++q) {
-        posq[q] = nq[q] > 0.f ? bp + prefix_count(mpos[q]) : bz + prefix_count(mzero[q]);
-        bp += __popcll(mpos[q]);
-        bz += __popcll(mzero[q]);
-      }
-    }
-    const float N32 = (float)N;
-
-    double sx = G.s0x, sy = G.s0y, sz = G.s0z;
-    int Kev = G.K;
-    if (G.seed_steps && io.seeds) {
-      // steps from the seed's predicted spread: the smallest iteration count
-      // in [kmin, kmax] whose first step covers kappa * sigma on every axis,
-      // ending on the configured final step
-      const double lv = io.seeds[e * 4 + 3];
-      const double sg = exp(0.5 * lv) * G.kappa;
-      double s3[3] = {G.sfinal[0], G.sfinal[1], G.sfinal[2]};
-      const int nn3[3] = {G.nx, G.ny, G.nz};
-      int kk = 0;
-      for (; kk < G.kmin - 1; ++kk)
-        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
-      if (!(sg < __builtin_huge_val())) {
-        for (; kk < G.kmax - 1; ++kk)
-          for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
-      } else {
-        for (;;) {
-          bool short_ = false;
-          for (int a = 0; a < 3; ++a)
-            if (nn3[a] > 1 && s3[a] < sg * G.sscale[a]) short_ = true;
-          if (!short_ || kk >= G.kmax - 1) break;
-          for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
-          ++kk;
-        }
-      }
-      Kev = uni(kk + 1);
-      sx = uni(G.nx > 1 ? s3[0] : 0.0);
-      sy = uni(G.ny > 1 ? s3[1] : 0.0);
-      sz = uni(G.nz > 1 ? s3[2] : 0.0);
-    }
-    int nfp = 0;
-    for (int k = 0; k < Kev; ++k) {
-      const int lk = opaque(lane);
-      // ---- r-z: collapse the table along z for this iteration's planes
-      if constexpr (KIND == ANTS_LRF_RZ) {
-        const int ntot = G.nz * L.nintp;
-        for (int i = lane; i < ntot; i += 64) {
-          int jz = i / L.nintp, m = i - jz * L.nintp;
-          double zz = cz + (double)(jz - G.hz) * sz;
-          float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-          int mz;
-          double tz, bz[4];
-          if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
-            bweights64(tz, bz);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              float wq = (float)bz[q];
-              float4 P = btab[(mz + q) * L.nintp + m];
-              acc.x = fmaf(wq, P.x, acc.x);
-              acc.y = fmaf(wq, P.y, acc.y);
-              acc.z = fmaf(wq, P.z, acc.z);
-              acc.w = fmaf(wq, P.w, acc.w);
-            }
-          }
-          ztab[i] = acc;
-        }
-        wave_sync_lds();
-      }
-
-      // ---- reference at the centre, per sensor (lane-parallel)
-      NodeF<KIND> ndc;
-      {
-        double xx, yy, zz;
-        int jc = (G.hz * G.ny + G.hy) * G.nx + G.hx;
-        make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jc, ztab, ndc, xx, yy, zz);
-      }
-      float Sc = 0.f;
-#pragma unroll
-      for (int q = 0; q < SL; ++q) {
-        int a = lane + 64 * q;
-        if (a < na) {
-          float dX = (float)(L.X[a] - cx), dY = (float)(L.Y[a] - cy);
-          int tofs = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
-          float Lc = lrf32<KIND>(ndc, dX, dY, tofs, btab, L.c32, L.nc0, finv, nlast);
-          float g = (float)L.g[a];
-          Sc = fmaf(g, Lc, Sc);
-          recA[posq[q]] = make_float4(dX, dY, nq[q], 1.0f / fmaxf(Lc, flf));
-          recB[posq[q]] = make_float4(g, Lc, __int_as_float(tofs), __int_as_float(a));
-        }
-      }
-      Sc = uni(wsum_f(Sc));
-      const bool rel = Sc > 0.f;   // centre-relative form available
-      if (!rel) {
-        // absolute form: L_c = 0 and 1/L_c = 1 make dS = S and the log terms absolute
-#pragma unroll
-        for (int q = 0; q < SL; ++q) {
-          int a = lane + 64 * q;
-          if (a < na) {
-            recA[posq[q]].w = 1.f;
-            recB[posq[q]].y = 0.f;
-          }
-        }
-      }
-      const float iSc = rel ? 1.0f / Sc : 1.0f;
-      wave_sync_lds();
-
-      // ---- node set-up
-      NodeF<KIND> nd[NT];
-      bool valid[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        double xx, yy, zz;
-        valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, t * 64 + lk, ztab, nd[t], xx,
-                                   yy, zz);
-      }
-
-      // ---- FP32 screen
-      float D[NT], Snode[NT];
-      if constexpr (STAT == ANTS_STAT_ML) {
-        float dS[NT], T[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) { dS[t] = 0.f; T[t] = 0.f; }
-        for (int p = 0; p < npos; ++p) {
-          float4 A = recA[p], B = recB[p];
-          int tofs = __float_as_int(B.z);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
-            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
-            T[t] = fmaf(A.z, __builtin_amdgcn_logf(fmaxf(Lv, flf) * A.w), T[t]);
-          }
-        }
-        for (int p = npos; p < na; ++p) {
-          float4 A = recA[p], B = recB[p];
-          int tofs = __float_as_int(B.z);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
-            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          float S = rel ? Sc + dS[t] : dS[t];
-          float lS = rel ? log2_1p(dS[t] * iSc) : __builtin_amdgcn_logf(dS[t]);
-          float d = N32 * lS - T[t];
-          Snode[t] = S;
-          D[t] = (valid[t] && S > 0.f && d < kInf && d > -kInf) ? d : kInf;
-        }
-      } else {
-        float S[NT], Q[NT], Ag[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) { S[t] = 0.f; Q[t] = 0.f; }
-        for (int p = 0; p < na; ++p) {
-          float4 A = recA[p], B = recB[p];
-          int tofs = __float_as_int(B.z);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
-            S[t] = fmaf(B.x, Lv, S[t]);
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) Ag[t] = S[t] > 0.f ? N32 / S[t] : 0.f;
-        for (int p = 0; p < na; ++p) {
-          float4 A = recA[p], B = recB[p];
-          int tofs = __float_as_int(B.z);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            float Lv = lrf32<KIND>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
-            float mu = Ag[t] * B.x * Lv;
-            float dd = A.z - mu;
-            float v = fmaxf(mu, fvf);
-            Q[t] = fmaf(dd * dd, __builtin_amdgcn_rcpf(v), Q[t]);
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          Snode[t] = S[t];
-          D[t] = (valid[t] && S[t] > 0.f && Q[t] < kInf) ? Q[t] : kInf;
-        }
-      }
-
-      // ---- trusted screen values; best screened node
-      // (centre-relative ML values of nodes with S far below S_c suffer
-      //  cancellation; such nodes are always re-decided in FP64)
-      bool trusted[NT];
-      float best = kInf;
-      int jb = 1 << 30;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        trusted[t] = (STAT == ANTS_STAT_ML && rel) ? (Snode[t] >= 0.01f * Sc) : true;
-        float v = trusted[t] ? D[t] : kInf;
-        int j = t * 64 + lane;
-        if (v < best || (v == best && j < jb)) { best = v; jb = j; }
-      }
-      wargmin_f(best, jb);
-      best = uni(best);
-      jb = uni(jb);
-
-      // ---- error bound of the screen at the best node (lane-parallel over sensors)
-      float margin = 0.f;
-      if (best < kInf) {
-        NodeF<KIND> ndb;
-        double xx, yy, zz;
-        make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, ndb, xx, yy, zz);
-        float Lb[SL];
-        float4 RA[SL], RB[SL];
-        float Sb = 0.f;
-#pragma unroll
-        for (int q = 0; q < SL; ++q) {
-          int a = lane + 64 * q;
-          Lb[q] = 0.f;
-          RA[q] = make_float4(0.f, 0.f, 0.f, 1.f);
-          RB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (a < na) {
-            RA[q] = recA[posq[q]];
-            RB[q] = recB[posq[q]];
-            Lb[q] = lrf32<KIND>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab, L.c32,
-                                L.nc0, finv, nlast);
-            Sb = fmaf(RB[q].x, Lb[q], Sb);
-          }
-        }
-        Sb = wsum_f(Sb);
-        if (STAT == ANTS_STAT_ML) {
-          float A1 = 0.f, A2 = 0.f, A3 = 0.f;
-          float iSb = Sb > 0.f ? 1.0f / Sb : 0.f;
-#pragma unroll
-          for (int q = 0; q < SL; ++q) {
-            int a = lane + 64 * q;
-            if (a < na) {
-              float mu = N32 * RB[q].x * Lb[q] * iSb;
-              A1 += fabsf(mu - RA[q].z);
-              A2 += fabsf(RA[q].z * __builtin_amdgcn_logf(fmaxf(Lb[q], flf) * RA[q].w));
-              A3 += RB[q].x * fabsf(Lb[q] - RB[q].y);
-            }
-          }
-          A1 = wsum_f(A1);
-          A2 = wsum_f(A2);
-          A3 = wsum_f(A3);
-          float lsr = (rel && Sb > 0.f) ? fabsf(__builtin_amdgcn_logf(Sb * iSc)) : 0.f;
-          float E = kU * (kLog2e * (24.f * A1 + 2.f * N32 + (float)(na + 2) * N32 * A3 * iSb) +
-                          (float)(na + 4) * A2 + 4.f * N32 * lsr);
-          margin = 4.f * G.margin_scale * E;
-        } else {
-          float A1 = 0.f;
-          float Ab = Sb > 0.f ? N32 / Sb : 0.f;
-#pragma unroll
-          for (int q = 0; q < SL; ++q) {
-            int a = lane + 64 * q;
-            if (a < na) {
-              float mu = Ab * RB[q].x * Lb[q];
-              float dd = RA[q].z - mu;
-              float v = fmaxf(mu, fvf);
-              A1 += 2.f * fabsf(dd) + dd * dd / v;
-            }
-          }
-          A1 = wsum_f(A1);
-          float E = kU * (float)(24 + na + 4) * A1;
-          margin = 4.f * G.margin_scale * E;
-        }
-        margin = uni(margin);
-        if (!(margin < kInf)) margin = kInf;
-      }
-
-      // ---- candidates: trusted nodes within the bound, and untrusted valid nodes
-      int ncand = 0;
-      bool only_trusted = true;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        bool c = trusted[t] ? (D[t] < kInf && D[t] <= best + margin)
-                            : (valid[t] && Snode[t] > -kInf);
-        uint64_t m = __ballot(c);
-        if (c) cand[ncand + prefix_count(m)] = t * 64 + lane;
-        ncand += __popcll(m);
-        if (__ballot(c && !trusted[t])) only_trusted = false;
-      }
-      wave_sync_lds();
-
-      int win = -1;
-      bool tie = false;
-      if (ncand == 1 && only_trusted) {
-        win = jb;
-      } else if (ncand > 0) {
-        double bestd = __builtin_huge_val();
-        int jd = 1 << 30;
-        for (int base = 0; base < ncand; base += 64) {
-          double Dv = __builtin_huge_val();
-          int j = 1 << 30;
-          if (base + lane < ncand) {
-            j = cand[base + lane];
-            NodeF<KIND> ndd;
-            double xx, yy, zz;
-            bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, ndd, xx, yy, zz);
-            if (ok) {
-              double S = 0.0, T = 0.0;
-              for (int p = 0; p < na; ++p) {
-                float4 A = recA[p];
-                int a = __float_as_int(recB[p].w);
-                double Lv = lrf64<KIND>(L, a, xx, yy, zz);
-                S += L.g[a] * Lv;
-                if (A.z > 0.f) T += (double)A.z * log(Lv > G.lfloor ? Lv : G.lfloor);
-              }
-              if (S > 0.0) {
-                if (STAT == ANTS_STAT_ML) {
-                  Dv = N * log(S) - T;
-                } else {
-                  double Aa = N / S, Q = 0.0;
-                  for (int p = 0; p < na; ++p) {
-                    float4 A = recA[p];
-                    int a = __float_as_int(recB[p].w);
-                    double mu = Aa * L.g[a] * lrf64<KIND>(L, a, xx, yy, zz);
-                    double dd = (double)A.z - mu;
-                    Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
-                  }
-                  Dv = Q;
-                }
-                if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
-              }
-            }
-          }
-          double v1 = Dv;
-          int j1 = j;
-          wargmin_d(v1, j1);
-          const bool fin = v1 < __builtin_huge_val();
-          // candidates are listed in increasing node index, so an earlier
-          // chunk's winner keeps priority on equal values
-          int nsame = __popcll(__ballot(fin && Dv == v1));
-          if (v1 < bestd) {
-            bestd = v1;
-            jd = j1;
-            tie = nsame > 1;
-          } else if (fin && v1 == bestd) {
-            tie = true;
-          }
-        }
-        nfp += ncand;
-        win = bestd < __builtin_huge_val() ? jd : -1;
-        win = uni(win);
-      }
-      if (io.path && lane == 0 && k < G.K) io.path[e * G.K + k] = win;
-      if (win < 0) {
-        status |= ANTS_EV_NO_VALID_NODE;
-      } else {
-        if (tie) status |= ANTS_EV_TIE;
-        int jx = win % G.nx, jy = (win / G.nx) % G.ny, jz = win / (G.nx * G.ny);
-        cx = uni(cx + (double)(jx - G.hx) * sx);
-        cy = uni(cy + (double)(jy - G.hy) * sy);
-        cz = uni(cz + (double)(jz - G.hz) * sz);
-      }
-      sx = uni(sx * G.shrink);
-      sy = uni(sy * G.shrink);
-      sz = uni(sz * G.shrink);
-      wave_sync_lds();
-    }
-
-    // ---------------- outputs at the final centre, FP64, lane-parallel over sensors
-    double S = 0.0;
-    double Lf[SL];
-#pragma unroll
-    for (int q = 0; q < SL; ++q) {
-      int a = lane + 64 * q;
-      Lf[q] = 0.0;
-      if (a < na) {
-        Lf[q] = lrf64<KIND>(L, a, cx, cy, cz);
-        S += L.g[a] * Lf[q];
-      }
-    }
-    S = wsum_d(S);
-    double Aa = N / S, ll = 0.0, q2 = 0.0;
-    bool okS = S > 0.0 && S < __builtin_huge_val();
-    if (okS) {
-#pragma unroll
-      for (int q = 0; q < SL; ++q) {
-        int a = lane + 64 * q;
-        if (a < na) {
-          double mu = Aa * L.g[a] * Lf[q];
-          double Lt = Lf[q] > G.lfloor ? Lf[q] : G.lfloor;
-          double n = (double)nq[q];
-          if (n > 0.0) ll += n * log(Aa * L.g[a] * Lt);
-          ll -= mu;
-          double dd = n - mu;
-          q2 += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
-        }
-      }
-      ll = wsum_d(ll);
-      q2 = wsum_d(q2);
-    }
-    if (io.path && Kev < G.K && lane >= Kev && lane < G.K) io.path[e * G.K + lane] = -1;
-    status |= G.or_status;
-    if (lane == 0) {
-      if (G.fb_thr > 0.0 && !(okS && ndf > 0 && q2 / ndf <= G.fb_thr)) {
-        int slot = atomicAdd(io.fb_count, 1);
-        io.fb_list[slot] = (int32_t)e;
-      }
-      float nan = __builtin_nanf("");
-      io.x[e] = (float)cx;
-      io.y[e] = (float)cy;
-      io.z[e] = (float)cz;
-      io.E[e] = okS ? (float)Aa : nan;
-      io.lnl[e] = okS ? (float)ll : nan;
-      io.chi2[e] = okS ? (float)q2 : nan;
-      io.ndf[e] = ndf;
-      io.status[e] = status;
-      if (io.nfp) io.nfp[e] = nfp;
-    }
+    process_event<KIND, STAT, NT, SL>(L, G, io, e, btab, wbase, opaque(lane0));
   }
 }
 
@@ -772,6 +777,108 @@ hipError_t launch_ks(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t
   return launch_kss<KIND, STAT, 4>(L, G, io, s, mb);
 }
 
+
+// ------------------------------------------------- persistent multi-detector
+
+// One launch over event chunks from several detectors (LRF sets): waves pull
+// work items (chunk, tile of `T` events) from a device counter until the
+// stream is exhausted; every wave leaves the loop once the counter passes
+// the last item.
+template <int KIND, int STAT, int NT, int SL>
+__global__ void __launch_bounds__(256) cg_multi_kernel(MultiP P) {
+  extern __shared__ float4 smem4[];
+  float4* btab = smem4;
+  if (P.tab_in_lds) {
+    for (int si = 0; si < P.n_sets; ++si) {
+      const DevLrf& L = P.sets[si].L;
+      const int n = KIND == ANTS_LRF_AXIAL ? L.ntab * L.nintp : KIND == ANTS_LRF_RZ ? L.nc1 * L.nintp : 0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x)
+        btab[P.sets[si].tab_off + i] = ((const float4*)L.pp)[i];
+    }
+  }
+  __syncthreads();
+  const int lane0 = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* wbase = (unsigned char*)(smem4 + P.btab_n) + (size_t)wv * P.per_wave_bytes;
+  for (;;) {
+    int item = 0;
+    if (lane0 == 0) item = atomicAdd(P.counter, 1);
+    item = uni(__shfl(item, 0));
+    if (item >= P.n_items) break;
+    int lo = 0, hi = P.n_chunks;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (P.prefix[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    lo = uni(lo);
+    const ChunkDesc ch = P.chunks[lo];
+    const SetDesc& sd = P.sets[ch.set];
+    IoP io = P.out;
+    io.sig = ch.sig;
+    io.ld = sd.L.ns;
+    io.n = ch.n;
+    io.x += ch.out_off;
+    io.y += ch.out_off;
+    io.z += ch.out_off;
+    io.E += ch.out_off;
+    io.lnl += ch.out_off;
+    io.chi2 += ch.out_off;
+    io.ndf += ch.out_off;
+    io.status += ch.out_off;
+    const float4* tb = P.tab_in_lds ? btab + sd.tab_off : (const float4*)sd.L.pp;
+    const int64_t e0 = (int64_t)(item - P.prefix[lo]) * P.T;
+    const int64_t e1 = e0 + P.T < ch.n ? e0 + P.T : ch.n;
+    for (int64_t e = e0; e < e1; ++e)
+      process_event<KIND, STAT, NT, SL>(sd.L, sd.G, io, e, tb, wbase, opaque(lane0));
+  }
+}
+
+template <int KIND, int STAT, int NT, int SL>
+hipError_t launch_multi_t(const MultiP& P, int blocks, hipStream_t stream) {
+  size_t smem = (size_t)P.btab_n * 16 + (size_t)kWavesPerBlock * P.per_wave_bytes;
+  auto kern = cg_multi_kernel<KIND, STAT, NT, SL>;
+  if (smem > 65536) {
+    hipError_t st = hipFuncSetAttribute((const void*)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (st != hipSuccess) return st;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), smem, stream, P);
+  return hipGetLastError();
+}
+
+template <int KIND, int STAT, int SL>
+hipError_t launch_multi_ks(const MultiP& P, int nn, int blocks, hipStream_t s) {
+  int nt = (nn + 63) / 64;
+  if (nt <= 1) return launch_multi_t<KIND, STAT, 1, SL>(P, blocks, s);
+  if (nt <= 2) return launch_multi_t<KIND, STAT, 2, SL>(P, blocks, s);
+  if (nt <= 4) return launch_multi_t<KIND, STAT, 4, SL>(P, blocks, s);
+  if (nt <= 6) return launch_multi_t<KIND, STAT, 6, SL>(P, blocks, s);
+  return launch_multi_t<KIND, STAT, 8, SL>(P, blocks, s);
+}
+
+template <int KIND, int STAT>
+hipError_t launch_multi_k(const MultiP& P, int nn, int na, int blocks, hipStream_t s) {
+  if (na <= 64) return launch_multi_ks<KIND, STAT, 1>(P, nn, blocks, s);
+  if (na <= 128) return launch_multi_ks<KIND, STAT, 2>(P, nn, blocks, s);
+  return launch_multi_ks<KIND, STAT, 4>(P, nn, blocks, s);
+}
+
+}  // namespace
+
+hipError_t launch_multi(const MultiP& P, int kind, int stat, int max_nn, int max_na, int blocks,
+                        hipStream_t s) {
+  if (kind == ANTS_LRF_AXIAL)
+    return stat == ANTS_STAT_ML ? launch_multi_k<ANTS_LRF_AXIAL, 0>(P, max_nn, max_na, blocks, s)
+                                : launch_multi_k<ANTS_LRF_AXIAL, 1>(P, max_nn, max_na, blocks, s);
+  if (kind == ANTS_LRF_XY)
+    return stat == ANTS_STAT_ML ? launch_multi_k<ANTS_LRF_XY, 0>(P, max_nn, max_na, blocks, s)
+                                : launch_multi_k<ANTS_LRF_XY, 1>(P, max_nn, max_na, blocks, s);
+  return stat == ANTS_STAT_ML ? launch_multi_k<ANTS_LRF_RZ, 0>(P, max_nn, max_na, blocks, s)
+                              : launch_multi_k<ANTS_LRF_RZ, 1>(P, max_nn, max_na, blocks, s);
+}
+
+namespace {
 }  // namespace
 
 hipError_t launch_grid(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t stream,

@@ -118,7 +118,8 @@ typedef enum { ANTS_STAT_ML = 0, ANTS_STAT_CHI2 = 1 } ants_stat;
 typedef enum { ANTS_START_COG = 0, ANTS_START_MAXSENSOR = 1, ANTS_START_SEED = 2 } ants_start;
 
 typedef struct {
-  int32_t nodes[3];        /* odd, >= 1; nodes[2] = 1 for 2-D; product <= 512  */
+  int32_t nodes[3];        /* odd, >= 1; nodes[2] = 1 for 2-D (<= 101 for r-z);
+                              product <= 512                                    */
   int32_t iterations;      /* K grids evaluated, 0 .. 64 (0 returns the start) */
   double shrink;           /* step factor per iteration, (0, 1]                */
   double step0[3];         /* initial step per axis, mm (> 0 where nodes > 1)  */

@@ -116,6 +116,7 @@ ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
                      kMaxNodes);
   if (L.kind != ANTS_LRF_RZ && G.nz != 1)
     return set_error(ANTS_E_ARG, "a 2-D LRF needs nodes[2] = 1");
+  if (G.nz > 101) return set_error(ANTS_E_ARG, "nodes[2] = %d exceeds 101", G.nz);
   G.nn = G.nx * G.ny * G.nz;
   G.hx = (G.nx - 1) / 2;
   G.hy = (G.ny - 1) / 2;

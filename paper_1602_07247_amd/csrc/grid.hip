@@ -166,12 +166,26 @@ __device__ __forceinline__ float lrf32(const NodeF<KIND>& nd, float dX, float dY
 
 // Node j of the current grid: FP64 position, FP32 screen description and
 // validity (nodes whose z, or XY position, leave the LRF domain have S = 0).
+// Node index -> (jx, jy, jz) packed as jx | jy << 10 | jz << 20, one entry
+// per node of the current grid (avoids integer division in the loops).
+__device__ __forceinline__ void fill_nodeidx(const GridP& G, int* tab, int lane) {
+  for (int j = lane; j < kMaxNodes; j += 64) {
+    int v = 0;
+    if (j < G.nn) {
+      const int jx = j % G.nx, jy = (j / G.nx) % G.ny, jz = j / (G.nx * G.ny);
+      v = jx | (jy << 10) | (jz << 20);
+    }
+    tab[j] = v;
+  }
+}
+
 template <int KIND>
 __device__ __forceinline__ bool make_node(const DevLrf& L, const GridP& G, double cx, double cy,
                                           double cz, double sx, double sy, double sz, int j,
-                                          const float4* ztab, NodeF<KIND>& nd, double& x,
-                                          double& y, double& z) {
-  int jx = j % G.nx, jy = (j / G.nx) % G.ny, jz = j / (G.nx * G.ny);
+                                          const float4* ztab, const int* nodeidx,
+                                          NodeF<KIND>& nd, double& x, double& y, double& z) {
+  const int packed = nodeidx[j];
+  const int jx = packed & 1023, jy = (packed >> 10) & 1023, jz = packed >> 20;
   double ox = (double)(jx - G.hx) * sx;
   double oy = (double)(jy - G.hy) * sy;
   double oz = (double)(jz - G.hz) * sz;
@@ -224,6 +238,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   float4* recB = recA + L.na;
   float4* ztab = recB + L.na;
   int* cand = (int*)(ztab + (KIND == ANTS_LRF_RZ ? G.nz * L.nintp : 0));
+  const int* nodeidx = cand + kMaxNodes;
   const int na = L.na;
   const int nlast = L.nintp - 1;
   const float finv = L.finv0;
@@ -353,25 +368,36 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     const int lk = opaque(lane);
     // ---- r-z: collapse the table along z for this iteration's planes
     if constexpr (KIND == ANTS_LRF_RZ) {
-      const int ntot = G.nz * L.nintp;
-      for (int i = lane; i < ntot; i += 64) {
-        int jz = i / L.nintp, m = i - jz * L.nintp;
-        double zz = cz + (double)(jz - G.hz) * sz;
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      // plane weights once per plane (the candidate list area is free here)
+      float4* pw = (float4*)cand;
+      int* pm = cand + 4 * G.nz;
+      for (int jz = lane; jz < G.nz; jz += 64) {
+        const double zz = cz + (double)(jz - G.hz) * sz;
         int mz;
         double tz, bz[4];
         if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
           bweights64(tz, bz);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float wq = (float)bz[q];
-            float4 P = btab[(mz + q) * L.nintp + m];
-            acc.x = fmaf(wq, P.x, acc.x);
-            acc.y = fmaf(wq, P.y, acc.y);
-            acc.z = fmaf(wq, P.z, acc.z);
-            acc.w = fmaf(wq, P.w, acc.w);
-          }
+          pw[jz] = make_float4((float)bz[0], (float)bz[1], (float)bz[2], (float)bz[3]);
+          pm[jz] = mz;
+        } else {
+          pw[jz] = make_float4(0.f, 0.f, 0.f, 0.f);
+          pm[jz] = 0;
         }
+      }
+      wave_sync_lds();
+      const int ntot = G.nz * L.nintp;
+      const float inv_nintp = 1.0f / (float)L.nintp;
+      for (int i = lane; i < ntot; i += 64) {
+        const int jz = (int)(((float)i + 0.5f) * inv_nintp);
+        const int m = i - jz * L.nintp;
+        const float4 w = pw[jz];
+        const float4* P = btab + pm[jz] * L.nintp + m;
+        const float4 P0 = P[0], P1 = P[L.nintp], P2 = P[2 * L.nintp], P3 = P[3 * L.nintp];
+        float4 acc;
+        acc.x = fmaf(w.w, P3.x, fmaf(w.z, P2.x, fmaf(w.y, P1.x, w.x * P0.x)));
+        acc.y = fmaf(w.w, P3.y, fmaf(w.z, P2.y, fmaf(w.y, P1.y, w.x * P0.y)));
+        acc.z = fmaf(w.w, P3.z, fmaf(w.z, P2.z, fmaf(w.y, P1.z, w.x * P0.z)));
+        acc.w = fmaf(w.w, P3.w, fmaf(w.z, P2.w, fmaf(w.y, P1.w, w.x * P0.w)));
         ztab[i] = acc;
       }
       wave_sync_lds();
@@ -382,7 +408,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     {
       double xx, yy, zz;
       int jc = (G.hz * G.ny + G.hy) * G.nx + G.hx;
-      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jc, ztab, ndc, xx, yy, zz);
+      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jc, ztab, nodeidx, ndc, xx, yy, zz);
     }
     float Sc = 0.f;
 #pragma unroll
@@ -420,7 +446,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       double xx, yy, zz;
-      valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, t * 64 + lk, ztab, nd[t], xx,
+      valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, t * 64 + lk, ztab, nodeidx, nd[t], xx,
                                  yy, zz);
     }
 
@@ -513,7 +539,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     if (best < kInf) {
       NodeF<KIND> ndb;
       double xx, yy, zz;
-      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, ndb, xx, yy, zz);
+      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, nodeidx, ndb, xx, yy, zz);
       float Lb[SL];
       float4 RA[SL], RB[SL];
       float Sb = 0.f;
@@ -589,8 +615,65 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 
     int win = -1;
     bool tie = false;
+    // lanes over sensors, one candidate at a time, when that is cheaper
+    const int serial_max = (na * 5) / (SL * 5 + 2);
     if (ncand == 1 && only_trusted) {
       win = jb;
+    } else if (ncand > 0 && ncand <= serial_max) {
+      double bestd = __builtin_huge_val();
+      int jd = 1 << 30;
+      for (int c = 0; c < ncand; ++c) {
+        const int j = uni(cand[c]);
+        NodeF<KIND> ndd;
+        double xx, yy, zz;
+        const bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx,
+                                        yy, zz);
+        double Dv = __builtin_huge_val();
+        if (ok) {
+          double S = 0.0, T = 0.0, Lq[SL];
+#pragma unroll
+          for (int q = 0; q < SL; ++q) {
+            const int a = lane + 64 * q;
+            Lq[q] = 0.0;
+            if (a < na) {
+              Lq[q] = lrf64<KIND>(L, a, xx, yy, zz);
+              S += L.g[a] * Lq[q];
+              if (nq[q] > 0.f) T += (double)nq[q] * log(Lq[q] > G.lfloor ? Lq[q] : G.lfloor);
+            }
+          }
+          S = wsum_d(S);
+          if (S > 0.0) {
+            if (STAT == ANTS_STAT_ML) {
+              Dv = N * log(S) - wsum_d(T);
+            } else {
+              const double Aa = N / S;
+              double Q = 0.0;
+#pragma unroll
+              for (int q = 0; q < SL; ++q) {
+                const int a = lane + 64 * q;
+                if (a < na) {
+                  const double mu = Aa * L.g[a] * Lq[q];
+                  const double dd = (double)nq[q] - mu;
+                  Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+                }
+              }
+              Dv = wsum_d(Q);
+            }
+            if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
+          }
+        }
+        Dv = uni(Dv);
+        // candidates come in increasing node index: equal values keep the first
+        if (Dv < bestd) {
+          bestd = Dv;
+          jd = j;
+          tie = false;
+        } else if (Dv == bestd && Dv < __builtin_huge_val()) {
+          tie = true;
+        }
+      }
+      nfp += ncand;
+      win = bestd < __builtin_huge_val() ? jd : -1;
     } else if (ncand > 0) {
       double bestd = __builtin_huge_val();
       int jd = 1 << 30;
@@ -601,7 +684,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           j = cand[base + lane];
           NodeF<KIND> ndd;
           double xx, yy, zz;
-          bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, ndd, xx, yy, zz);
+          bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx, yy, zz);
           if (ok) {
             double S = 0.0, T = 0.0;
             for (int p = 0; p < na; ++p) {
@@ -716,8 +799,13 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   }
 }
 
+// Occupancy target: three waves per SIMD (168 VGPRs) for every variant
+// whose live state fits; the XY kernels with many node tiles keep two.
+template <int KIND, int NT>
+constexpr int waves_per_eu() { return (KIND == ANTS_LRF_XY && NT >= 4) ? 2 : 3; }
+
 template <int KIND, int STAT, int NT, int SL>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>())))
 cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, int btab_n) {
   extern __shared__ float4 smem4[];
   // block-shared table: axial pp tables, or r-z r-polynomials per z-row
@@ -728,6 +816,11 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwb = blockDim.x >> 6;
   unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
+  {
+    int* cand = (int*)(wbase + 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp : 0));
+    fill_nodeidx(G, cand + kMaxNodes, lane0);
+    wave_sync_lds();
+  }
   int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
   for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
     const int64_t e = io.list ? (int64_t)io.list[w] : w;
@@ -741,7 +834,7 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   int btab_n = 0;
   if (KIND == ANTS_LRF_AXIAL) btab_n = L.ntab * L.nintp;
   if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
-  int per_wave = 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp : 0) + 4 * kMaxNodes;
+  int per_wave = 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp : 0) + 8 * kMaxNodes;
   per_wave = (per_wave + 15) & ~15;
   size_t smem = (size_t)btab_n * 16 + (size_t)kWavesPerBlock * per_wave;
   int64_t nwork = io.n;
@@ -785,7 +878,8 @@ hipError_t launch_ks(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t
 // stream is exhausted; every wave leaves the loop once the counter passes
 // the last item.
 template <int KIND, int STAT, int NT, int SL>
-__global__ void __launch_bounds__(256) cg_multi_kernel(MultiP P) {
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>()))) cg_multi_kernel(MultiP P) {
   extern __shared__ float4 smem4[];
   float4* btab = smem4;
   if (P.tab_in_lds) {
@@ -800,6 +894,7 @@ __global__ void __launch_bounds__(256) cg_multi_kernel(MultiP P) {
   const int lane0 = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   unsigned char* wbase = (unsigned char*)(smem4 + P.btab_n) + (size_t)wv * P.per_wave_bytes;
+  int cur_set = -1;
   for (;;) {
     int item = 0;
     if (lane0 == 0) item = atomicAdd(P.counter, 1);
@@ -814,6 +909,13 @@ __global__ void __launch_bounds__(256) cg_multi_kernel(MultiP P) {
     lo = uni(lo);
     const ChunkDesc ch = P.chunks[lo];
     const SetDesc& sd = P.sets[ch.set];
+    if (ch.set != cur_set) {
+      cur_set = ch.set;
+      int* cand = (int*)(wbase + 32 * sd.L.na +
+                         (KIND == ANTS_LRF_RZ ? 16 * sd.G.nz * sd.L.nintp : 0));
+      fill_nodeidx(sd.G, cand + kMaxNodes, lane0);
+      wave_sync_lds();
+    }
     IoP io = P.out;
     io.sig = ch.sig;
     io.ld = sd.L.ns;

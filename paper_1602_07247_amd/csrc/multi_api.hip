@@ -49,7 +49,7 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
     P->max_nn = d.G.nn > P->max_nn ? d.G.nn : P->max_nn;
     P->max_na = d.L.na > P->max_na ? d.L.na : P->max_na;
     int pw = 32 * d.L.na + (d.L.kind == ANTS_LRF_RZ ? 16 * d.G.nz * d.L.nintp : 0) +
-             4 * kMaxNodes;
+             8 * kMaxNodes;
     per_wave = pw > per_wave ? pw : per_wave;
     P->sets.push_back(d);
   }

@@ -48,7 +48,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             sys.stderr.write(f"--- {src}\n{out}\n")
         raise RuntimeError("HIP build failed: " + ", ".join(s for s, _ in failed))
     tmp = LIB + f".tmp{os.getpid()}"
-    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC",
+                           "-Wl,--no-undefined", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     return LIB
 

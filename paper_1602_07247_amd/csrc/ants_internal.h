@@ -30,6 +30,8 @@ struct DevLrf {
   double lo0, hi0, lo1, hi1;
   double d0, d1;       // breakpoint spacing
   float finv0;         // 1/d0 (axial and r-z: lo0 = 0)
+  double inv_d0;       // 1/d0 in FP64 (screen distances are kept in units of d0)
+  int nonneg;          // every FP32 cubic piece is >= 0 on [0, 1] (no clamp needed)
   const int32_t* col;  // [na] column of the active sensor in a signal row
   const int32_t* tab;  // [na] coefficient table of the sensor
   const double* X;     // [na] sensor centre
@@ -116,8 +118,8 @@ struct MultiP {
   int btab_n;
   int tab_in_lds;
 };
-hipError_t launch_multi(const MultiP& P, int kind, int stat, int max_nn, int max_na, int blocks,
-                        hipStream_t s);
+hipError_t launch_multi(const MultiP& P, int kind, int stat, int max_nn, int max_na, bool nonneg,
+                        int blocks, hipStream_t s);
 
 // ------------------------------------------------------------ learned seed
 struct GemmP {

@@ -294,6 +294,33 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
   d.d0 = (d.hi0 - d.lo0) / (nb0 - 1);
   d.d1 = kind == ANTS_LRF_AXIAL ? 1.0 : (d.hi1 - d.lo1) / (nb1 - 1);
   d.finv0 = (float)(1.0 / d.d0);
+  d.inv_d0 = 1.0 / d.d0;
+  // non-negative pieces: the screen can skip the clamp at 0
+  d.nonneg = 0;
+  if (!pp.empty()) {
+    bool nn = true;
+    for (size_t r = 0; r + 3 < pp.size() && nn; r += 4) {
+      const double a0 = pp[r], a1 = pp[r + 1], a2 = pp[r + 2], a3 = pp[r + 3];
+      auto val = [&](double t) { return a0 + t * (a1 + t * (a2 + t * a3)); };
+      double mn = fmin(val(0.0), val(1.0));
+      // stationary points of the cubic in (0, 1)
+      const double A = 3.0 * a3, B = 2.0 * a2, Cc = a1;
+      if (A != 0.0) {
+        const double disc = B * B - 4.0 * A * Cc;
+        if (disc >= 0.0) {
+          const double sq = sqrt(disc);
+          const double t1 = (-B - sq) / (2.0 * A), t2 = (-B + sq) / (2.0 * A);
+          if (t1 > 0.0 && t1 < 1.0) mn = fmin(mn, val(t1));
+          if (t2 > 0.0 && t2 < 1.0) mn = fmin(mn, val(t2));
+        }
+      } else if (B != 0.0) {
+        const double t1 = -Cc / B;
+        if (t1 > 0.0 && t1 < 1.0) mn = fmin(mn, val(t1));
+      }
+      nn = mn >= 0.0;
+    }
+    d.nonneg = nn ? 1 : 0;
+  }
 
   hipError_t e = hipSuccess;
   int32_t *dcol = nullptr, *dtab = nullptr;

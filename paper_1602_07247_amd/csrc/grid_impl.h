@@ -1,0 +1,1003 @@
+// Contracting-grid reconstruction kernel for gfx950 (CDNA4, wave64).
+//
+// Method (arXiv:1602.07247, Sec. 5.1.2.2): per event, a regular grid of
+// nodes centred on the start position; at every node the expected signals
+// come from the sensors' light response functions, the energy is the ratio
+// of the summed signals to the summed LRFs, the match is scored by maximum
+// likelihood or least squares (Sec. 5.1.2), the best node becomes the centre
+// of a finer grid with the same node count, for a fixed number of
+// iterations.  Start: gain-weighted centroid (Sec. 5.1.1) or the strongest
+// sensor (Sec. 5.1.2.1) or a caller seed.  Passive sensors are skipped
+// (Sec. 5.3).
+//
+// Mapping: one wavefront per event, lanes = grid nodes (tiles of 64 nodes),
+// a uniform loop over the event's active sensors.  Per-event sensor records
+// are broadcast from LDS; LRF piecewise-cubic tables sit in LDS (axial and
+// r-z; the r-z table is collapsed along z for the seven z-planes of each
+// iteration so each (node, sensor) pair costs one cubic in r); XY bicubic
+// coefficients are read through the cache.
+//
+// Precision: nodes are first screened in FP32 with the statistic written
+// relative to the current centre (ratios L/L_centre and S/S_centre), which
+// keeps the rounding error proportional to the distance from the centre.
+// A per-iteration bound on that error is computed at the best screened
+// node; every node whose screened value lies within the bound of the best
+// is re-evaluated in FP64 (the vector FP64 rate equals the unpacked FP32
+// rate on this chip), and the FP64 values decide.  Ties in FP64 go to the
+// lowest node index.
+#pragma once
+
+#include <math.h>
+
+#include "ants_internal.h"
+#include "lrf64.h"
+
+namespace ants {
+namespace {
+
+constexpr float kU = 5.9604645e-8f;  // unit roundoff of FP32
+constexpr float kInf = __builtin_huge_valf();
+constexpr float kLog2e = 1.4426950408889634f;
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ double wsum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ float wsum_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+// lexicographic minimum of (value, index) over the wave
+__device__ __forceinline__ void wargmin_f(float& v, int& j) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    float v2 = __shfl_xor(v, o);
+    int j2 = __shfl_xor(j, o);
+    if (v2 < v || (v2 == v && j2 < j)) { v = v2; j = j2; }
+  }
+}
+__device__ __forceinline__ void wargmin_d(double& v, int& j) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    double v2 = __shfl_xor(v, o);
+    int j2 = __shfl_xor(j, o);
+    if (v2 < v || (v2 == v && j2 < j)) { v = v2; j = j2; }
+  }
+}
+// lexicographic maximum of (value, -index): strongest sensor, lowest index
+__device__ __forceinline__ void wargmax_f(float& v, int& j) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    float v2 = __shfl_xor(v, o);
+    int j2 = __shfl_xor(j, o);
+    if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
+  }
+}
+__device__ __forceinline__ int prefix_count(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+// values equal in every lane, moved to scalar registers
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uni(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_readfirstlane(p.x);
+  p.y = __builtin_amdgcn_readfirstlane(p.y);
+  return __builtin_bit_cast(double, p);
+}
+// An opaque copy of a value: stops the compiler from hoisting per-lane
+// set-up work out of the event loop and pinning it in registers for the
+// whole kernel (it is cheaper to recompute than to keep).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// --------------------------------------------------- FP32 screening LRF
+
+// Per-lane description of one node for the FP32 screen.
+template <int KIND>
+struct NodeF {
+  float ox, oy;          // offset from the centre (axial, r-z)
+  const float4* tab;     // r-z: this node's z-plane table (LDS)
+};
+template <>
+struct NodeF<ANTS_LRF_XY> {
+  int cell;              // my * nc0 + mx
+  float w[16];           // wy[a] * wx[b]
+};
+
+// Sensor record broadcast from LDS: A = {dX, dY, n, 1/L_c}, B = {g, L_c, table offset, a}
+template <int KIND, bool NN>
+__device__ __forceinline__ float lrf32(const NodeF<KIND>& nd, float dX, float dY, int tofs,
+                                       const float4* btab, const float* c32, int nc0,
+                                       float finv, int nlast) {
+  if constexpr (KIND == ANTS_LRF_XY) {
+    typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+    const float* p = c32 + tofs + nd.cell;
+    f4u r0 = *(const f4u*)(p);
+    f4u r1 = *(const f4u*)(p + nc0);
+    f4u r2 = *(const f4u*)(p + 2 * nc0);
+    f4u r3 = *(const f4u*)(p + 3 * nc0);
+    float v = nd.w[0] * r0.x;
+    v = fmaf(nd.w[1], r0.y, v);
+    v = fmaf(nd.w[2], r0.z, v);
+    v = fmaf(nd.w[3], r0.w, v);
+    v = fmaf(nd.w[4], r1.x, v);
+    v = fmaf(nd.w[5], r1.y, v);
+    v = fmaf(nd.w[6], r1.z, v);
+    v = fmaf(nd.w[7], r1.w, v);
+    v = fmaf(nd.w[8], r2.x, v);
+    v = fmaf(nd.w[9], r2.y, v);
+    v = fmaf(nd.w[10], r2.z, v);
+    v = fmaf(nd.w[11], r2.w, v);
+    v = fmaf(nd.w[12], r3.x, v);
+    v = fmaf(nd.w[13], r3.y, v);
+    v = fmaf(nd.w[14], r3.z, v);
+    v = fmaf(nd.w[15], r3.w, v);
+    return fmaxf(v, 0.f);
+  } else {
+    // offsets are in units of the breakpoint spacing: v = r / d0
+    float dx = nd.ox - dX, dy = nd.oy - dY;
+    float r2 = fmaf(dx, dx, dy * dy);
+    float v = __builtin_amdgcn_sqrtf(r2);
+    int m = (int)fminf(v, (float)nlast);
+    float t = __builtin_amdgcn_fractf(v);
+    const float4* T;
+    if constexpr (KIND == ANTS_LRF_RZ) T = nd.tab;
+    else T = btab + tofs;
+    float4 c = T[m];
+    float p = fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
+    return NN ? p : fmaxf(p, 0.f);
+  }
+}
+
+// Node j of the current grid: FP64 position, FP32 screen description and
+// validity (nodes whose z, or XY position, leave the LRF domain have S = 0).
+// Node index -> (jx, jy, jz) packed as jx | jy << 10 | jz << 20, one entry
+// per node of the current grid (avoids integer division in the loops).
+__device__ __forceinline__ void fill_nodeidx(const GridP& G, int* tab, int lane) {
+  for (int j = lane; j < kMaxNodes; j += 64) {
+    int v = 0;
+    if (j < G.nn) {
+      const int jx = j % G.nx, jy = (j / G.nx) % G.ny, jz = j / (G.nx * G.ny);
+      v = jx | (jy << 10) | (jz << 20);
+    }
+    tab[j] = v;
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ bool make_node(const DevLrf& L, const GridP& G, double cx, double cy,
+                                          double cz, double sx, double sy, double sz, int j,
+                                          const float4* ztab, const int* nodeidx,
+                                          NodeF<KIND>& nd, double& x, double& y, double& z) {
+  const int packed = nodeidx[j];
+  const int jx = packed & 1023, jy = (packed >> 10) & 1023, jz = packed >> 20;
+  double ox = (double)(jx - G.hx) * sx;
+  double oy = (double)(jy - G.hy) * sy;
+  double oz = (double)(jz - G.hz) * sz;
+  x = cx + ox;
+  y = cy + oy;
+  z = cz + oz;
+  bool valid = j < G.nn;
+  if constexpr (KIND != ANTS_LRF_XY) {
+    nd.ox = (float)(ox * L.inv_d0);
+    nd.oy = (float)(oy * L.inv_d0);
+  }
+  if constexpr (KIND == ANTS_LRF_RZ) {
+    int jzc = jz < G.nz ? jz : G.nz - 1;
+    nd.tab = ztab + jzc * L.nintp;
+    valid = valid && in_domain(z, L.lo1, L.hi1);
+  }
+  if constexpr (KIND == ANTS_LRF_XY) {
+    int m0 = 0, m1 = 0;
+    double t0 = 0.0, t1 = 0.0, b0[4], b1[4];
+    bool in0 = locate64(x, L.nb0, L.lo0, L.hi0, L.d0, m0, t0);
+    bool in1 = locate64(y, L.nb1, L.lo1, L.hi1, L.d1, m1, t1);
+    valid = valid && in0 && in1;
+    bweights64(t0, b0);
+    bweights64(t1, b1);
+    nd.cell = m1 * L.nc0 + m0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) nd.w[a * 4 + b] = (float)(b1[a] * b0[b]);
+  }
+  return valid;
+}
+
+// log2(1 + x) with small relative error for small |x| (per node only)
+__device__ __forceinline__ float log2_1p(float x) {
+  float u = 1.0f + x;
+  float d = u - 1.0f;
+  return d == 0.0f ? x * kLog2e : __builtin_amdgcn_logf(u) * (x / d);
+}
+
+// --------------------------------------------------------------- kernel
+
+// One event on one wavefront.  btab: block-shared tables (LDS); wbase: this
+// wave's LDS region (sensor records, r-z plane tables, candidate list).
+template <int KIND, int STAT, int NT, int SL, bool NN>
+__device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, const IoP& io,
+                                              const int64_t e, const float4* btab,
+                                              unsigned char* wbase, const int lane) {
+  float4* recA = (float4*)wbase;
+  float4* recB = recA + L.na;
+  float4* ztab = recB + L.na;
+  int* cand = (int*)(ztab + (KIND == ANTS_LRF_RZ ? G.nz * L.nintp : 0));
+  const int* nodeidx = cand + kMaxNodes;
+  const int na = L.na;
+  const int nlast = L.nintp - 1;
+  const float finv = L.finv0;
+  const float flf = (float)G.lfloor;
+  const float fvf = (float)G.vfloor;
+  const float* row = io.sig + e * io.ld;
+
+  // ---------------- event set-up: signals of the active sensors
+  float nq[SL];
+  int posq[SL];
+  double N = 0.0, cw = 0.0, cxs = 0.0, cys = 0.0;
+  bool bad = false;
+  float best_n = -1.0f;
+  int best_a = 1 << 30;
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    int a = lane + 64 * q;
+    nq[q] = 0.f;
+    if (a < na) {
+      float n = row[L.col[a]];
+      nq[q] = n;
+      if (!(n >= 0.f) || !(n < kInf)) {
+        bad = true;
+      } else {
+        double wgt = (double)n / L.g[a];
+        N += (double)n;
+        cw += wgt;
+        cxs += L.X[a] * wgt;
+        cys += L.Y[a] * wgt;
+        if (n > best_n) { best_n = n; best_a = a; }
+      }
+    }
+  }
+  bool any_bad = __ballot(bad) != 0ull;
+  N = uni(wsum_d(N));
+  const int ndf = na - (G.dim + 1);
+  int status = 0;
+  if (na == 0) status = ANTS_EV_NO_ACTIVE;
+  else if (any_bad) status = ANTS_EV_BAD_INPUT;
+  else if (!(N > 0.0)) status = ANTS_EV_EMPTY;
+  if (status) {
+    if (lane == 0) {
+      float nan = __builtin_nanf("");
+      io.x[e] = nan; io.y[e] = nan; io.z[e] = nan; io.E[e] = nan;
+      io.lnl[e] = nan; io.chi2[e] = nan; io.ndf[e] = ndf; io.status[e] = status;
+      if (io.nfp) io.nfp[e] = 0;
+    }
+    if (io.path && lane < G.K) io.path[e * G.K + lane] = -1;
+    return;
+  }
+  cw = wsum_d(cw);
+  cxs = wsum_d(cxs);
+  cys = wsum_d(cys);
+
+  double cx, cy, cz = G.z_start;
+  if (G.start == ANTS_START_SEED && io.seeds) {
+    cx = io.seeds[e * 4 + 0];
+    cy = io.seeds[e * 4 + 1];
+    if (G.dim == 3) cz = io.seeds[e * 4 + 2];
+  } else if (G.start == ANTS_START_MAXSENSOR) {
+    wargmax_f(best_n, best_a);
+    best_a = uni(best_a);
+    cx = L.X[best_a];
+    cy = L.Y[best_a];
+  } else {
+    cx = cxs / cw;
+    cy = cys / cw;
+  }
+  cx = uni(cx);
+  cy = uni(cy);
+  cz = uni(cz);
+
+  // sensor records in LDS: sensors with n > 0 first, then n == 0
+  int npos = 0;
+  {
+    uint64_t mpos[SL], mzero[SL];
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      int a = lane + 64 * q;
+      mpos[q] = __ballot(a < na && nq[q] > 0.f);
+      mzero[q] = __ballot(a < na && !(nq[q] > 0.f));
+      npos += __popcll(mpos[q]);
+    }
+    int bp = 0, bz = npos;
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      posq[q] = nq[q] > 0.f ? bp + prefix_count(mpos[q]) : bz + prefix_count(mzero[q]);
+      bp += __popcll(mpos[q]);
+      bz += __popcll(mzero[q]);
+    }
+  }
+  const float N32 = (float)N;
+
+  double sx = G.s0x, sy = G.s0y, sz = G.s0z;
+  int Kev = G.K;
+  if (G.seed_steps && io.seeds) {
+    // steps from the seed's predicted spread: the smallest iteration count
+    // in [kmin, kmax] whose first step covers kappa * sigma on every axis,
+    // ending on the configured final step
+    const double lv = io.seeds[e * 4 + 3];
+    const double sg = exp(0.5 * lv) * G.kappa;
+    double s3[3] = {G.sfinal[0], G.sfinal[1], G.sfinal[2]};
+    const int nn3[3] = {G.nx, G.ny, G.nz};
+    int kk = 0;
+    for (; kk < G.kmin - 1; ++kk)
+      for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+    if (!(sg < __builtin_huge_val())) {
+      for (; kk < G.kmax - 1; ++kk)
+        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+    } else {
+      for (;;) {
+        bool short_ = false;
+        for (int a = 0; a < 3; ++a)
+          if (nn3[a] > 1 && s3[a] < sg * G.sscale[a]) short_ = true;
+        if (!short_ || kk >= G.kmax - 1) break;
+        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+        ++kk;
+      }
+    }
+    Kev = uni(kk + 1);
+    sx = uni(G.nx > 1 ? s3[0] : 0.0);
+    sy = uni(G.ny > 1 ? s3[1] : 0.0);
+    sz = uni(G.nz > 1 ? s3[2] : 0.0);
+  }
+  int nfp = 0;
+  for (int k = 0; k < Kev; ++k) {
+    const int lk = opaque(lane);
+    // ---- r-z: collapse the table along z for this iteration's planes
+    if constexpr (KIND == ANTS_LRF_RZ) {
+      // plane weights once per plane (the candidate list area is free here)
+      float4* pw = (float4*)cand;
+      int* pm = cand + 4 * G.nz;
+      for (int jz = lane; jz < G.nz; jz += 64) {
+        const double zz = cz + (double)(jz - G.hz) * sz;
+        int mz;
+        double tz, bz[4];
+        if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
+          bweights64(tz, bz);
+          pw[jz] = make_float4((float)bz[0], (float)bz[1], (float)bz[2], (float)bz[3]);
+          pm[jz] = mz;
+        } else {
+          pw[jz] = make_float4(0.f, 0.f, 0.f, 0.f);
+          pm[jz] = 0;
+        }
+      }
+      wave_sync_lds();
+      const int ntot = G.nz * L.nintp;
+      const float inv_nintp = 1.0f / (float)L.nintp;
+      for (int i = lane; i < ntot; i += 64) {
+        const int jz = (int)(((float)i + 0.5f) * inv_nintp);
+        const int m = i - jz * L.nintp;
+        const float4 w = pw[jz];
+        const float4* P = btab + pm[jz] * L.nintp + m;
+        const float4 P0 = P[0], P1 = P[L.nintp], P2 = P[2 * L.nintp], P3 = P[3 * L.nintp];
+        float4 acc;
+        acc.x = fmaf(w.w, P3.x, fmaf(w.z, P2.x, fmaf(w.y, P1.x, w.x * P0.x)));
+        acc.y = fmaf(w.w, P3.y, fmaf(w.z, P2.y, fmaf(w.y, P1.y, w.x * P0.y)));
+        acc.z = fmaf(w.w, P3.z, fmaf(w.z, P2.z, fmaf(w.y, P1.z, w.x * P0.z)));
+        acc.w = fmaf(w.w, P3.w, fmaf(w.z, P2.w, fmaf(w.y, P1.w, w.x * P0.w)));
+        ztab[i] = acc;
+      }
+      wave_sync_lds();
+    }
+
+    // ---- reference at the centre, per sensor (lane-parallel)
+    NodeF<KIND> ndc;
+    {
+      double xx, yy, zz;
+      int jc = (G.hz * G.ny + G.hy) * G.nx + G.hx;
+      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jc, ztab, nodeidx, ndc, xx, yy, zz);
+    }
+    float Sc = 0.f;
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      int a = lane + 64 * q;
+      if (a < na) {
+        float dX = (float)((L.X[a] - cx) * L.inv_d0),
+              dY = (float)((L.Y[a] - cy) * L.inv_d0);
+        int tofs = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
+        float Lc = lrf32<KIND, NN>(ndc, dX, dY, tofs, btab, L.c32, L.nc0, finv, nlast);
+        float g = (float)L.g[a];
+        Sc = fmaf(g, Lc, Sc);
+        recA[posq[q]] = make_float4(dX, dY, nq[q], 1.0f / fmaxf(Lc, flf));
+        recB[posq[q]] = make_float4(g, Lc, __int_as_float(tofs), __int_as_float(a));
+      }
+    }
+    Sc = uni(wsum_f(Sc));
+    const bool rel = Sc > 0.f;   // centre-relative form available
+    if (!rel) {
+      // absolute form: L_c = 0 and 1/L_c = 1 make dS = S and the log terms absolute
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        int a = lane + 64 * q;
+        if (a < na) {
+          recA[posq[q]].w = 1.f;
+          recB[posq[q]].y = 0.f;
+        }
+      }
+    }
+    const float iSc = rel ? 1.0f / Sc : 1.0f;
+    wave_sync_lds();
+
+    // ---- node set-up
+    NodeF<KIND> nd[NT];
+    bool valid[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double xx, yy, zz;
+      valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, t * 64 + lk, ztab, nodeidx, nd[t], xx,
+                                 yy, zz);
+    }
+
+    // ---- FP32 screen
+    float D[NT], Snode[NT];
+    if constexpr (STAT == ANTS_STAT_ML) {
+      float dS[NT], T[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { dS[t] = 0.f; T[t] = 0.f; }
+      for (int p = 0; p < npos; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+          T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
+        }
+      }
+      for (int p = npos; p < na; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        float S = rel ? Sc + dS[t] : dS[t];
+        float lS = rel ? log2_1p(dS[t] * iSc) : __builtin_amdgcn_logf(dS[t]);
+        float d = N32 * lS - T[t];
+        // a sensor with counts where the screened LRF is 0 (or a rounding
+        // hole) makes d infinite or NaN: such nodes go to FP64, untrusted
+        const bool fin = d < kInf && d > -kInf;
+        const bool live = valid[t] && S > 0.f;
+        D[t] = (live && fin) ? d : kInf;
+        Snode[t] = (live && !fin) ? -1.0f : S;
+      }
+    } else {
+      float S[NT], Q[NT], Ag[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { S[t] = 0.f; Q[t] = 0.f; }
+      for (int p = 0; p < na; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          S[t] = fmaf(B.x, Lv, S[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) Ag[t] = S[t] > 0.f ? N32 / S[t] : 0.f;
+      for (int p = 0; p < na; ++p) {
+        float4 A = recA[p], B = recB[p];
+        int tofs = __float_as_int(B.z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          float mu = Ag[t] * B.x * Lv;
+          float dd = A.z - mu;
+          float v = fmaxf(mu, fvf);
+          Q[t] = fmaf(dd * dd, __builtin_amdgcn_rcpf(v), Q[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        Snode[t] = S[t];
+        D[t] = (valid[t] && S[t] > 0.f && Q[t] < kInf) ? Q[t] : kInf;
+      }
+    }
+
+    // ---- trusted screen values; best screened node
+    // (centre-relative ML values of nodes with S far below S_c suffer
+    //  cancellation; such nodes are always re-decided in FP64)
+    bool trusted[NT];
+    float best = kInf;
+    int jb = 1 << 30;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      trusted[t] = (STAT == ANTS_STAT_ML && rel) ? (Snode[t] >= 0.01f * Sc)
+                   : (STAT == ANTS_STAT_ML) ? !(Snode[t] < 0.f) : true;
+      float v = trusted[t] ? D[t] : kInf;
+      int j = t * 64 + lane;
+      if (v < best || (v == best && j < jb)) { best = v; jb = j; }
+    }
+    wargmin_f(best, jb);
+    best = uni(best);
+    jb = uni(jb);
+
+    // ---- error bound of the screen at the best node (lane-parallel over sensors)
+    float margin = 0.f;
+    if (best < kInf) {
+      NodeF<KIND> ndb;
+      double xx, yy, zz;
+      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, nodeidx, ndb, xx, yy, zz);
+      float Lb[SL];
+      float4 RA[SL], RB[SL];
+      float Sb = 0.f;
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        int a = lane + 64 * q;
+        Lb[q] = 0.f;
+        RA[q] = make_float4(0.f, 0.f, 0.f, 1.f);
+        RB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (a < na) {
+          RA[q] = recA[posq[q]];
+          RB[q] = recB[posq[q]];
+          Lb[q] = lrf32<KIND, NN>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab, L.c32,
+                              L.nc0, finv, nlast);
+          Sb = fmaf(RB[q].x, Lb[q], Sb);
+        }
+      }
+      Sb = wsum_f(Sb);
+      if (STAT == ANTS_STAT_ML) {
+        float A1 = 0.f, A2 = 0.f, A3 = 0.f;
+        float iSb = Sb > 0.f ? 1.0f / Sb : 0.f;
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+          int a = lane + 64 * q;
+          if (a < na) {
+            float mu = N32 * RB[q].x * Lb[q] * iSb;
+            A1 += fabsf(mu - RA[q].z);
+            A2 += fabsf(RA[q].z * __builtin_amdgcn_logf(fmaxf(Lb[q], flf) * RA[q].w));
+            A3 += RB[q].x * fabsf(Lb[q] - RB[q].y);
+          }
+        }
+        A1 = wsum_f(A1);
+        A2 = wsum_f(A2);
+        A3 = wsum_f(A3);
+        float lsr = (rel && Sb > 0.f) ? fabsf(__builtin_amdgcn_logf(Sb * iSc)) : 0.f;
+        float E = kU * (kLog2e * (24.f * A1 + 2.f * N32 + (float)(na + 2) * N32 * A3 * iSb) +
+                        (float)(na + 4) * A2 + 4.f * N32 * lsr);
+        margin = 4.f * G.margin_scale * E;
+      } else {
+        float A1 = 0.f;
+        float Ab = Sb > 0.f ? N32 / Sb : 0.f;
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+          int a = lane + 64 * q;
+          if (a < na) {
+            float mu = Ab * RB[q].x * Lb[q];
+            float dd = RA[q].z - mu;
+            float v = fmaxf(mu, fvf);
+            A1 += 2.f * fabsf(dd) + dd * dd / v;
+          }
+        }
+        A1 = wsum_f(A1);
+        float E = kU * (float)(24 + na + 4) * A1;
+        margin = 4.f * G.margin_scale * E;
+      }
+      margin = uni(margin);
+      if (!(margin < kInf)) margin = kInf;
+    }
+
+    // ---- candidates: trusted nodes within the bound, and untrusted valid nodes
+    int ncand = 0;
+    bool only_trusted = true;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bool c = trusted[t] ? (D[t] < kInf && D[t] <= best + margin)
+                          : (valid[t] && Snode[t] > -kInf);
+      uint64_t m = __ballot(c);
+      if (c) cand[ncand + prefix_count(m)] = t * 64 + lane;
+      ncand += __popcll(m);
+      if (__ballot(c && !trusted[t])) only_trusted = false;
+    }
+    wave_sync_lds();
+
+    int win = -1;
+    bool tie = false;
+    // lanes over sensors, one candidate at a time, when that is cheaper
+    const int serial_max = (na * 5) / (SL * 5 + 2);
+    if (ncand == 1 && only_trusted) {
+      win = jb;
+    } else if (ncand > 0 && ncand <= serial_max) {
+      double bestd = __builtin_huge_val();
+      int jd = 1 << 30;
+      for (int c = 0; c < ncand; ++c) {
+        const int j = uni(cand[c]);
+        NodeF<KIND> ndd;
+        double xx, yy, zz;
+        const bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx,
+                                        yy, zz);
+        double Dv = __builtin_huge_val();
+        if (ok) {
+          double S = 0.0, T = 0.0, Lq[SL];
+#pragma unroll
+          for (int q = 0; q < SL; ++q) {
+            const int a = lane + 64 * q;
+            Lq[q] = 0.0;
+            if (a < na) {
+              Lq[q] = lrf64<KIND>(L, a, xx, yy, zz);
+              S += L.g[a] * Lq[q];
+              if (nq[q] > 0.f) T += (double)nq[q] * log(Lq[q] > G.lfloor ? Lq[q] : G.lfloor);
+            }
+          }
+          S = wsum_d(S);
+          if (S > 0.0) {
+            if (STAT == ANTS_STAT_ML) {
+              Dv = N * log(S) - wsum_d(T);
+            } else {
+              const double Aa = N / S;
+              double Q = 0.0;
+#pragma unroll
+              for (int q = 0; q < SL; ++q) {
+                const int a = lane + 64 * q;
+                if (a < na) {
+                  const double mu = Aa * L.g[a] * Lq[q];
+                  const double dd = (double)nq[q] - mu;
+                  Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+                }
+              }
+              Dv = wsum_d(Q);
+            }
+            if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
+          }
+        }
+        Dv = uni(Dv);
+        // candidates come in increasing node index: equal values keep the first
+        if (Dv < bestd) {
+          bestd = Dv;
+          jd = j;
+          tie = false;
+        } else if (Dv == bestd && Dv < __builtin_huge_val()) {
+          tie = true;
+        }
+      }
+      nfp += ncand;
+      win = bestd < __builtin_huge_val() ? jd : -1;
+    } else if (ncand > 0) {
+      double bestd = __builtin_huge_val();
+      int jd = 1 << 30;
+      for (int base = 0; base < ncand; base += 64) {
+        double Dv = __builtin_huge_val();
+        int j = 1 << 30;
+        if (base + lane < ncand) {
+          j = cand[base + lane];
+          NodeF<KIND> ndd;
+          double xx, yy, zz;
+          bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx, yy, zz);
+          if (ok) {
+            double S = 0.0, T = 0.0;
+            for (int p = 0; p < na; ++p) {
+              float4 A = recA[p];
+              int a = __float_as_int(recB[p].w);
+              double Lv = lrf64<KIND>(L, a, xx, yy, zz);
+              S += L.g[a] * Lv;
+              if (A.z > 0.f) T += (double)A.z * log(Lv > G.lfloor ? Lv : G.lfloor);
+            }
+            if (S > 0.0) {
+              if (STAT == ANTS_STAT_ML) {
+                Dv = N * log(S) - T;
+              } else {
+                double Aa = N / S, Q = 0.0;
+                for (int p = 0; p < na; ++p) {
+                  float4 A = recA[p];
+                  int a = __float_as_int(recB[p].w);
+                  double mu = Aa * L.g[a] * lrf64<KIND>(L, a, xx, yy, zz);
+                  double dd = (double)A.z - mu;
+                  Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+                }
+                Dv = Q;
+              }
+              if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
+            }
+          }
+        }
+        double v1 = Dv;
+        int j1 = j;
+        wargmin_d(v1, j1);
+        const bool fin = v1 < __builtin_huge_val();
+        // candidates are listed in increasing node index, so an earlier
+        // chunk's winner keeps priority on equal values
+        int nsame = __popcll(__ballot(fin && Dv == v1));
+        if (v1 < bestd) {
+          bestd = v1;
+          jd = j1;
+          tie = nsame > 1;
+        } else if (fin && v1 == bestd) {
+          tie = true;
+        }
+      }
+      nfp += ncand;
+      win = bestd < __builtin_huge_val() ? jd : -1;
+      win = uni(win);
+    }
+    if (io.path && lane == 0 && k < G.K) io.path[e * G.K + k] = win;
+    if (win < 0) {
+      status |= ANTS_EV_NO_VALID_NODE;
+    } else {
+      if (tie) status |= ANTS_EV_TIE;
+      int jx = win % G.nx, jy = (win / G.nx) % G.ny, jz = win / (G.nx * G.ny);
+      cx = uni(cx + (double)(jx - G.hx) * sx);
+      cy = uni(cy + (double)(jy - G.hy) * sy);
+      cz = uni(cz + (double)(jz - G.hz) * sz);
+    }
+    sx = uni(sx * G.shrink);
+    sy = uni(sy * G.shrink);
+    sz = uni(sz * G.shrink);
+    wave_sync_lds();
+  }
+
+  // ---------------- outputs at the final centre, FP64, lane-parallel over sensors
+  double S = 0.0;
+  double Lf[SL];
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    int a = lane + 64 * q;
+    Lf[q] = 0.0;
+    if (a < na) {
+      Lf[q] = lrf64<KIND>(L, a, cx, cy, cz);
+      S += L.g[a] * Lf[q];
+    }
+  }
+  S = wsum_d(S);
+  double Aa = N / S, ll = 0.0, q2 = 0.0;
+  bool okS = S > 0.0 && S < __builtin_huge_val();
+  if (okS) {
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      int a = lane + 64 * q;
+      if (a < na) {
+        double mu = Aa * L.g[a] * Lf[q];
+        double Lt = Lf[q] > G.lfloor ? Lf[q] : G.lfloor;
+        double n = (double)nq[q];
+        if (n > 0.0) ll += n * log(Aa * L.g[a] * Lt);
+        ll -= mu;
+        double dd = n - mu;
+        q2 += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+      }
+    }
+    ll = wsum_d(ll);
+    q2 = wsum_d(q2);
+  }
+  if (io.path && Kev < G.K && lane >= Kev && lane < G.K) io.path[e * G.K + lane] = -1;
+  status |= G.or_status;
+  if (lane == 0) {
+    if (G.fb_thr > 0.0 && !(okS && ndf > 0 && q2 / ndf <= G.fb_thr)) {
+      int slot = atomicAdd(io.fb_count, 1);
+      io.fb_list[slot] = (int32_t)e;
+    }
+    float nan = __builtin_nanf("");
+    io.x[e] = (float)cx;
+    io.y[e] = (float)cy;
+    io.z[e] = (float)cz;
+    io.E[e] = okS ? (float)Aa : nan;
+    io.lnl[e] = okS ? (float)ll : nan;
+    io.chi2[e] = okS ? (float)q2 : nan;
+    io.ndf[e] = ndf;
+    io.status[e] = status;
+    if (io.nfp) io.nfp[e] = nfp;
+  }
+}
+
+// Occupancy target: three waves per SIMD (168 VGPRs) for every variant
+// whose live state fits; the XY kernels with many node tiles keep two.
+template <int KIND, int NT>
+constexpr int waves_per_eu() { return (KIND == ANTS_LRF_XY && NT >= 4) ? 2 : 3; }
+
+template <int KIND, int STAT, int NT, int SL, bool NN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>())))
+cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, int btab_n) {
+  extern __shared__ float4 smem4[];
+  // block-shared table: axial pp tables, or r-z r-polynomials per z-row
+  float4* btab = smem4;
+  for (int i = threadIdx.x; i < btab_n; i += blockDim.x) btab[i] = ((const float4*)L.pp)[i];
+  __syncthreads();
+  const int lane0 = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nwb = blockDim.x >> 6;
+  unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
+  {
+    int* cand = (int*)(wbase + 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp : 0));
+    fill_nodeidx(G, cand + kMaxNodes, lane0);
+    wave_sync_lds();
+  }
+  int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
+  for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
+    const int64_t e = io.list ? (int64_t)io.list[w] : w;
+    process_event<KIND, STAT, NT, SL, NN>(L, G, io, e, btab, wbase, opaque(lane0));
+  }
+}
+
+template <int KIND, int STAT, int NT, int SL, bool NN>
+hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t stream,
+                    int max_blocks) {
+  int btab_n = 0;
+  if (KIND == ANTS_LRF_AXIAL) btab_n = L.ntab * L.nintp;
+  if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
+  int per_wave = 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp : 0) + 8 * kMaxNodes;
+  per_wave = (per_wave + 15) & ~15;
+  size_t smem = (size_t)btab_n * 16 + (size_t)kWavesPerBlock * per_wave;
+  int64_t nwork = io.n;
+  int64_t blocks = (nwork + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
+  auto kern = cg_kernel<KIND, STAT, NT, SL, NN>;
+  if (smem > 65536) {
+    hipError_t st = hipFuncSetAttribute((const void*)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (st != hipSuccess) return st;
+  }
+  int64_t waves_total = blocks * kWavesPerBlock;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), smem, stream, L, G,
+                     io, waves_total, per_wave, btab_n);
+  return hipGetLastError();
+}
+
+template <int KIND, int STAT, int SL, bool NN>
+hipError_t launch_kss(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
+  int nt = (G.nn + 63) / 64;
+  if (nt <= 1) return launch_t<KIND, STAT, 1, SL, NN>(L, G, io, s, mb);
+  if (nt <= 2) return launch_t<KIND, STAT, 2, SL, NN>(L, G, io, s, mb);
+  if (nt <= 4) return launch_t<KIND, STAT, 4, SL, NN>(L, G, io, s, mb);
+  if (nt <= 6) return launch_t<KIND, STAT, 6, SL, NN>(L, G, io, s, mb);
+  return launch_t<KIND, STAT, 8, SL, NN>(L, G, io, s, mb);
+}
+
+template <int KIND, int STAT, bool NN>
+hipError_t launch_ksn(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
+  if (L.na <= 64) return launch_kss<KIND, STAT, 1, NN>(L, G, io, s, mb);
+  if (L.na <= 128) return launch_kss<KIND, STAT, 2, NN>(L, G, io, s, mb);
+  return launch_kss<KIND, STAT, 4, NN>(L, G, io, s, mb);
+}
+
+template <int KIND, int STAT>
+hipError_t launch_ks(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
+  if (KIND != ANTS_LRF_XY && L.nonneg) return launch_ksn<KIND, STAT, true>(L, G, io, s, mb);
+  return launch_ksn<KIND, STAT, false>(L, G, io, s, mb);
+}
+
+
+// ------------------------------------------------- persistent multi-detector
+
+// One launch over event chunks from several detectors (LRF sets): waves pull
+// work items (chunk, tile of `T` events) from a device counter until the
+// stream is exhausted; every wave leaves the loop once the counter passes
+// the last item.
+template <int KIND, int STAT, int NT, int SL, bool NN>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>()))) cg_multi_kernel(MultiP P) {
+  extern __shared__ float4 smem4[];
+  float4* btab = smem4;
+  if (P.tab_in_lds) {
+    for (int si = 0; si < P.n_sets; ++si) {
+      const DevLrf& L = P.sets[si].L;
+      const int n = KIND == ANTS_LRF_AXIAL ? L.ntab * L.nintp : KIND == ANTS_LRF_RZ ? L.nc1 * L.nintp : 0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x)
+        btab[P.sets[si].tab_off + i] = ((const float4*)L.pp)[i];
+    }
+  }
+  __syncthreads();
+  const int lane0 = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* wbase = (unsigned char*)(smem4 + P.btab_n) + (size_t)wv * P.per_wave_bytes;
+  int cur_set = -1;
+  for (;;) {
+    int item = 0;
+    if (lane0 == 0) item = atomicAdd(P.counter, 1);
+    item = uni(__shfl(item, 0));
+    if (item >= P.n_items) break;
+    int lo = 0, hi = P.n_chunks;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (P.prefix[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    lo = uni(lo);
+    const ChunkDesc ch = P.chunks[lo];
+    const SetDesc& sd = P.sets[ch.set];
+    if (ch.set != cur_set) {
+      cur_set = ch.set;
+      int* cand = (int*)(wbase + 32 * sd.L.na +
+                         (KIND == ANTS_LRF_RZ ? 16 * sd.G.nz * sd.L.nintp : 0));
+      fill_nodeidx(sd.G, cand + kMaxNodes, lane0);
+      wave_sync_lds();
+    }
+    IoP io = P.out;
+    io.sig = ch.sig;
+    io.ld = sd.L.ns;
+    io.n = ch.n;
+    io.x += ch.out_off;
+    io.y += ch.out_off;
+    io.z += ch.out_off;
+    io.E += ch.out_off;
+    io.lnl += ch.out_off;
+    io.chi2 += ch.out_off;
+    io.ndf += ch.out_off;
+    io.status += ch.out_off;
+    const float4* tb = P.tab_in_lds ? btab + sd.tab_off : (const float4*)sd.L.pp;
+    const int64_t e0 = (int64_t)(item - P.prefix[lo]) * P.T;
+    const int64_t e1 = e0 + P.T < ch.n ? e0 + P.T : ch.n;
+    for (int64_t e = e0; e < e1; ++e)
+      process_event<KIND, STAT, NT, SL, NN>(sd.L, sd.G, io, e, tb, wbase, opaque(lane0));
+  }
+}
+
+template <int KIND, int STAT, int NT, int SL, bool NN>
+hipError_t launch_multi_t(const MultiP& P, int blocks, hipStream_t stream) {
+  size_t smem = (size_t)P.btab_n * 16 + (size_t)kWavesPerBlock * P.per_wave_bytes;
+  auto kern = cg_multi_kernel<KIND, STAT, NT, SL, NN>;
+  if (smem > 65536) {
+    hipError_t st = hipFuncSetAttribute((const void*)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (st != hipSuccess) return st;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), smem, stream, P);
+  return hipGetLastError();
+}
+
+template <int KIND, int STAT, int SL, bool NN>
+hipError_t launch_multi_ks(const MultiP& P, int nn, int blocks, hipStream_t s) {
+  int nt = (nn + 63) / 64;
+  if (nt <= 1) return launch_multi_t<KIND, STAT, 1, SL, NN>(P, blocks, s);
+  if (nt <= 2) return launch_multi_t<KIND, STAT, 2, SL, NN>(P, blocks, s);
+  if (nt <= 4) return launch_multi_t<KIND, STAT, 4, SL, NN>(P, blocks, s);
+  if (nt <= 6) return launch_multi_t<KIND, STAT, 6, SL, NN>(P, blocks, s);
+  return launch_multi_t<KIND, STAT, 8, SL, NN>(P, blocks, s);
+}
+
+template <int KIND, int STAT, bool NN>
+hipError_t launch_multi_kn(const MultiP& P, int nn, int na, int blocks, hipStream_t s) {
+  if (na <= 64) return launch_multi_ks<KIND, STAT, 1, NN>(P, nn, blocks, s);
+  if (na <= 128) return launch_multi_ks<KIND, STAT, 2, NN>(P, nn, blocks, s);
+  return launch_multi_ks<KIND, STAT, 4, NN>(P, nn, blocks, s);
+}
+
+template <int KIND>
+hipError_t launch_multi_k(const MultiP& P, int stat, int nn, int na, bool nonneg, int blocks,
+                          hipStream_t s) {
+  const bool nnz = KIND != ANTS_LRF_XY && nonneg;
+  if (stat == ANTS_STAT_ML)
+    return nnz ? launch_multi_kn<KIND, 0, true>(P, nn, na, blocks, s)
+               : launch_multi_kn<KIND, 0, false>(P, nn, na, blocks, s);
+  return nnz ? launch_multi_kn<KIND, 1, true>(P, nn, na, blocks, s)
+             : launch_multi_kn<KIND, 1, false>(P, nn, na, blocks, s);
+}
+
+// launcher of one LRF kind: ML or chi2 statistic, node tiles, sensor slots,
+// non-negative tables
+template <int KIND>
+hipError_t launch_grid_k(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
+  return G.stat == ANTS_STAT_ML ? launch_ks<KIND, 0>(L, G, io, s, mb)
+                                : launch_ks<KIND, 1>(L, G, io, s, mb);
+}
+
+}  // namespace
+}  // namespace ants

@@ -14,6 +14,7 @@ struct Prepared {
   std::vector<SetDesc> sets;
   std::vector<ChunkDesc> chunks;
   int kind = 0, stat = 0, max_nn = 0, max_na = 0, btab_n = 0, per_wave = 0;
+  bool nonneg = true;
 };
 
 ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets,
@@ -46,6 +47,7 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
                   : d.L.kind == ANTS_LRF_RZ  ? d.L.nc1 * d.L.nintp
                                              : 0;
     tab += n;
+    P->nonneg = P->nonneg && d.L.nonneg;
     P->max_nn = d.G.nn > P->max_nn ? d.G.nn : P->max_nn;
     P->max_na = d.L.na > P->max_na ? d.L.na : P->max_na;
     int pw = 32 * d.L.na + (d.L.kind == ANTS_LRF_RZ ? 16 * d.G.nz * d.L.nintp : 0) +
@@ -140,7 +142,7 @@ ants_status run(ants_lrfset* owner, const Prepared& P, const ants_plan& plan, an
   int blocks = num_cu() * plan.blocks_per_cu;
   int64_t need = ((int64_t)M.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > need) blocks = (int)(need > 0 ? need : 1);
-  if (e == hipSuccess) e = launch_multi(M, P.kind, P.stat, P.max_nn, P.max_na, blocks, s);
+  if (e == hipSuccess) e = launch_multi(M, P.kind, P.stat, P.max_nn, P.max_na, P.nonneg, blocks, s);
   return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_reconstruct_multi launch");
 }
 

@@ -107,6 +107,24 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// FP64 r-z LRF of sensor a at (x, y) on a z-plane whose B-spline rows were
+// collapsed along z beforehand (zc: nc0 coefficients of the 1-D spline in r)
+__device__ __forceinline__ double lrf64_plane(const DevLrf& L, int a, double x, double y,
+                                              const double* zc) {
+  const double dx = x - L.X[a], dy = y - L.Y[a];
+  const double r = sqrt(dx * dx + dy * dy);
+  const double tol = 1e-9 * (L.hi0 - L.lo0);
+  if (!(r >= L.lo0 - tol && r <= L.hi0 + tol)) return 0.0;
+  const double v = (r - L.lo0) * L.inv_d0;
+  int k = (int)floor(v);
+  k = k < 0 ? 0 : k;
+  k = k > L.nb0 - 2 ? L.nb0 - 2 : k;
+  double b[4];
+  bweights64(v - (double)k, b);
+  const double val = zc[k] * b[0] + zc[k + 1] * b[1] + zc[k + 2] * b[2] + zc[k + 3] * b[3];
+  return val > 0.0 ? val : 0.0;
+}
+
 // --------------------------------------------------- FP32 screening LRF
 
 // Per-lane description of one node for the FP32 screen.
@@ -241,6 +259,8 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   float4* ztab = recB + L.na;
   int* cand = (int*)(ztab + (KIND == ANTS_LRF_RZ ? G.nz * L.nintp : 0));
   const int* nodeidx = cand + kMaxNodes;
+  // r-z: FP64 spline rows collapsed on each z-plane of the current grid
+  double* zc64 = (double*)(cand + 2 * kMaxNodes);
   const int na = L.na;
   const int nlast = L.nintp - 1;
   const float finv = L.finv0;
@@ -401,6 +421,22 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         acc.z = fmaf(w.w, P3.z, fmaf(w.z, P2.z, fmaf(w.y, P1.z, w.x * P0.z)));
         acc.w = fmaf(w.w, P3.w, fmaf(w.z, P2.w, fmaf(w.y, P1.w, w.x * P0.w)));
         ztab[i] = acc;
+      }
+      const int nct = G.nz * L.nc0;
+      const float inv_nc0 = 1.0f / (float)L.nc0;
+      for (int i = lane; i < nct; i += 64) {
+        const int jz = (int)(((float)i + 0.5f) * inv_nc0);
+        const int c = i - jz * L.nc0;
+        const double zz = cz + (double)(jz - G.hz) * sz;
+        int mz;
+        double tz, bz[4], v = 0.0;
+        if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
+          bweights64(tz, bz);
+          const double* col = L.c64 + (size_t)mz * L.nc0 + c;
+          v = bz[0] * col[0] + bz[1] * col[L.nc0] + bz[2] * col[2 * L.nc0] +
+              bz[3] * col[3 * L.nc0];
+        }
+        zc64[i] = v;
       }
       wave_sync_lds();
     }
@@ -644,7 +680,10 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
             const int a = lane + 64 * q;
             Lq[q] = 0.0;
             if (a < na) {
-              Lq[q] = lrf64<KIND>(L, a, xx, yy, zz);
+              if constexpr (KIND == ANTS_LRF_RZ)
+                Lq[q] = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> 20) * L.nc0);
+              else
+                Lq[q] = lrf64<KIND>(L, a, xx, yy, zz);
               S += L.g[a] * Lq[q];
               if (nq[q] > 0.f) T += (double)nq[q] * log(Lq[q] > G.lfloor ? Lq[q] : G.lfloor);
             }
@@ -698,7 +737,11 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
             for (int p = 0; p < na; ++p) {
               float4 A = recA[p];
               int a = __float_as_int(recB[p].w);
-              double Lv = lrf64<KIND>(L, a, xx, yy, zz);
+              double Lv;
+              if constexpr (KIND == ANTS_LRF_RZ)
+                Lv = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> 20) * L.nc0);
+              else
+                Lv = lrf64<KIND>(L, a, xx, yy, zz);
               S += L.g[a] * Lv;
               if (A.z > 0.f) T += (double)A.z * log(Lv > G.lfloor ? Lv : G.lfloor);
             }
@@ -710,7 +753,12 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
                 for (int p = 0; p < na; ++p) {
                   float4 A = recA[p];
                   int a = __float_as_int(recB[p].w);
-                  double mu = Aa * L.g[a] * lrf64<KIND>(L, a, xx, yy, zz);
+                  double Lv2;
+                  if constexpr (KIND == ANTS_LRF_RZ)
+                    Lv2 = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> 20) * L.nc0);
+                  else
+                    Lv2 = lrf64<KIND>(L, a, xx, yy, zz);
+                  double mu = Aa * L.g[a] * Lv2;
                   double dd = (double)A.z - mu;
                   Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
                 }
@@ -842,7 +890,8 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   int btab_n = 0;
   if (KIND == ANTS_LRF_AXIAL) btab_n = L.ntab * L.nintp;
   if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
-  int per_wave = 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp : 0) + 8 * kMaxNodes;
+  int per_wave = 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp + 8 * G.nz * L.nc0 : 0) +
+                 8 * kMaxNodes;
   per_wave = (per_wave + 15) & ~15;
   size_t smem = (size_t)btab_n * 16 + (size_t)kWavesPerBlock * per_wave;
   int64_t nwork = io.n;

@@ -50,7 +50,8 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
     P->nonneg = P->nonneg && d.L.nonneg;
     P->max_nn = d.G.nn > P->max_nn ? d.G.nn : P->max_nn;
     P->max_na = d.L.na > P->max_na ? d.L.na : P->max_na;
-    int pw = 32 * d.L.na + (d.L.kind == ANTS_LRF_RZ ? 16 * d.G.nz * d.L.nintp : 0) +
+    int pw = 32 * d.L.na +
+             (d.L.kind == ANTS_LRF_RZ ? 16 * d.G.nz * d.L.nintp + 8 * d.G.nz * d.L.nc0 : 0) +
              8 * kMaxNodes;
     per_wave = pw > per_wave ? pw : per_wave;
     P->sets.push_back(d);

@@ -16,6 +16,27 @@ constexpr int kSlots = kMaxSensors / 64;
 constexpr int kMaxNodes = 512;       // 8 tiles of 64 nodes
 constexpr int kWavesPerBlock = 4;
 
+// Tiles of 64 node lanes used for a grid of nn nodes (the event kernels
+// are instantiated for these counts).
+__host__ __device__ constexpr int node_tiles(int nn) {
+  return nn <= 64 ? 1 : nn <= 128 ? 2 : nn <= 256 ? 4 : nn <= 384 ? 6 : 8;
+}
+
+// Per-wave LDS bytes of the event kernels: sensor records (32 B per active
+// sensor); for r-z the FP32 plane tables (16 B per plane and interval),
+// which the FP64 spline rows (8 B per plane and r-coefficient) overlay
+// during the FP64 decisions, and the plane weights (16 B FP32 + 32 B FP64
+// + 4 B first z-coefficient per plane); 16-bit candidate list and
+// node-index table of 64 entries per node tile.
+inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt) {
+  int b = 32 * na + 256 * nt;
+  if (kind == ANTS_LRF_RZ) {
+    const int zt = 16 * nz * nintp, zr = 8 * nz * nc0;
+    b += ((zt > zr ? zt : zr) + 15) / 16 * 16 + 52 * nz;
+  }
+  return (b + 15) & ~15;
+}
+
 // Device-resident view of an LRF set.  Sensors are the active ones only,
 // in their original order ("compact index" a = 0..na-1).
 struct DevLrf {
@@ -45,6 +66,8 @@ struct DevLrf {
 struct GridP {
   int nx, ny, nz, nn;  // nodes per axis, total
   int hx, hy, hz;      // (n-1)/2
+  int shy, shz;        // node index packing: jx | jy << shy | jz << shz
+  int mskx, msky;      // (1 << bits of nx) - 1, (1 << bits of ny) - 1
   int K;               // iterations
   int dim;             // 2 or 3
   int stat;            // ANTS_STAT_*

@@ -121,6 +121,15 @@ ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
   G.hx = (G.nx - 1) / 2;
   G.hy = (G.ny - 1) / 2;
   G.hz = (G.nz - 1) / 2;
+  {
+    // bits per axis index; at most 12 in total for grids of <= 512 nodes
+    auto bits = [](int n) { int b = 0; while ((1 << b) < n) ++b; return b; };
+    const int bx = bits(G.nx), by = bits(G.ny);
+    G.shy = bx;
+    G.shz = bx + by;
+    G.mskx = (1 << bx) - 1;
+    G.msky = (1 << by) - 1;
+  }
   G.K = cfg->iterations;
   if (G.K < 0 || G.K > 64) return set_error(ANTS_E_ARG, "iterations = %d outside 0..64", G.K);
   if (!(cfg->shrink > 0.0 && cfg->shrink <= 1.0))

@@ -186,26 +186,60 @@ __device__ __forceinline__ float lrf32(const NodeF<KIND>& nd, float dX, float dY
 
 // Node j of the current grid: FP64 position, FP32 screen description and
 // validity (nodes whose z, or XY position, leave the LRF domain have S = 0).
-// Node index -> (jx, jy, jz) packed as jx | jy << 10 | jz << 20, one entry
-// per node of the current grid (avoids integer division in the loops).
-__device__ __forceinline__ void fill_nodeidx(const GridP& G, int* tab, int lane) {
-  for (int j = lane; j < kMaxNodes; j += 64) {
+// Node index -> (jx, jy, jz) packed as jx | jy << shy | jz << shz (16 bits),
+// one entry per node lane (avoids integer division in the loops).
+__device__ __forceinline__ void fill_nodeidx(const GridP& G, uint16_t* tab, int ntab, int lane) {
+  for (int j = lane; j < ntab; j += 64) {
     int v = 0;
     if (j < G.nn) {
       const int jx = j % G.nx, jy = (j / G.nx) % G.ny, jz = j / (G.nx * G.ny);
-      v = jx | (jy << 10) | (jz << 20);
+      v = jx | (jy << G.shy) | (jz << G.shz);
     }
-    tab[j] = v;
+    tab[j] = (uint16_t)v;
   }
+}
+
+// A wave's LDS area (sizes as in wave_lds_bytes).
+struct WaveLds {
+  float4* recA;        // per sensor record: dX, dY, n, 1/L_c
+  float4* recB;        // g, L_c, table offset, sensor index
+  float4* ztab;        // r-z: FP32 plane tables [nz][nintp]
+  double* zc64;        // r-z: FP64 spline rows [nz][nc0], overlaying ztab
+  float4* pw32;        // r-z: FP32 z-weights per plane
+  double* pw64;        // r-z: FP64 z-weights per plane
+  int* pm;             // r-z: first z-coefficient per plane
+  uint16_t* cand;      // candidate list
+  uint16_t* nodeidx;   // packed node indices
+};
+template <int KIND, int NT>
+__device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& L,
+                                            const GridP& G) {
+  WaveLds w;
+  w.recA = (float4*)wbase;
+  w.recB = w.recA + L.na;
+  w.ztab = w.recB + L.na;
+  w.zc64 = (double*)w.ztab;
+  int zq = 0, nzp = 0;
+  if constexpr (KIND == ANTS_LRF_RZ) {
+    const int zt = G.nz * L.nintp, zr = (G.nz * L.nc0 + 1) / 2;
+    zq = zt > zr ? zt : zr;
+    nzp = G.nz;
+  }
+  w.pw32 = w.ztab + zq;
+  w.pw64 = (double*)(w.pw32 + nzp);
+  w.pm = (int*)(w.pw64 + 4 * nzp);
+  w.cand = (uint16_t*)(w.pm + nzp);
+  w.nodeidx = w.cand + 64 * NT;
+  return w;
 }
 
 template <int KIND>
 __device__ __forceinline__ bool make_node(const DevLrf& L, const GridP& G, double cx, double cy,
                                           double cz, double sx, double sy, double sz, int j,
-                                          const float4* ztab, const int* nodeidx,
+                                          const float4* ztab, const uint16_t* nodeidx,
                                           NodeF<KIND>& nd, double& x, double& y, double& z) {
   const int packed = nodeidx[j];
-  const int jx = packed & 1023, jy = (packed >> 10) & 1023, jz = packed >> 20;
+  const int jx = packed & G.mskx, jy = (packed >> G.shy) & G.msky, jz = packed >> G.shz;
   double ox = (double)(jx - G.hx) * sx;
   double oy = (double)(jy - G.hy) * sy;
   double oz = (double)(jz - G.hz) * sz;
@@ -254,13 +288,18 @@ template <int KIND, int STAT, int NT, int SL, bool NN>
 __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, const IoP& io,
                                               const int64_t e, const float4* btab,
                                               unsigned char* wbase, const int lane) {
-  float4* recA = (float4*)wbase;
-  float4* recB = recA + L.na;
-  float4* ztab = recB + L.na;
-  int* cand = (int*)(ztab + (KIND == ANTS_LRF_RZ ? G.nz * L.nintp : 0));
-  const int* nodeidx = cand + kMaxNodes;
+  const WaveLds W = wave_lds<KIND, NT>(wbase, L, G);
+  float4* recA = W.recA;
+  float4* recB = W.recB;
+  float4* ztab = W.ztab;
+  uint16_t* cand = W.cand;
+  const uint16_t* nodeidx = W.nodeidx;
   // r-z: FP64 spline rows collapsed on each z-plane of the current grid
-  double* zc64 = (double*)(cand + 2 * kMaxNodes);
+  // (they overlay the FP32 plane tables, which the FP64 decision does not
+  // read), the z-weights and the first z-coefficient of each plane
+  double* zc64 = W.zc64;
+  double* pw64 = W.pw64;
+  int* pm64 = W.pm;
   const int na = L.na;
   const int nlast = L.nintp - 1;
   const float finv = L.finv0;
@@ -390,21 +429,22 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     const int lk = opaque(lane);
     // ---- r-z: collapse the table along z for this iteration's planes
     if constexpr (KIND == ANTS_LRF_RZ) {
-      // plane weights once per plane (the candidate list area is free here)
-      float4* pw = (float4*)cand;
-      int* pm = cand + 4 * G.nz;
+      // plane weights once per plane
+      float4* pw = W.pw32;
+      int* pm = W.pm;
       for (int jz = lane; jz < G.nz; jz += 64) {
         const double zz = cz + (double)(jz - G.hz) * sz;
         int mz;
         double tz, bz[4];
         if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
           bweights64(tz, bz);
-          pw[jz] = make_float4((float)bz[0], (float)bz[1], (float)bz[2], (float)bz[3]);
-          pm[jz] = mz;
         } else {
-          pw[jz] = make_float4(0.f, 0.f, 0.f, 0.f);
-          pm[jz] = 0;
+          bz[0] = bz[1] = bz[2] = bz[3] = 0.0;
+          mz = 0;
         }
+        pw[jz] = make_float4((float)bz[0], (float)bz[1], (float)bz[2], (float)bz[3]);
+        pm[jz] = mz;
+        for (int r = 0; r < 4; ++r) pw64[4 * jz + r] = bz[r];
       }
       wave_sync_lds();
       const int ntot = G.nz * L.nintp;
@@ -422,24 +462,25 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         acc.w = fmaf(w.w, P3.w, fmaf(w.z, P2.w, fmaf(w.y, P1.w, w.x * P0.w)));
         ztab[i] = acc;
       }
-      const int nct = G.nz * L.nc0;
-      const float inv_nc0 = 1.0f / (float)L.nc0;
-      for (int i = lane; i < nct; i += 64) {
-        const int jz = (int)(((float)i + 0.5f) * inv_nc0);
-        const int c = i - jz * L.nc0;
-        const double zz = cz + (double)(jz - G.hz) * sz;
-        int mz;
-        double tz, bz[4], v = 0.0;
-        if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
-          bweights64(tz, bz);
-          const double* col = L.c64 + (size_t)mz * L.nc0 + c;
-          v = bz[0] * col[0] + bz[1] * col[L.nc0] + bz[2] * col[2 * L.nc0] +
-              bz[3] * col[3 * L.nc0];
-        }
-        zc64[i] = v;
-      }
       wave_sync_lds();
     }
+    // r-z: FP64 rows of the planes, made on the first FP64 decision of the
+    // iteration (most iterations decide from the screen alone)
+    auto make_rows = [&]() {
+      if constexpr (KIND == ANTS_LRF_RZ) {
+        const int nct = G.nz * L.nc0;
+        const float inv_nc0 = 1.0f / (float)L.nc0;
+        for (int i = lane; i < nct; i += 64) {
+          const int jz = (int)(((float)i + 0.5f) * inv_nc0);
+          const int c = i - jz * L.nc0;
+          const double* col = L.c64 + (size_t)pm64[jz] * L.nc0 + c;
+          const double* w = pw64 + 4 * jz;
+          zc64[i] = w[0] * col[0] + w[1] * col[L.nc0] + w[2] * col[2 * L.nc0] +
+                    w[3] * col[3 * L.nc0];
+        }
+        wave_sync_lds();
+      }
+    };
 
     // ---- reference at the centre, per sensor (lane-parallel)
     NodeF<KIND> ndc;
@@ -480,13 +521,20 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     wave_sync_lds();
 
     // ---- node set-up
+    // grids of at most 32 nodes split the sensors between the two halves of
+    // the wave: lanes l and l + 32 both hold node l, each sums over every
+    // other sensor, and the halves add their sums
+    const bool split = NT == 1 && G.nn <= 32;
+    const int hb = split ? (lk >> 5) : 0;
+    const int pstep = split ? 2 : 1;
     NodeF<KIND> nd[NT];
     bool valid[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       double xx, yy, zz;
-      valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, t * 64 + lk, ztab, nodeidx, nd[t], xx,
-                                 yy, zz);
+      const int j = split ? (lk & 31) : t * 64 + lk;
+      valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, nd[t], xx, yy, zz);
+      if (split) valid[t] = valid[t] && lk < 32;
     }
 
     // ---- FP32 screen
@@ -495,8 +543,9 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       float dS[NT], T[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) { dS[t] = 0.f; T[t] = 0.f; }
-      for (int p = 0; p < npos; ++p) {
-        float4 A = recA[p], B = recB[p];
+      int p = 0;
+      for (; p + pstep <= npos; p += pstep) {
+        float4 A = recA[p + hb], B = recB[p + hb];
         int tofs = __float_as_int(B.z);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -505,14 +554,36 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
         }
       }
-      for (int p = npos; p < na; ++p) {
+      if (split && p < npos) {
+        // odd count: the first half takes the last sensor, the second adds
+        // zero (or NaN where the first half's term is infinite already)
         float4 A = recA[p], B = recB[p];
+        const float w = hb ? 0.f : 1.f;
+        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+                                   finv, nlast);
+        dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
+        T[0] = fmaf(A.z * w, __builtin_amdgcn_logf(Lv * A.w), T[0]);
+      }
+      p = npos;
+      for (; p + pstep <= na; p += pstep) {
+        float4 A = recA[p + hb], B = recB[p + hb];
         int tofs = __float_as_int(B.z);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
           dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
         }
+      }
+      if (split && p < na) {
+        float4 A = recA[p], B = recB[p];
+        const float w = hb ? 0.f : 1.f;
+        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+                                   finv, nlast);
+        dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
+      }
+      if (split) {
+        dS[0] += __shfl_xor(dS[0], 32);
+        T[0] += __shfl_xor(T[0], 32);
       }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -530,8 +601,9 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       float S[NT], Q[NT], Ag[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) { S[t] = 0.f; Q[t] = 0.f; }
-      for (int p = 0; p < na; ++p) {
-        float4 A = recA[p], B = recB[p];
+      int p = 0;
+      for (; p + pstep <= na; p += pstep) {
+        float4 A = recA[p + hb], B = recB[p + hb];
         int tofs = __float_as_int(B.z);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -539,10 +611,17 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           S[t] = fmaf(B.x, Lv, S[t]);
         }
       }
+      if (split && p < na) {
+        float4 A = recA[p], B = recB[p];
+        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+                                   finv, nlast);
+        S[0] = fmaf(hb ? 0.f : B.x, Lv, S[0]);
+      }
+      if (split) S[0] += __shfl_xor(S[0], 32);
 #pragma unroll
       for (int t = 0; t < NT; ++t) Ag[t] = S[t] > 0.f ? N32 / S[t] : 0.f;
-      for (int p = 0; p < na; ++p) {
-        float4 A = recA[p], B = recB[p];
+      for (p = 0; p + pstep <= na; p += pstep) {
+        float4 A = recA[p + hb], B = recB[p + hb];
         int tofs = __float_as_int(B.z);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -553,6 +632,16 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           Q[t] = fmaf(dd * dd, __builtin_amdgcn_rcpf(v), Q[t]);
         }
       }
+      if (split && p < na) {
+        float4 A = recA[p], B = recB[p];
+        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+                                   finv, nlast);
+        float mu = Ag[0] * B.x * Lv;
+        float dd = A.z - mu;
+        float v = fmaxf(mu, fvf);
+        Q[0] = fmaf(hb ? 0.f : dd * dd, __builtin_amdgcn_rcpf(v), Q[0]);
+      }
+      if (split) Q[0] += __shfl_xor(Q[0], 32);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         Snode[t] = S[t];
@@ -651,7 +740,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       bool c = trusted[t] ? (D[t] < kInf && D[t] <= best + margin)
                           : (valid[t] && Snode[t] > -kInf);
       uint64_t m = __ballot(c);
-      if (c) cand[ncand + prefix_count(m)] = t * 64 + lane;
+      if (c) cand[ncand + prefix_count(m)] = (uint16_t)(t * 64 + lane);
       ncand += __popcll(m);
       if (__ballot(c && !trusted[t])) only_trusted = false;
     }
@@ -664,6 +753,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     if (ncand == 1 && only_trusted) {
       win = jb;
     } else if (ncand > 0 && ncand <= serial_max) {
+      make_rows();
       double bestd = __builtin_huge_val();
       int jd = 1 << 30;
       for (int c = 0; c < ncand; ++c) {
@@ -681,7 +771,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
             Lq[q] = 0.0;
             if (a < na) {
               if constexpr (KIND == ANTS_LRF_RZ)
-                Lq[q] = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> 20) * L.nc0);
+                Lq[q] = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> G.shz) * L.nc0);
               else
                 Lq[q] = lrf64<KIND>(L, a, xx, yy, zz);
               S += L.g[a] * Lq[q];
@@ -722,6 +812,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       nfp += ncand;
       win = bestd < __builtin_huge_val() ? jd : -1;
     } else if (ncand > 0) {
+      make_rows();
       double bestd = __builtin_huge_val();
       int jd = 1 << 30;
       for (int base = 0; base < ncand; base += 64) {
@@ -739,7 +830,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
               int a = __float_as_int(recB[p].w);
               double Lv;
               if constexpr (KIND == ANTS_LRF_RZ)
-                Lv = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> 20) * L.nc0);
+                Lv = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> G.shz) * L.nc0);
               else
                 Lv = lrf64<KIND>(L, a, xx, yy, zz);
               S += L.g[a] * Lv;
@@ -755,7 +846,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
                   int a = __float_as_int(recB[p].w);
                   double Lv2;
                   if constexpr (KIND == ANTS_LRF_RZ)
-                    Lv2 = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> 20) * L.nc0);
+                    Lv2 = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> G.shz) * L.nc0);
                   else
                     Lv2 = lrf64<KIND>(L, a, xx, yy, zz);
                   double mu = Aa * L.g[a] * Lv2;
@@ -855,10 +946,11 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   }
 }
 
-// Occupancy target: three waves per SIMD (168 VGPRs) for every variant
-// whose live state fits; the XY kernels with many node tiles keep two.
+// Occupancy target: four waves per SIMD (128 VGPRs) for one node tile,
+// whose time goes largely to latency-bound reductions and FP64 decisions;
+// three (168 VGPRs) for more tiles; the XY kernels with many tiles keep two.
 template <int KIND, int NT>
-constexpr int waves_per_eu() { return (KIND == ANTS_LRF_XY && NT >= 4) ? 2 : 3; }
+constexpr int waves_per_eu() { return (KIND == ANTS_LRF_XY && NT >= 4) ? 2 : NT == 1 ? 4 : 3; }
 
 template <int KIND, int STAT, int NT, int SL, bool NN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>())))
@@ -872,11 +964,8 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwb = blockDim.x >> 6;
   unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
-  {
-    int* cand = (int*)(wbase + 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp : 0));
-    fill_nodeidx(G, cand + kMaxNodes, lane0);
-    wave_sync_lds();
-  }
+  fill_nodeidx(G, wave_lds<KIND, NT>(wbase, L, G).nodeidx, 64 * NT, lane0);
+  wave_sync_lds();
   int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
   for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
     const int64_t e = io.list ? (int64_t)io.list[w] : w;
@@ -890,20 +979,25 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   int btab_n = 0;
   if (KIND == ANTS_LRF_AXIAL) btab_n = L.ntab * L.nintp;
   if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
-  int per_wave = 32 * L.na + (KIND == ANTS_LRF_RZ ? 16 * G.nz * L.nintp + 8 * G.nz * L.nc0 : 0) +
-                 8 * kMaxNodes;
-  per_wave = (per_wave + 15) & ~15;
+  const int per_wave = wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT);
   size_t smem = (size_t)btab_n * 16 + (size_t)kWavesPerBlock * per_wave;
   int64_t nwork = io.n;
   int64_t blocks = (nwork + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (blocks > max_blocks) blocks = max_blocks;
-  if (blocks < 1) blocks = 1;
   auto kern = cg_kernel<KIND, STAT, NT, SL, NN>;
   if (smem > 65536) {
     hipError_t st = hipFuncSetAttribute((const void*)kern,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (st != hipSuccess) return st;
   }
+  // waves stride over the events: launch no more blocks than are resident
+  // at once, so that no block starts after the others have finished
+  int resident = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, 64 * kWavesPerBlock, smem) ==
+          hipSuccess &&
+      resident > 0 && (int64_t)resident * num_cu() < max_blocks)
+    max_blocks = resident * num_cu();
+  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
   int64_t waves_total = blocks * kWavesPerBlock;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), smem, stream, L, G,
                      io, waves_total, per_wave, btab_n);
@@ -912,12 +1006,13 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
 
 template <int KIND, int STAT, int SL, bool NN>
 hipError_t launch_kss(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
-  int nt = (G.nn + 63) / 64;
-  if (nt <= 1) return launch_t<KIND, STAT, 1, SL, NN>(L, G, io, s, mb);
-  if (nt <= 2) return launch_t<KIND, STAT, 2, SL, NN>(L, G, io, s, mb);
-  if (nt <= 4) return launch_t<KIND, STAT, 4, SL, NN>(L, G, io, s, mb);
-  if (nt <= 6) return launch_t<KIND, STAT, 6, SL, NN>(L, G, io, s, mb);
-  return launch_t<KIND, STAT, 8, SL, NN>(L, G, io, s, mb);
+  switch (node_tiles(G.nn)) {
+    case 1: return launch_t<KIND, STAT, 1, SL, NN>(L, G, io, s, mb);
+    case 2: return launch_t<KIND, STAT, 2, SL, NN>(L, G, io, s, mb);
+    case 4: return launch_t<KIND, STAT, 4, SL, NN>(L, G, io, s, mb);
+    case 6: return launch_t<KIND, STAT, 6, SL, NN>(L, G, io, s, mb);
+    default: return launch_t<KIND, STAT, 8, SL, NN>(L, G, io, s, mb);
+  }
 }
 
 template <int KIND, int STAT, bool NN>
@@ -974,9 +1069,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>()))) cg_multi_kernel(M
     const SetDesc& sd = P.sets[ch.set];
     if (ch.set != cur_set) {
       cur_set = ch.set;
-      int* cand = (int*)(wbase + 32 * sd.L.na +
-                         (KIND == ANTS_LRF_RZ ? 16 * sd.G.nz * sd.L.nintp : 0));
-      fill_nodeidx(sd.G, cand + kMaxNodes, lane0);
+      fill_nodeidx(sd.G, wave_lds<KIND, NT>(wbase, sd.L, sd.G).nodeidx, 64 * NT, lane0);
       wave_sync_lds();
     }
     IoP io = P.out;
@@ -1014,12 +1107,13 @@ hipError_t launch_multi_t(const MultiP& P, int blocks, hipStream_t stream) {
 
 template <int KIND, int STAT, int SL, bool NN>
 hipError_t launch_multi_ks(const MultiP& P, int nn, int blocks, hipStream_t s) {
-  int nt = (nn + 63) / 64;
-  if (nt <= 1) return launch_multi_t<KIND, STAT, 1, SL, NN>(P, blocks, s);
-  if (nt <= 2) return launch_multi_t<KIND, STAT, 2, SL, NN>(P, blocks, s);
-  if (nt <= 4) return launch_multi_t<KIND, STAT, 4, SL, NN>(P, blocks, s);
-  if (nt <= 6) return launch_multi_t<KIND, STAT, 6, SL, NN>(P, blocks, s);
-  return launch_multi_t<KIND, STAT, 8, SL, NN>(P, blocks, s);
+  switch (node_tiles(nn)) {
+    case 1: return launch_multi_t<KIND, STAT, 1, SL, NN>(P, blocks, s);
+    case 2: return launch_multi_t<KIND, STAT, 2, SL, NN>(P, blocks, s);
+    case 4: return launch_multi_t<KIND, STAT, 4, SL, NN>(P, blocks, s);
+    case 6: return launch_multi_t<KIND, STAT, 6, SL, NN>(P, blocks, s);
+    default: return launch_multi_t<KIND, STAT, 8, SL, NN>(P, blocks, s);
+  }
 }
 
 template <int KIND, int STAT, bool NN>

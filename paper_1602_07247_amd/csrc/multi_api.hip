@@ -50,11 +50,13 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
     P->nonneg = P->nonneg && d.L.nonneg;
     P->max_nn = d.G.nn > P->max_nn ? d.G.nn : P->max_nn;
     P->max_na = d.L.na > P->max_na ? d.L.na : P->max_na;
-    int pw = 32 * d.L.na +
-             (d.L.kind == ANTS_LRF_RZ ? 16 * d.G.nz * d.L.nintp + 8 * d.G.nz * d.L.nc0 : 0) +
-             8 * kMaxNodes;
-    per_wave = pw > per_wave ? pw : per_wave;
     P->sets.push_back(d);
+  }
+  // every set's wave area is laid out with the launch's node-tile count
+  for (const SetDesc& d : P->sets) {
+    const int pw = wave_lds_bytes(d.L.kind, d.L.na, d.G.nz, d.L.nintp, d.L.nc0,
+                                  node_tiles(P->max_nn));
+    per_wave = pw > per_wave ? pw : per_wave;
   }
   if ((size_t)tab * 16 > 96 * 1024)
     return set_error(ANTS_E_UNSUPPORTED, "LRF tables of all sets exceed 96 KiB of LDS");

@@ -58,6 +58,25 @@ def test_parity_against_oracle(ants, k, n, stat):
     np.testing.assert_array_equal(gpu["ndf"], ref["ndf"])
 
 
+@pytest.mark.parametrize("k,nodes,stat,n", [(0, (5, 5, 1), 0, 3_000), (0, (5, 5, 1), 1, 2_000),
+                                             (0, (3, 3, 1), 0, 2_000), (1, (5, 5, 1), 0, 1_000),
+                                             (1, (3, 3, 1), 1, 1_000), (2, (3, 3, 3), 0, 2_000),
+                                             (2, (3, 3, 3), 1, 1_000), (2, (5, 5, 1), 0, 1_000)])
+def test_parity_small_grids_split_sensor_loop(ants, k, nodes, stat, n):
+    # grids of <= 32 nodes run the screen with the sensors split between the
+    # two halves of a wave (odd and even sensor counts, both statistics)
+    wl, sig, truth = _events(k, n, seed_off=2)
+    grid = W.GridCfg(**{**wl.grid.__dict__, "nodes": nodes, "stat": stat,
+                        "iterations": wl.grid.iterations + 2})
+    ref = oracle.reconstruct(wl.lrf, grid, sig)
+    gpu = _run(ants, wl, sig, grid)
+    res = compare(ref, gpu, sig, stat, three_d=nodes[2] > 1)
+    print(summary(res), "| mean FP64 nodes/event", gpu["n_fp64"].mean())
+    assert res["frac"] >= 0.999, summary(res)
+    full = _run(ants, wl, sig[:500], grid, screen_scale=1e30)
+    np.testing.assert_array_equal(gpu["path"][:500], full["path"])
+
+
 def test_screen_is_sound_full_fp64_gives_same_answers(ants):
     # with an unbounded screening margin every valid node is decided in FP64;
     # the default margin must reach exactly the same decisions

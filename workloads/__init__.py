@@ -271,7 +271,7 @@ def chunk_stream(total: int, seed_offset: int = 0, median=1e4, sigma_ln=1.0,
     return np.asarray(sizes, np.int64), np.asarray(geoms, np.int32)
 
 
-def seeded_refine_grid(kappa: float = 2.0, kmin: int = 2, kmax: int = 8) -> GridCfg:
+def seeded_refine_grid(kappa: float = 1.0, kmin: int = 2, kmax: int = 8) -> GridCfg:
     """Refinement grid of the learned-seed path: 3 x 3 x 3 nodes started at
     the seed, ending on the plain grid's final step (workload 2: 10, 10,
     50/6 mm halved over 8 iterations), with the iteration count chosen per

@@ -139,7 +139,7 @@ typedef struct {
    * iterations from s_f * shrink^-(K-1) (iterated quotients), K the
    * smallest with s_f * shrink^-(K-1) >= seed_kappa * sigma_a on every axis
    * with nodes > 1 (seed_kmax when s is not finite).  Requires
-   * 1 <= seed_kmin <= seed_kmax <= iterations. */
+   * 1 <= seed_kmin <= seed_kmax <= min(iterations, 16). */
   int32_t seed_steps;
   double seed_kappa;
   int32_t seed_kmin, seed_kmax;

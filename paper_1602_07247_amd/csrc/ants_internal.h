@@ -15,6 +15,7 @@ constexpr int kMaxSensors = 256;     // row length limit (4 sensor slots per lan
 constexpr int kSlots = kMaxSensors / 64;
 constexpr int kMaxNodes = 512;       // 8 tiles of 64 nodes
 constexpr int kWavesPerBlock = 4;
+constexpr int kMaxSeedSteps = 16;   // iteration counts a seed's spread may select
 
 // Tiles of 64 node lanes used for a grid of nn nodes (the event kernels
 // are instantiated for these counts).
@@ -23,13 +24,14 @@ __host__ __device__ constexpr int node_tiles(int nn) {
 }
 
 // Per-wave LDS bytes of the event kernels: sensor records (32 B per active
-// sensor); for r-z the FP32 plane tables (16 B per plane and interval),
+// sensor, rewritten every iteration, and 32 B of FP64 data per event); for r-z the FP32 plane tables (16 B per plane and interval),
 // which the FP64 spline rows (8 B per plane and r-coefficient) overlay
 // during the FP64 decisions, and the plane weights (16 B FP32 + 32 B FP64
 // + 4 B first z-coefficient per plane); 16-bit candidate list and
-// node-index table of 64 entries per node tile.
+// node-index table of 64 entries per node tile; the per-axis steps for
+// each iteration count a seed may select.
 inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt) {
-  int b = 32 * na + 256 * nt;
+  int b = 64 * na + 256 * nt + 24 * kMaxSeedSteps;
   if (kind == ANTS_LRF_RZ) {
     const int zt = 16 * nz * nintp, zr = 8 * nz * nc0;
     b += ((zt > zr ? zt : zr) + 15) / 16 * 16 + 52 * nz;

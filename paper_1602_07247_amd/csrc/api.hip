@@ -160,9 +160,11 @@ ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
   G.margin_scale = sc > 3e38 ? 3e38f : (float)sc;
   G.seed_steps = 0;
   if (cfg->start == ANTS_START_SEED && cfg->seed_steps) {
-    if (!(cfg->seed_kmin >= 1 && cfg->seed_kmin <= cfg->seed_kmax && cfg->seed_kmax <= G.K))
-      return set_error(ANTS_E_ARG, "need 1 <= seed_kmin (%d) <= seed_kmax (%d) <= iterations (%d)",
-                       cfg->seed_kmin, cfg->seed_kmax, G.K);
+    if (!(cfg->seed_kmin >= 1 && cfg->seed_kmin <= cfg->seed_kmax && cfg->seed_kmax <= G.K &&
+          cfg->seed_kmax <= kMaxSeedSteps))
+      return set_error(ANTS_E_ARG,
+                       "need 1 <= seed_kmin (%d) <= seed_kmax (%d) <= min(iterations (%d), %d)",
+                       cfg->seed_kmin, cfg->seed_kmax, G.K, kMaxSeedSteps);
     if (!(cfg->seed_kappa > 0.0 && isfinite(cfg->seed_kappa)))
       return set_error(ANTS_E_ARG, "seed_kappa = %g must be positive", cfg->seed_kappa);
     for (int a = 0; a < 3; ++a)

@@ -43,42 +43,88 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-__device__ __forceinline__ double wsum_d(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Cross-lane moves within rows of 16 lanes (DPP): xor 1, xor 2 (quad
+// permutes), then the half-row and row mirrors, which act as xor 4 and xor 8
+// once the quads, then the half-rows, hold equal values.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int C>
+__device__ __forceinline__ int dpp(int v) {
+  return __builtin_amdgcn_mov_dpp(v, C, 0xF, 0xF, true);
+}
+template <int C>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(dpp<C>(__float_as_int(v)));
+}
+template <int C>
+__device__ __forceinline__ double dpp(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = dpp<C>(p.x);
+  p.y = dpp<C>(p.y);
+  return __builtin_bit_cast(double, p);
+}
+__device__ __forceinline__ float lane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ int lane_val(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double lane_val(double v, int l) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_readlane(p.x, l);
+  p.y = __builtin_amdgcn_readlane(p.y, l);
+  return __builtin_bit_cast(double, p);
+}
+// Sums over the wave (all lanes active): butterfly within each row of 16
+// lanes, then the four row sums in a fixed order; every lane gets the same
+// value.
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+  v += dpp<kDppXor1>(v);
+  v += dpp<kDppXor2>(v);
+  v += dpp<kDppHalfMirror>(v);
+  v += dpp<kDppMirror>(v);
+  return ((lane_val(v, 0) + lane_val(v, 16)) + lane_val(v, 32)) + lane_val(v, 48);
+}
+// Sums over aligned groups of 2^lg lanes (lg uniform, all lanes active);
+// every lane gets its group's sum.
+template <typename T>
+__device__ __forceinline__ T gsum(T v, int lg, int lane) {
+  if (lg >= 1) v += dpp<kDppXor1>(v);
+  if (lg >= 2) v += dpp<kDppXor2>(v);
+  if (lg >= 3) v += dpp<kDppHalfMirror>(v);
+  if (lg >= 4) v += dpp<kDppMirror>(v);
+  if (lg == 5) {
+    const T lo = lane_val(v, 0) + lane_val(v, 16), hi = lane_val(v, 32) + lane_val(v, 48);
+    v = lane < 32 ? lo : hi;
+  } else if (lg >= 6) {
+    v = ((lane_val(v, 0) + lane_val(v, 16)) + lane_val(v, 32)) + lane_val(v, 48);
+  }
   return v;
 }
-__device__ __forceinline__ float wsum_f(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+__device__ __forceinline__ double wsum_d(double v) { return wsum(v); }
+__device__ __forceinline__ float wsum_f(float v) { return wsum(v); }
+// lexicographic minimum of (value, index) over the wave; with MAX, maximum
+// of the value with the lowest index among equal values
+template <bool MAX, typename T>
+__device__ __forceinline__ void take_better(T& v, int& j, T v2, int j2) {
+  const bool b = MAX ? (v2 > v || (v2 == v && j2 < j)) : (v2 < v || (v2 == v && j2 < j));
+  if (b) { v = v2; j = j2; }
 }
-// lexicographic minimum of (value, index) over the wave
-__device__ __forceinline__ void wargmin_f(float& v, int& j) {
+template <bool MAX, typename T>
+__device__ __forceinline__ void warg(T& v, int& j) {
+  take_better<MAX>(v, j, dpp<kDppXor1>(v), dpp<kDppXor1>(j));
+  take_better<MAX>(v, j, dpp<kDppXor2>(v), dpp<kDppXor2>(j));
+  take_better<MAX>(v, j, dpp<kDppHalfMirror>(v), dpp<kDppHalfMirror>(j));
+  take_better<MAX>(v, j, dpp<kDppMirror>(v), dpp<kDppMirror>(j));
+  T v0 = lane_val(v, 0);
+  int j0 = lane_val(j, 0);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    float v2 = __shfl_xor(v, o);
-    int j2 = __shfl_xor(j, o);
-    if (v2 < v || (v2 == v && j2 < j)) { v = v2; j = j2; }
-  }
+  for (int r = 16; r < 64; r += 16) take_better<MAX>(v0, j0, lane_val(v, r), lane_val(j, r));
+  v = v0;
+  j = j0;
 }
-__device__ __forceinline__ void wargmin_d(double& v, int& j) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    double v2 = __shfl_xor(v, o);
-    int j2 = __shfl_xor(j, o);
-    if (v2 < v || (v2 == v && j2 < j)) { v = v2; j = j2; }
-  }
-}
-// lexicographic maximum of (value, -index): strongest sensor, lowest index
-__device__ __forceinline__ void wargmax_f(float& v, int& j) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    float v2 = __shfl_xor(v, o);
-    int j2 = __shfl_xor(j, o);
-    if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
-  }
-}
+__device__ __forceinline__ void wargmin_f(float& v, int& j) { warg<false>(v, j); }
+__device__ __forceinline__ void wargmin_d(double& v, int& j) { warg<false>(v, j); }
+// strongest sensor, lowest index among equals
+__device__ __forceinline__ void wargmax_f(float& v, int& j) { warg<true>(v, j); }
 __device__ __forceinline__ int prefix_count(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -109,9 +155,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 // FP64 r-z LRF of sensor a at (x, y) on a z-plane whose B-spline rows were
 // collapsed along z beforehand (zc: nc0 coefficients of the 1-D spline in r)
-__device__ __forceinline__ double lrf64_plane(const DevLrf& L, int a, double x, double y,
-                                              const double* zc) {
-  const double dx = x - L.X[a], dy = y - L.Y[a];
+__device__ __forceinline__ double lrf64_plane(const DevLrf& L, double X, double Y, double x,
+                                              double y, const double* zc) {
+  const double dx = x - X, dy = y - Y;
   const double r = sqrt(dx * dx + dy * dy);
   const double tol = 1e-9 * (L.hi0 - L.lo0);
   if (!(r >= L.lo0 - tol && r <= L.hi0 + tol)) return 0.0;
@@ -199,10 +245,18 @@ __device__ __forceinline__ void fill_nodeidx(const GridP& G, uint16_t* tab, int 
   }
 }
 
+// FP64 data of an active sensor, stored per event in record order.
+struct SensorRec64 {
+  double X, Y, g;
+  int coff;            // FP64 coefficient offset
+  int tofs;            // FP32 table offset
+};
+
 // A wave's LDS area (sizes as in wave_lds_bytes).
 struct WaveLds {
   float4* recA;        // per sensor record: dX, dY, n, 1/L_c
   float4* recB;        // g, L_c, table offset, sensor index
+  SensorRec64* rec64;  // X, Y, g, table offsets
   float4* ztab;        // r-z: FP32 plane tables [nz][nintp]
   double* zc64;        // r-z: FP64 spline rows [nz][nc0], overlaying ztab
   float4* pw32;        // r-z: FP32 z-weights per plane
@@ -210,6 +264,7 @@ struct WaveLds {
   int* pm;             // r-z: first z-coefficient per plane
   uint16_t* cand;      // candidate list
   uint16_t* nodeidx;   // packed node indices
+  double* sstep;       // seeded refinement: steps per axis after k quotients
 };
 template <int KIND, int NT>
 __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& L,
@@ -217,7 +272,8 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& 
   WaveLds w;
   w.recA = (float4*)wbase;
   w.recB = w.recA + L.na;
-  w.ztab = w.recB + L.na;
+  w.rec64 = (SensorRec64*)(w.recB + L.na);
+  w.ztab = (float4*)(w.rec64 + L.na);
   w.zc64 = (double*)w.ztab;
   int zq = 0, nzp = 0;
   if constexpr (KIND == ANTS_LRF_RZ) {
@@ -225,12 +281,32 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& 
     zq = zt > zr ? zt : zr;
     nzp = G.nz;
   }
+  // doubles first, then 4-byte and 2-byte entries (natural alignment)
   w.pw32 = w.ztab + zq;
   w.pw64 = (double*)(w.pw32 + nzp);
-  w.pm = (int*)(w.pw64 + 4 * nzp);
+  w.sstep = w.pw64 + 4 * nzp;
+  w.pm = (int*)(w.sstep + 3 * kMaxSeedSteps);
   w.cand = (uint16_t*)(w.pm + nzp);
   w.nodeidx = w.cand + 64 * NT;
   return w;
+}
+
+// Per-wave set-up: node index table and, for seeded refinement, the final
+// step divided by the shrink factor k times (iterated quotients), k <
+// kMaxSeedSteps, per axis.
+template <int KIND, int NT>
+__device__ __forceinline__ void wave_setup(unsigned char* wbase, const DevLrf& L, const GridP& G,
+                                           int lane) {
+  const WaveLds w = wave_lds<KIND, NT>(wbase, L, G);
+  fill_nodeidx(G, w.nodeidx, 64 * NT, lane);
+  if (G.seed_steps && lane < 3) {
+    double s = G.sfinal[lane];
+    for (int k = 0; k < kMaxSeedSteps; ++k) {
+      w.sstep[3 * k + lane] = s;
+      s = s / G.shrink;
+    }
+  }
+  wave_sync_lds();
 }
 
 template <int KIND>
@@ -291,6 +367,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   const WaveLds W = wave_lds<KIND, NT>(wbase, L, G);
   float4* recA = W.recA;
   float4* recB = W.recB;
+  SensorRec64* rec64 = W.rec64;
   float4* ztab = W.ztab;
   uint16_t* cand = W.cand;
   const uint16_t* nodeidx = W.nodeidx;
@@ -392,6 +469,19 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     }
   }
   const float N32 = (float)N;
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    const int a = lane + 64 * q;
+    if (a < na) {
+      SensorRec64 r;
+      r.X = L.X[a];
+      r.Y = L.Y[a];
+      r.g = L.g[a];
+      r.coff = coef_off64<KIND>(L, a);
+      r.tofs = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
+      rec64[posq[q]] = r;
+    }
+  }
 
   double sx = G.s0x, sy = G.s0y, sz = G.s0z;
   int Kev = G.K;
@@ -400,29 +490,24 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     // in [kmin, kmax] whose first step covers kappa * sigma on every axis,
     // ending on the configured final step
     const double lv = io.seeds[e * 4 + 3];
-    const double sg = exp(0.5 * lv) * G.kappa;
-    double s3[3] = {G.sfinal[0], G.sfinal[1], G.sfinal[2]};
-    const int nn3[3] = {G.nx, G.ny, G.nz};
-    int kk = 0;
-    for (; kk < G.kmin - 1; ++kk)
-      for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+    const double sg = uni(exp(0.5 * lv) * G.kappa);
+    const double* st = W.sstep;
+    int kk = G.kmin - 1;
     if (!(sg < __builtin_huge_val())) {
-      for (; kk < G.kmax - 1; ++kk)
-        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
+      kk = G.kmax - 1;
     } else {
-      for (;;) {
-        bool short_ = false;
-        for (int a = 0; a < 3; ++a)
-          if (nn3[a] > 1 && s3[a] < sg * G.sscale[a]) short_ = true;
-        if (!short_ || kk >= G.kmax - 1) break;
-        for (int a = 0; a < 3; ++a) s3[a] = s3[a] / G.shrink;
-        ++kk;
+      for (; kk < G.kmax - 1; ++kk) {
+        const bool short_ = (G.nx > 1 && st[3 * kk] < sg * G.sscale[0]) ||
+                            (G.ny > 1 && st[3 * kk + 1] < sg * G.sscale[1]) ||
+                            (G.nz > 1 && st[3 * kk + 2] < sg * G.sscale[2]);
+        if (!short_) break;
       }
     }
-    Kev = uni(kk + 1);
-    sx = uni(G.nx > 1 ? s3[0] : 0.0);
-    sy = uni(G.ny > 1 ? s3[1] : 0.0);
-    sz = uni(G.nz > 1 ? s3[2] : 0.0);
+    kk = uni(kk);
+    Kev = kk + 1;
+    sx = uni(G.nx > 1 ? st[3 * kk] : 0.0);
+    sy = uni(G.ny > 1 ? st[3 * kk + 1] : 0.0);
+    sz = uni(G.nz > 1 ? st[3 * kk + 2] : 0.0);
   }
   int nfp = 0;
   for (int k = 0; k < Kev; ++k) {
@@ -494,11 +579,12 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     for (int q = 0; q < SL; ++q) {
       int a = lane + 64 * q;
       if (a < na) {
-        float dX = (float)((L.X[a] - cx) * L.inv_d0),
-              dY = (float)((L.Y[a] - cy) * L.inv_d0);
-        int tofs = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
+        const SensorRec64 r = rec64[posq[q]];
+        float dX = (float)((r.X - cx) * L.inv_d0),
+              dY = (float)((r.Y - cy) * L.inv_d0);
+        int tofs = r.tofs;
         float Lc = lrf32<KIND, NN>(ndc, dX, dY, tofs, btab, L.c32, L.nc0, finv, nlast);
-        float g = (float)L.g[a];
+        float g = (float)r.g;
         Sc = fmaf(g, Lc, Sc);
         recA[posq[q]] = make_float4(dX, dY, nq[q], 1.0f / fmaxf(Lc, flf));
         recB[posq[q]] = make_float4(g, Lc, __int_as_float(tofs), __int_as_float(a));
@@ -748,124 +834,83 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 
     int win = -1;
     bool tie = false;
-    // lanes over sensors, one candidate at a time, when that is cheaper
-    const int serial_max = (na * 5) / (SL * 5 + 2);
     if (ncand == 1 && only_trusted) {
       win = jb;
-    } else if (ncand > 0 && ncand <= serial_max) {
-      make_rows();
-      double bestd = __builtin_huge_val();
-      int jd = 1 << 30;
-      for (int c = 0; c < ncand; ++c) {
-        const int j = uni(cand[c]);
-        NodeF<KIND> ndd;
-        double xx, yy, zz;
-        const bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx,
-                                        yy, zz);
-        double Dv = __builtin_huge_val();
-        if (ok) {
-          double S = 0.0, T = 0.0, Lq[SL];
-#pragma unroll
-          for (int q = 0; q < SL; ++q) {
-            const int a = lane + 64 * q;
-            Lq[q] = 0.0;
-            if (a < na) {
-              if constexpr (KIND == ANTS_LRF_RZ)
-                Lq[q] = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> G.shz) * L.nc0);
-              else
-                Lq[q] = lrf64<KIND>(L, a, xx, yy, zz);
-              S += L.g[a] * Lq[q];
-              if (nq[q] > 0.f) T += (double)nq[q] * log(Lq[q] > G.lfloor ? Lq[q] : G.lfloor);
-            }
-          }
-          S = wsum_d(S);
-          if (S > 0.0) {
-            if (STAT == ANTS_STAT_ML) {
-              Dv = N * log(S) - wsum_d(T);
-            } else {
-              const double Aa = N / S;
-              double Q = 0.0;
-#pragma unroll
-              for (int q = 0; q < SL; ++q) {
-                const int a = lane + 64 * q;
-                if (a < na) {
-                  const double mu = Aa * L.g[a] * Lq[q];
-                  const double dd = (double)nq[q] - mu;
-                  Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
-                }
-              }
-              Dv = wsum_d(Q);
-            }
-            if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
-          }
-        }
-        Dv = uni(Dv);
-        // candidates come in increasing node index: equal values keep the first
-        if (Dv < bestd) {
-          bestd = Dv;
-          jd = j;
-          tie = false;
-        } else if (Dv == bestd && Dv < __builtin_huge_val()) {
-          tie = true;
-        }
-      }
-      nfp += ncand;
-      win = bestd < __builtin_huge_val() ? jd : -1;
     } else if (ncand > 0) {
       make_rows();
+      // FP64 values of the candidates: groups of gs lanes per candidate,
+      // each lane over every gs-th sensor; gs from a cost model (sensor
+      // terms : group reduction steps : per-candidate work = 9 : 1 : 6)
+      int gs = 64, best_cost = 1 << 30;
+      for (int g = 1; g <= 64; g <<= 1) {
+        const int per_pass = 64 / g;
+        const int cost = ((ncand + per_pass - 1) / per_pass) *
+                         (((na + g - 1) / g) * 9 + (31 - __builtin_clz(g)) + 6);
+        if (cost < best_cost) {
+          best_cost = cost;
+          gs = g;
+        }
+      }
+      const int lgs = uni(31 - __builtin_clz(gs));
+      const int sub = lane & ((1 << lgs) - 1);
+      const int per_pass = 64 >> lgs;
       double bestd = __builtin_huge_val();
       int jd = 1 << 30;
-      for (int base = 0; base < ncand; base += 64) {
-        double Dv = __builtin_huge_val();
-        int j = 1 << 30;
-        if (base + lane < ncand) {
-          j = cand[base + lane];
+      for (int base = 0; base < ncand; base += per_pass) {
+        const int c = base + (lane >> lgs);
+        const int j = c < ncand ? (int)cand[c] : (1 << 30);
+        double xx = 0.0, yy = 0.0, zz = 0.0;
+        bool ok = false;
+        const double* zrow = zc64;
+        if (c < ncand) {
           NodeF<KIND> ndd;
-          double xx, yy, zz;
-          bool ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx, yy, zz);
-          if (ok) {
-            double S = 0.0, T = 0.0;
-            for (int p = 0; p < na; ++p) {
-              float4 A = recA[p];
-              int a = __float_as_int(recB[p].w);
-              double Lv;
-              if constexpr (KIND == ANTS_LRF_RZ)
-                Lv = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> G.shz) * L.nc0);
-              else
-                Lv = lrf64<KIND>(L, a, xx, yy, zz);
-              S += L.g[a] * Lv;
-              if (A.z > 0.f) T += (double)A.z * log(Lv > G.lfloor ? Lv : G.lfloor);
-            }
-            if (S > 0.0) {
-              if (STAT == ANTS_STAT_ML) {
-                Dv = N * log(S) - T;
-              } else {
-                double Aa = N / S, Q = 0.0;
-                for (int p = 0; p < na; ++p) {
-                  float4 A = recA[p];
-                  int a = __float_as_int(recB[p].w);
-                  double Lv2;
-                  if constexpr (KIND == ANTS_LRF_RZ)
-                    Lv2 = lrf64_plane(L, a, xx, yy, zc64 + (nodeidx[j] >> G.shz) * L.nc0);
-                  else
-                    Lv2 = lrf64<KIND>(L, a, xx, yy, zz);
-                  double mu = Aa * L.g[a] * Lv2;
-                  double dd = (double)A.z - mu;
-                  Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
-                }
-                Dv = Q;
-              }
-              if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
-            }
+          ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx, yy, zz);
+          if constexpr (KIND == ANTS_LRF_RZ) zrow = zc64 + (nodeidx[j] >> G.shz) * L.nc0;
+        }
+        double S = 0.0, T = 0.0;
+        if (ok) {
+          for (int p = sub; p < na; p += 1 << lgs) {
+            const float n = recA[p].z;
+            const SensorRec64 r = rec64[p];
+            double Lv;
+            if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
+            else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
+            S += r.g * Lv;
+            if (STAT == ANTS_STAT_ML && n > 0.f)
+              T += (double)n * log(Lv > G.lfloor ? Lv : G.lfloor);
           }
         }
+        S = gsum(S, lgs, lane);
+        double Dv = __builtin_huge_val();
+        if constexpr (STAT == ANTS_STAT_ML) {
+          T = gsum(T, lgs, lane);
+          if (ok && S > 0.0) Dv = N * log(S) - T;
+        } else {
+          double Q = 0.0;
+          if (ok && S > 0.0) {
+            const double Aa = N / S;
+            for (int p = sub; p < na; p += 1 << lgs) {
+              const float n = recA[p].z;
+              const SensorRec64 r = rec64[p];
+              double Lv;
+              if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
+              else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
+              const double mu = Aa * r.g * Lv;
+              const double dd = (double)n - mu;
+              Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+            }
+          }
+          Q = gsum(Q, lgs, lane);
+          if (ok && S > 0.0) Dv = Q;
+        }
+        if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
         double v1 = Dv;
         int j1 = j;
         wargmin_d(v1, j1);
         const bool fin = v1 < __builtin_huge_val();
         // candidates are listed in increasing node index, so an earlier
-        // chunk's winner keeps priority on equal values
-        int nsame = __popcll(__ballot(fin && Dv == v1));
+        // pass's winner keeps priority on equal values
+        const int nsame = __popcll(__ballot(fin && Dv == v1 && sub == 0));
         if (v1 < bestd) {
           bestd = v1;
           jd = j1;
@@ -875,15 +920,15 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         }
       }
       nfp += ncand;
-      win = bestd < __builtin_huge_val() ? jd : -1;
-      win = uni(win);
+      win = uni(bestd < __builtin_huge_val() ? jd : -1);
     }
     if (io.path && lane == 0 && k < G.K) io.path[e * G.K + k] = win;
     if (win < 0) {
       status |= ANTS_EV_NO_VALID_NODE;
     } else {
       if (tie) status |= ANTS_EV_TIE;
-      int jx = win % G.nx, jy = (win / G.nx) % G.ny, jz = win / (G.nx * G.ny);
+      const int pk = uni((int)nodeidx[win]);
+      const int jx = pk & G.mskx, jy = (pk >> G.shy) & G.msky, jz = pk >> G.shz;
       cx = uni(cx + (double)(jx - G.hx) * sx);
       cy = uni(cy + (double)(jy - G.hy) * sy);
       cz = uni(cz + (double)(jz - G.hz) * sz);
@@ -964,8 +1009,7 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwb = blockDim.x >> 6;
   unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
-  fill_nodeidx(G, wave_lds<KIND, NT>(wbase, L, G).nodeidx, 64 * NT, lane0);
-  wave_sync_lds();
+  wave_setup<KIND, NT>(wbase, L, G, lane0);
   int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
   for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
     const int64_t e = io.list ? (int64_t)io.list[w] : w;
@@ -1056,7 +1100,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>()))) cg_multi_kernel(M
   for (;;) {
     int item = 0;
     if (lane0 == 0) item = atomicAdd(P.counter, 1);
-    item = uni(__shfl(item, 0));
+    item = lane_val(item, 0);
     if (item >= P.n_items) break;
     int lo = 0, hi = P.n_chunks;
     while (hi - lo > 1) {
@@ -1069,8 +1113,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>()))) cg_multi_kernel(M
     const SetDesc& sd = P.sets[ch.set];
     if (ch.set != cur_set) {
       cur_set = ch.set;
-      fill_nodeidx(sd.G, wave_lds<KIND, NT>(wbase, sd.L, sd.G).nodeidx, 64 * NT, lane0);
-      wave_sync_lds();
+      wave_setup<KIND, NT>(wbase, sd.L, sd.G, lane0);
     }
     IoP io = P.out;
     io.sig = ch.sig;

@@ -31,30 +31,39 @@ __device__ __forceinline__ void bweights64(double t, double b[4]) {
   b[3] = t3 * (1.0 / 6.0);
 }
 
+// Offset of a sensor's FP64 B-spline coefficients in c64.
 template <int KIND>
-__device__ __forceinline__ double lrf64(const DevLrf& L, int a, double x, double y, double z) {
+__device__ __forceinline__ int coef_off64(const DevLrf& L, int a) {
+  if constexpr (KIND == ANTS_LRF_AXIAL) return L.tab[a] * L.nc0;
+  else if constexpr (KIND == ANTS_LRF_XY) return L.tab[a] * L.nc0 * L.nc1;
+  else return 0;
+}
+
+// FP64 LRF at (x, y, z) of a sensor at (X, Y) whose coefficients start at
+// c64 + coff.
+template <int KIND>
+__device__ __forceinline__ double lrf64s(const DevLrf& L, double X, double Y, int coff, double x,
+                                         double y, double z) {
   double v = 0.0;
   if constexpr (KIND == ANTS_LRF_AXIAL) {
-    double dx = x - L.X[a], dy = y - L.Y[a];
+    double dx = x - X, dy = y - Y;
     double r = sqrt(dx * dx + dy * dy);
     int m;
     double t, b[4];
     if (!locate64(r, L.nb0, L.lo0, L.hi0, L.d0, m, t)) return 0.0;
     bweights64(t, b);
-    const double* c = L.c64 + (size_t)L.tab[a] * L.nc0 + m;
+    const double* c = L.c64 + coff + m;
     v = c[0] * b[0] + c[1] * b[1] + c[2] * b[2] + c[3] * b[3];
   } else {
     double u, w;
-    const double* c;
+    const double* c = L.c64 + coff;
     if constexpr (KIND == ANTS_LRF_RZ) {
-      double dx = x - L.X[a], dy = y - L.Y[a];
+      double dx = x - X, dy = y - Y;
       u = sqrt(dx * dx + dy * dy);
       w = z;
-      c = L.c64;
     } else {
       u = x;
       w = y;
-      c = L.c64 + (size_t)L.tab[a] * L.nc0 * L.nc1;
     }
     int m0, m1;
     double t0, t1, b0[4], b1[4];
@@ -69,6 +78,10 @@ __device__ __forceinline__ double lrf64(const DevLrf& L, int a, double x, double
     }
   }
   return v > 0.0 ? v : 0.0;
+}
+template <int KIND>
+__device__ __forceinline__ double lrf64(const DevLrf& L, int a, double x, double y, double z) {
+  return lrf64s<KIND>(L, L.X[a], L.Y[a], coef_off64<KIND>(L, a), x, y, z);
 }
 
 __device__ __forceinline__ bool in_domain(double u, double lo, double hi) {

@@ -161,6 +161,65 @@ def timed(fn, steps, warmup, stream):
     return wall, ev_ms
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_kernel_rz_hex37_10M_traffic.json")
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1602_07247_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from
+    the committed counter summary, or None when the kernel sources changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t["kernels"].get(kernel, {}).get("traffic")
+
+
+def seed_iterations(s, g):
+    """Iterations each event runs in the seeded refinement, from the network's
+    log-variance s: the smallest K in [kmin, kmax] whose first step (final
+    step divided K - 1 times by the shrink factor) covers kappa * sigma on
+    every axis with more than one node; kmax when sigma is not finite."""
+    sf = []
+    for a in range(3):
+        f = g.step0[a]
+        for _ in range(1, g.iterations):
+            f *= g.shrink
+        sf.append(f)
+    st = np.empty((g.seed_kmax, 3))
+    cur = list(sf)
+    for k in range(g.seed_kmax):
+        st[k] = cur
+        cur = [c / g.shrink for c in cur]
+    sg = np.exp(0.5 * np.asarray(s, np.float64)) * g.seed_kappa
+    kk = np.full(sg.shape, g.seed_kmax - 1)
+    done = ~np.isfinite(sg)
+    for k in range(g.seed_kmin - 1, g.seed_kmax - 1):
+        ok = np.ones(sg.shape, bool)
+        for a in range(3):
+            if g.nodes[a] > 1:
+                ok &= ~(st[k, a] < sg * g.seed_scale[a])
+        sel = ok & ~done
+        kk[sel] = k
+        done |= sel
+    return kk + 1
+
+
 def sigma_xy(out, truth):
     t = truth.cpu().numpy()
     dx = out["x"].cpu().numpy() - t[:, 0]
@@ -204,6 +263,11 @@ def main():
     flops = n * evals * FLOP_PER_EVAL_ML
     achieved = flops / (ev_p * 1e-3) / 1e12
     sp = sigma_xy(out_plain, truth)
+    roof_plain = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                  "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                  "traffic": profiled_traffic("plain"),
+                  "kernel": "cg_kernel<RZ,ML,NT=6,SL=1> (7x7x7 plain grid)", "kernel_ms": ev_p,
+                  "flop_per_launch": flops}
     rec = {
         "metric": "events/s reconstructed (plain grid vs NN-seeded) at equal sigma_xy, 1 MI355X",
         "value": n / wall_p, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -214,11 +278,9 @@ def main():
                                "NN seed + 3x3x3 refinement with chi2/ndf>2 fallback; ML",
                    "events": n, "sensors": 37},
         "plain": {"events_per_s": n / wall_p, "ms_per_step": 1e3 * wall_p,
-                  "sigma_xy_mm": sp[0], "sigma_xy_fiducial_mm": sp[1], "p95_radial_mm": sp[2]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "cg_kernel<RZ,ML,NT=6,SL=1> (plain grid)", "kernel_ms": ev_p,
-                     "flop_per_launch": flops},
+                  "sigma_xy_mm": sp[0], "sigma_xy_fiducial_mm": sp[1], "p95_radial_mm": sp[2],
+                  "roofline": roof_plain},
+        "roofline": roof_plain,
     }
 
     if not args.plain_only:
@@ -243,6 +305,27 @@ def main():
         nfb = int(nfb_box["n"].item())
         # network forward alone (share of the seeded step)
         _, ev_mlp = timed(lambda: net.forward(lrf, sig, stream=stream), 2, 1, stream)
+        # the step's dominant kernel: the 3x3x3 refinement (one node tile),
+        # timed alone from the same seeds; FLOP from each event's iterations
+        import torch
+        pred = net.forward(lrf, sig, stream=stream)
+        seeds = pred.clone()
+        seeds[:, :3] = (pred[:, :3] * torch.tensor(W.SEED_POS_SCALE, device=pred.device)
+                        + torch.tensor(W.SEED_POS_OFFSET, device=pred.device))
+        seeds = seeds.contiguous()
+        out_r = ants.alloc_out(n)
+        _, ev_r = timed(lambda: ants.reconstruct(lrf, refine, sig, seeds=seeds, out=out_r,
+                                                 stream=stream), args.steps, 1, stream)
+        rg = W.seeded_refine_grid(kappa=args.kappa)
+        k_ev = seed_iterations(pred[:, 3].cpu().numpy(), rg)
+        flops_r = int(k_ev.sum()) * int(np.prod(rg.nodes)) * 37 * FLOP_PER_EVAL_ML
+        ach_r = flops_r / (ev_r * 1e-3) / 1e12
+        rec["roofline"] = {"bound": "alu", "achieved": ach_r, "peak": PEAK_FP32_TFLOPS,
+                           "unit": "TFLOP/s", "frac": ach_r / PEAK_FP32_TFLOPS,
+                           "traffic": profiled_traffic("refine"),
+                           "kernel": "cg_kernel<RZ,ML,NT=1,SL=1> (3x3x3 seeded refinement)",
+                           "kernel_ms": ev_r, "flop_per_launch": flops_r,
+                           "mean_iterations": float(k_ev.mean())}
         rec["value"] = n / wall_s
         rec["ms_per_step"] = 1e3 * wall_s
         rec["seeded"] = {"events_per_s": n / wall_s, "ms_per_step": 1e3 * wall_s,

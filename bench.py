@@ -44,8 +44,8 @@ def parse():
     ap.add_argument("--events", type=int, default=10_000_000)
     ap.add_argument("--train-events", type=int, default=5_000_000)
     ap.add_argument("--val-events", type=int, default=500_000)
-    ap.add_argument("--epochs", type=int, default=6)
-    ap.add_argument("--kappa", type=float, default=1.0)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--kappa", type=float, default=0.5)
     ap.add_argument("--plain-only", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=24_000,
                     help="events for the oracle CPU baseline (0 = skip)")
@@ -289,7 +289,7 @@ def main():
                        pos_offset=W.SEED_POS_OFFSET)
         t0 = time.perf_counter()
         losses = net.train(lrf, wl.events, args.train_events, args.val_events, batch=4096,
-                           epochs=args.epochs, lr=2e-3, lr_decay=0.7, seed=args.seed + 1)
+                           epochs=args.epochs, lr=2e-3, lr_decay=0.85, seed=args.seed + 1)
         t_train = time.perf_counter() - t0
         refine = ants.grid_cfg(W.seeded_refine_grid(kappa=args.kappa))
         out_seed = ants.alloc_out(n)

@@ -271,15 +271,18 @@ def chunk_stream(total: int, seed_offset: int = 0, median=1e4, sigma_ln=1.0,
     return np.asarray(sizes, np.int64), np.asarray(geoms, np.int32)
 
 
-def seeded_refine_grid(kappa: float = 1.0, kmin: int = 2, kmax: int = 8) -> GridCfg:
+# Network targets: (position - offset) / scale.  One scale on every axis, so
+# that the single predicted log-variance describes all three (the seeds'
+# errors are about equal in x, y and z for the 37-sensor r-z detector).
+SEED_POS_SCALE = (90.0, 90.0, 90.0)
+SEED_POS_OFFSET = (0.0, 0.0, 25.0)
+
+
+def seeded_refine_grid(kappa: float = 0.5, kmin: int = 2, kmax: int = 8) -> GridCfg:
     """Refinement grid of the learned-seed path: 3 x 3 x 3 nodes started at
     the seed, ending on the plain grid's final step (workload 2: 10, 10,
     50/6 mm halved over 8 iterations), with the iteration count chosen per
     event from the seed's predicted spread (kappa * sigma)."""
     return GridCfg((3, 3, 3), 8, 0.5, (10.0, 10.0, 50.0 / 6.0), 25.0, stat=0, start=2,
                    seed_steps=1, seed_kappa=kappa, seed_kmin=kmin, seed_kmax=kmax,
-                   seed_scale=(90.0, 90.0, 25.0))
-
-
-SEED_POS_SCALE = (90.0, 90.0, 25.0)
-SEED_POS_OFFSET = (0.0, 0.0, 25.0)
+                   seed_scale=SEED_POS_SCALE)

@@ -184,7 +184,25 @@ hipError_t launch_sum_f32(const float* v, int64_t n, float scale, float* out, hi
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, __bf16* pb, int64_t n,
                        const AdamP& A, hipStream_t s);
 hipError_t launch_to_bf16(const float* p, __bf16* pb, int64_t n, hipStream_t s);
-hipError_t launch_seeds(const float* Y, int64_t n, const HeadP& H, float* seeds, hipStream_t s);
+// Fused inference (hidden width 256): normalisation, every layer and the
+// output layer in one kernel; out = raw outputs (seeds = 0) or seeds in mm
+// with the log-variance (seeds = 1).
+constexpr int kFwdMaxLayers = 4;
+struct FwdP {
+  const float* sig;
+  int64_t ld;
+  const int32_t* col;
+  int na;
+  int64_t n;
+  int kin;                              // padded input width (multiple of 32, <= 256)
+  int layers;                           // hidden layers
+  const __bf16* W[kFwdMaxLayers + 1];   // BF16 weights [out][in], output layer last
+  const float* b[kFwdMaxLayers + 1];    // FP32 biases
+  float* out;                           // [n][4]
+  int seeds;
+  float scale[3], offset[3];
+};
+hipError_t launch_mlp_fwd(const FwdP& P, hipStream_t s);
 
 // Launch the contracting-grid kernel; returns a hipError_t.
 hipError_t launch_grid(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t stream,

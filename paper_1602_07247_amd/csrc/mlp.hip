@@ -104,6 +104,146 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmP P) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: one block of four waves runs FR events through every
+// layer with the activations held in LDS (two buffers, BF16, rows padded by
+// 8 elements); weights are read from global memory (L2-resident) straight
+// into the MFMA operand registers, one k-step ahead.  Each product is the
+// same sequence of 16x16x32 MFMAs as in gemm_kernel (FP32 accumulators from
+// zero, k ascending), so hidden activations and outputs equal that path's.
+// Hidden width 256: wave w owns output columns 64w..64w+63 of every layer.
+constexpr int FR = 64, FH = 256, FPITCH = FH + 8;
+
+// kernel-argument arrays indexed with constants only (no private copies)
+__device__ __forceinline__ const __bf16* fwd_w(const FwdP& P, int l) {
+  return l == 0 ? P.W[0] : l == 1 ? P.W[1] : l == 2 ? P.W[2] : l == 3 ? P.W[3] : P.W[4];
+}
+__device__ __forceinline__ const float* fwd_b(const FwdP& P, int l) {
+  return l == 0 ? P.b[0] : l == 1 ? P.b[1] : l == 2 ? P.b[2] : l == 3 ? P.b[3] : P.b[4];
+}
+
+__global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
+  extern __shared__ __align__(16) __bf16 fsm[];
+  __bf16* buf0 = fsm;                    // [FR][FPITCH]
+  __bf16* buf1 = fsm + FR * FPITCH;      // [FR][FPITCH]; inputs use its first rows
+  __shared__ float scl[FR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t e0 = (int64_t)blockIdx.x * FR;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+
+  // inputs x = bf16(n_a * (n_active / N)), as normalize_kernel
+  if (tid < FR) {
+    const int64_t e = e0 + tid;
+    float sc = 0.f;
+    if (e < P.n) {
+      const float* row = P.sig + e * P.ld;
+      float N = 0.f;
+      bool ok = true;
+      for (int a = 0; a < P.na; ++a) {
+        const float v = row[P.col[a]];
+        if (!(v >= 0.f) || !(v < __builtin_huge_valf())) ok = false;
+        N += v;
+      }
+      ok = ok && N > 0.f;
+      sc = ok ? (float)P.na / N : 0.f;
+    }
+    scl[tid] = sc;
+  }
+  __syncthreads();
+  const int kin = P.kin, pin = kin + 8;
+  for (int i = tid; i < FR * kin; i += 256) {
+    const int r = i / kin, a = i - r * kin;
+    const int64_t e = e0 + r;
+    __bf16 v = (__bf16)0.f;
+    if (e < P.n && a < P.na && scl[r] > 0.f) v = to_bf16(P.sig[e * P.ld + P.col[a]] * scl[r]);
+    buf1[r * pin + a] = v;
+  }
+  __syncthreads();
+
+  const __bf16* in = buf1;
+  int pitch = pin, din = kin;
+  __bf16* outb = buf0;
+#pragma unroll
+  for (int l = 0; l < kFwdMaxLayers; ++l) {
+    if (l >= P.layers) break;
+    const __bf16* W = fwd_w(P, l);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    bf16x8 b[4], bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *(const bf16x8*)(W + (int64_t)(wave * 64 + j * 16 + fr) * din + fk);
+    for (int k0 = 0; k0 < din; k0 += 32) {
+      if (k0 + 32 < din) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          bn[j] = *(const bf16x8*)(W + (int64_t)(wave * 64 + j * 16 + fr) * din + k0 + 32 + fk);
+      }
+      bf16x8 a[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)(in + (i * 16 + fr) * pitch + k0 + fk);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = bn[j];
+    }
+    // bias, ReLU, BF16 into the other buffer
+    const float* bias = fwd_b(P, l);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = wave * 64 + j * 16 + fr;
+      const float bc = bias[c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          outb[(i * 16 + (lane >> 4) * 4 + r) * FPITCH + c] = to_bf16(fmaxf(acc[i][j][r] + bc, 0.f));
+    }
+    __syncthreads();
+    in = outb;
+    pitch = FPITCH;
+    din = FH;
+    outb = (outb == buf0) ? buf1 : buf0;
+  }
+
+  // output layer (4 rows of weights, padded to one 16-column tile): wave w
+  // takes events 16w..16w+15
+  {
+    const __bf16* W = fwd_w(P, P.layers);
+    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < FH; k0 += 32) {
+      bf16x8 bb;
+      if (fr < 4) {
+        bb = *(const bf16x8*)(W + (int64_t)fr * FH + k0 + fk);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bb[q] = (__bf16)0.f;
+      }
+      const bf16x8 a = *(const bf16x8*)(in + (wave * 16 + fr) * FPITCH + k0 + fk);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+    }
+    if (fr < 4) {
+      const float bc = fwd_b(P, P.layers)[fr];
+      const float sc = fr == 0 ? P.scale[0] : fr == 1 ? P.scale[1] : P.scale[2];
+      const float of = fr == 0 ? P.offset[0] : fr == 1 ? P.offset[1] : P.offset[2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t e = e0 + wave * 16 + (lane >> 4) * 4 + r;
+        if (e < P.n) {
+          const float y = acc[r] + bc;
+          P.out[e * 4 + fr] = (P.seeds && fr < 3) ? of + sc * y : y;
+        }
+      }
+    }
+  }
+}
+
 // x_hat = bf16(n_a * (n_active / N)) for the active sensors, zero padding
 __global__ void normalize_kernel(const float* sig, int64_t ld, const int32_t* col, int na,
                                  int64_t n, int kin, __bf16* X) {
@@ -226,13 +366,6 @@ __global__ void to_bf16_kernel(const float* p, __bf16* pb, int64_t n) {
 }
 
 // network output (normalised) -> seed in mm: pos = offset + scale * y, s kept
-__global__ void seeds_kernel(const float* Y, int64_t n, HeadP H, float* seeds) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) seeds[e * 4 + c] = H.offset[c] + H.scale[c] * Y[e * 4 + c];
-  seeds[e * 4 + 3] = Y[e * 4 + 3];
-}
 
 inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
@@ -242,6 +375,17 @@ hipError_t launch_gemm(const GemmP& P, hipStream_t s) {
   if (P.M <= 0 || P.N <= 0) return hipSuccess;
   dim3 g((unsigned)((P.N + BN - 1) / BN), (unsigned)((P.M + BM - 1) / BM));
   hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_mlp_fwd(const FwdP& P, hipStream_t s) {
+  if (P.n <= 0) return hipSuccess;
+  if (P.kin > FH || P.kin % 32 || P.layers < 1 || P.layers > kFwdMaxLayers)
+    return hipErrorInvalidValue;
+  const size_t smem = (size_t)2 * FR * FPITCH * sizeof(__bf16);
+  hipError_t e = hipFuncSetAttribute((const void*)mlp_fwd_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlp_fwd_kernel, dim3((unsigned)((P.n + FR - 1) / FR)), dim3(256), smem, s, P);
   return hipGetLastError();
 }
 hipError_t launch_normalize(const float* sig, int64_t ld, const int32_t* col, int na, int64_t n,
@@ -285,11 +429,6 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, __bf16* pb,
 }
 hipError_t launch_to_bf16(const float* p, __bf16* pb, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(to_bf16_kernel, dim3(nb(n)), dim3(256), 0, s, p, pb, n);
-  return hipGetLastError();
-}
-hipError_t launch_seeds(const float* Y, int64_t n, const HeadP& H, float* seeds, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(seeds_kernel, dim3(nb(n)), dim3(256), 0, s, Y, n, H, seeds);
   return hipGetLastError();
 }
 

@@ -14,7 +14,6 @@ using namespace ants;
 namespace {
 
 constexpr int kMaxBatch = 65536;
-constexpr int64_t kFwdChunk = 1 << 20;   // events per forward chunk
 
 struct Dev {
   std::vector<void*> bufs;
@@ -117,6 +116,31 @@ hipError_t forward_rows(ants_mlp* M, const ants_lrfset* S, const float* sig, int
     e = launch_gemm(P, s);
   }
   return e;
+}
+
+// Fused inference over n events (no workspace): raw outputs or seeds.
+hipError_t infer(const ants_mlp* M, const ants_lrfset* S, const float* sig, int64_t n, float* out,
+                 bool seeds, hipStream_t s) {
+  FwdP P;
+  memset(&P, 0, sizeof(P));
+  P.sig = sig;
+  P.ld = S->ns;
+  P.col = S->d.col;
+  P.na = S->d.na;
+  P.n = n;
+  P.kin = M->nin_pad;
+  P.layers = M->layers;
+  for (int l = 0; l <= M->layers; ++l) {
+    P.W[l] = M->pb + M->offW[l];
+    P.b[l] = M->p + M->offB[l];
+  }
+  P.out = out;
+  P.seeds = seeds ? 1 : 0;
+  for (int a = 0; a < 3; ++a) {
+    P.scale[a] = M->head.scale[a];
+    P.offset[a] = M->head.offset[a];
+  }
+  return launch_mlp_fwd(P, s);
 }
 
 // loss and gradient of the mean loss over n rows (forward must have run)
@@ -318,17 +342,8 @@ ants_status ants_mlp_forward(ants_mlp* M, const ants_lrfset* S, int64_t n, const
   if (n == 0) return ANTS_OK;
   if (!d_signals || !d_pred) return set_error(ANTS_E_ARG, "NULL device pointer");
   hipStream_t s = (hipStream_t)hip_stream;
-  const int64_t chunk = n < kFwdChunk ? n : kFwdChunk;
-  st = mlp_workspace(M, chunk);
-  if (st != ANTS_OK) return st;
-  for (int64_t b = 0; b < n; b += chunk) {
-    int64_t r = n - b < chunk ? n - b : chunk;
-    hipError_t e = forward_rows(M, S, d_signals + b * S->ns, r, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_pred + b * 4, M->Y, r * 4 * sizeof(float), hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_error(e, "ants_mlp_forward");
-  }
-  return ANTS_OK;
+  hipError_t e = infer(M, S, d_signals, n, d_pred, false, s);
+  return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_mlp_forward");
 }
 
 ants_status ants_mlp_grad(ants_mlp* M, const ants_lrfset* S, int64_t n, const float* d_signals,
@@ -532,16 +547,8 @@ ants_status ants_reconstruct_seeded(ants_lrfset* S, ants_mlp* M, const ants_grid
   if (!seeds && e == hipSuccess) {
     e = ensure(&S->ws_seeds, &S->ws_seeds_bytes, (size_t)n * 16);
     if (e == hipSuccess) {
-      const int64_t chunk = n < kFwdChunk ? n : kFwdChunk;
-      st = mlp_workspace(M, chunk);
-      if (st != ANTS_OK) return st;
-      float* sd = (float*)S->ws_seeds;
-      for (int64_t b = 0; b < n && e == hipSuccess; b += chunk) {
-        int64_t r = n - b < chunk ? n - b : chunk;
-        e = forward_rows(M, S, d_signals + b * S->ns, r, s);
-        if (e == hipSuccess) e = launch_seeds(M->Y, r, M->head, sd + b * 4, s);
-      }
-      seeds = sd;
+      e = infer(M, S, d_signals, n, (float*)S->ws_seeds, true, s);
+      seeds = (float*)S->ws_seeds;
     }
   }
   if (e != hipSuccess) return hip_error(e, "ants_reconstruct_seeded (seeds)");

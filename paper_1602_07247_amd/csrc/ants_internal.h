@@ -29,9 +29,13 @@ __host__ __device__ constexpr int node_tiles(int nn) {
 // during the FP64 decisions, and the plane weights (16 B FP32 + 32 B FP64
 // + 4 B first z-coefficient per plane); 16-bit candidate list and
 // node-index table of 64 entries per node tile; the per-axis steps for
-// each iteration count a seed may select.
-inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt) {
+// each iteration count a seed may select; for the column-factored r-z
+// screen (fact_nxy = nodes per z-plane, 0 = not used) the partial sums of
+// every (column, sensor group) and a lane -> (column, group) table.
+inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt,
+                          int fact_nxy = 0) {
   int b = 64 * na + 256 * nt + 24 * kMaxSeedSteps;
+  if (fact_nxy > 0) b += 8 * nz * (fact_nxy > 64 ? fact_nxy : 64) + 128;
   if (kind == ANTS_LRF_RZ) {
     const int zt = 16 * nz * nintp, zr = 8 * nz * nc0;
     b += ((zt > zr ? zt : zr) + 15) / 16 * 16 + 52 * nz;

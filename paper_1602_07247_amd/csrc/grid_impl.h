@@ -265,8 +265,10 @@ struct WaveLds {
   uint16_t* cand;      // candidate list
   uint16_t* nodeidx;   // packed node indices
   double* sstep;       // seeded refinement: steps per axis after k quotients
+  float* fscr;         // factored r-z screen: partial sums [group][column][plane][2]
+  uint16_t* lanecg;    // factored r-z screen: column | group << 8 per lane
 };
-template <int KIND, int NT>
+template <int KIND, int NT, bool FA = false>
 __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& L,
                                             const GridP& G) {
   WaveLds w;
@@ -285,20 +287,31 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& 
   w.pw32 = w.ztab + zq;
   w.pw64 = (double*)(w.pw32 + nzp);
   w.sstep = w.pw64 + 4 * nzp;
-  w.pm = (int*)(w.sstep + 3 * kMaxSeedSteps);
+  w.fscr = (float*)(w.sstep + 3 * kMaxSeedSteps);
+  const int nxy = G.nx * G.ny;
+  w.pm = (int*)(w.fscr + (FA ? 2 * G.nz * (nxy > 64 ? nxy : 64) : 0));
   w.cand = (uint16_t*)(w.pm + nzp);
   w.nodeidx = w.cand + 64 * NT;
+  w.lanecg = w.nodeidx + 64 * NT;
   return w;
 }
 
 // Per-wave set-up: node index table and, for seeded refinement, the final
 // step divided by the shrink factor k times (iterated quotients), k <
 // kMaxSeedSteps, per axis.
-template <int KIND, int NT>
+template <int KIND, int NT, bool FA = false>
 __device__ __forceinline__ void wave_setup(unsigned char* wbase, const DevLrf& L, const GridP& G,
                                            int lane) {
-  const WaveLds w = wave_lds<KIND, NT>(wbase, L, G);
+  const WaveLds w = wave_lds<KIND, NT, FA>(wbase, L, G);
   fill_nodeidx(G, w.nodeidx, 64 * NT, lane);
+  if constexpr (FA) {
+    // factored screen: lane -> (column of the x-y lattice, sensor group);
+    // with more than 64 columns one group and several passes
+    const int nxy = G.nx * G.ny;
+    const int c = nxy <= 64 ? lane % nxy : lane;
+    const int g = nxy <= 64 ? lane / nxy : 0;
+    w.lanecg[lane] = (uint16_t)(c | (g << 8));
+  }
   if (G.seed_steps && lane < 3) {
     double s = G.sfinal[lane];
     for (int k = 0; k < kMaxSeedSteps; ++k) {
@@ -360,11 +373,12 @@ __device__ __forceinline__ float log2_1p(float x) {
 
 // One event on one wavefront.  btab: block-shared tables (LDS); wbase: this
 // wave's LDS region (sensor records, r-z plane tables, candidate list).
-template <int KIND, int STAT, int NT, int SL, bool NN>
+template <int KIND, int STAT, int NT, int SL, bool NN, int FZ>
 __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, const IoP& io,
                                               const int64_t e, const float4* btab,
                                               unsigned char* wbase, const int lane) {
-  const WaveLds W = wave_lds<KIND, NT>(wbase, L, G);
+  constexpr bool FA = FZ > 0;
+  const WaveLds W = wave_lds<KIND, NT, FA>(wbase, L, G);
   float4* recA = W.recA;
   float4* recB = W.recB;
   SensorRec64* rec64 = W.rec64;
@@ -610,7 +624,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     // grids of at most 32 nodes split the sensors between the two halves of
     // the wave: lanes l and l + 32 both hold node l, each sums over every
     // other sensor, and the halves add their sums
-    const bool split = NT == 1 && G.nn <= 32;
+    const bool split = !FA && NT == 1 && G.nn <= 32;
     const int hb = split ? (lk >> 5) : 0;
     const int pstep = split ? 2 : 1;
     NodeF<KIND> nd[NT];
@@ -629,47 +643,131 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       float dS[NT], T[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) { dS[t] = 0.f; T[t] = 0.f; }
-      int p = 0;
-      for (; p + pstep <= npos; p += pstep) {
-        float4 A = recA[p + hb], B = recB[p + hb];
-        int tofs = __float_as_int(B.z);
+      if constexpr (FA) {
+        // r-z, 2 to 8 z-planes: the distance from a sensor depends on the
+        // node's x-y column only, so lanes take (column, sensor group) and
+        // evaluate every plane from one distance; the groups' partial sums
+        // are then added per node through LDS
+        const int nxy = G.nx * G.ny;
+        constexpr int nz = FZ;   // equals G.nz
+        const int lcg = W.lanecg[lk];
+        const int c0 = lcg & 255, grp = lcg >> 8;
+        const int ngrp = nxy <= 64 ? 64 / nxy : 1;
+        float* scr = W.fscr;
+        for (int cbase = 0; cbase < nxy; cbase += 64) {
+          const int c = c0 + cbase;
+          if (c < nxy && grp < ngrp) {
+            const int pk = nodeidx[c];   // node c: column c on the first plane
+            const int jx = pk & G.mskx, jy = (pk >> G.shy) & G.msky;
+            const float ox = (float)((double)(jx - G.hx) * sx * L.inv_d0);
+            const float oy = (float)((double)(jy - G.hy) * sy * L.inv_d0);
+            float aS[nz], aT[nz];
+#pragma unroll
+            for (int q = 0; q < nz; ++q) { aS[q] = 0.f; aT[q] = 0.f; }
+            const int pstride = L.nintp;
+            for (int p = grp; p < npos; p += ngrp) {
+              const float4 A = recA[p], B = recB[p];
+              const float dx = ox - A.x, dy = oy - A.y;
+              const float v = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+              const int m = (int)fminf(v, (float)nlast);
+              const float tt = __builtin_amdgcn_fractf(v);
+              const float4* tp = ztab + m;
+              float4 cf[nz];
+#pragma unroll
+              for (int q = 0; q < nz; ++q) cf[q] = tp[q * pstride];
+#pragma unroll
+              for (int q = 0; q < nz; ++q) {
+                float Lv = fmaf(fmaf(fmaf(cf[q].w, tt, cf[q].z), tt, cf[q].y), tt, cf[q].x);
+                if (!NN) Lv = fmaxf(Lv, 0.f);
+                aS[q] = fmaf(B.x, Lv - B.y, aS[q]);
+                aT[q] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), aT[q]);
+              }
+            }
+            for (int p = npos + grp; p < na; p += ngrp) {
+              const float4 A = recA[p], B = recB[p];
+              const float dx = ox - A.x, dy = oy - A.y;
+              const float v = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+              const int m = (int)fminf(v, (float)nlast);
+              const float tt = __builtin_amdgcn_fractf(v);
+              const float4* tp = ztab + m;
+              float4 cf[nz];
+#pragma unroll
+              for (int q = 0; q < nz; ++q) cf[q] = tp[q * pstride];
+#pragma unroll
+              for (int q = 0; q < nz; ++q) {
+                float Lv = fmaf(fmaf(fmaf(cf[q].w, tt, cf[q].z), tt, cf[q].y), tt, cf[q].x);
+                if (!NN) Lv = fmaxf(Lv, 0.f);
+                aS[q] = fmaf(B.x, Lv - B.y, aS[q]);
+              }
+            }
+            float* o = scr + (grp * nxy + c) * nz * 2;
+#pragma unroll
+            for (int q = 0; q < nz; ++q) {
+              o[2 * q] = aS[q];
+              o[2 * q + 1] = aT[q];
+            }
+          }
+        }
+        wave_sync_lds();
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
-          dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
-          T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
+          const int j = t * 64 + lk;
+          if (j < G.nn) {
+            const int pk = nodeidx[j];
+            const int c = ((pk >> G.shy) & G.msky) * G.nx + (pk & G.mskx);
+            const float* o = scr + (c * nz + (pk >> G.shz)) * 2;
+            float a = 0.f, b = 0.f;
+            for (int g = 0; g < ngrp; ++g) {
+              a += o[g * nxy * nz * 2];
+              b += o[g * nxy * nz * 2 + 1];
+            }
+            dS[t] = a;
+            T[t] = b;
+          }
         }
-      }
-      if (split && p < npos) {
-        // odd count: the first half takes the last sensor, the second adds
-        // zero (or NaN where the first half's term is infinite already)
-        float4 A = recA[p], B = recB[p];
-        const float w = hb ? 0.f : 1.f;
-        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
-                                   finv, nlast);
-        dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
-        T[0] = fmaf(A.z * w, __builtin_amdgcn_logf(Lv * A.w), T[0]);
-      }
-      p = npos;
-      for (; p + pstep <= na; p += pstep) {
-        float4 A = recA[p + hb], B = recB[p + hb];
-        int tofs = __float_as_int(B.z);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
-          dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+      } else {
+        int p = 0;
+        for (; p + pstep <= npos; p += pstep) {
+          float4 A = recA[p + hb], B = recB[p + hb];
+          int tofs = __float_as_int(B.z);
+  #pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+            T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
+          }
         }
-      }
-      if (split && p < na) {
-        float4 A = recA[p], B = recB[p];
-        const float w = hb ? 0.f : 1.f;
-        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
-                                   finv, nlast);
-        dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
-      }
-      if (split) {
-        dS[0] += __shfl_xor(dS[0], 32);
-        T[0] += __shfl_xor(T[0], 32);
+        if (split && p < npos) {
+          // odd count: the first half takes the last sensor, the second adds
+          // zero (or NaN where the first half's term is infinite already)
+          float4 A = recA[p], B = recB[p];
+          const float w = hb ? 0.f : 1.f;
+          float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+                                     finv, nlast);
+          dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
+          T[0] = fmaf(A.z * w, __builtin_amdgcn_logf(Lv * A.w), T[0]);
+        }
+        p = npos;
+        for (; p + pstep <= na; p += pstep) {
+          float4 A = recA[p + hb], B = recB[p + hb];
+          int tofs = __float_as_int(B.z);
+  #pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+          }
+        }
+        if (split && p < na) {
+          float4 A = recA[p], B = recB[p];
+          const float w = hb ? 0.f : 1.f;
+          float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+                                     finv, nlast);
+          dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
+        }
+        if (split) {
+          dS[0] += __shfl_xor(dS[0], 32);
+          T[0] += __shfl_xor(T[0], 32);
+        }
       }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -997,7 +1095,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 template <int KIND, int NT>
 constexpr int waves_per_eu() { return (KIND == ANTS_LRF_XY && NT >= 4) ? 2 : NT == 1 ? 4 : 3; }
 
-template <int KIND, int STAT, int NT, int SL, bool NN>
+template <int KIND, int STAT, int NT, int SL, bool NN, int FZ>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>())))
 cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, int btab_n) {
   extern __shared__ float4 smem4[];
@@ -1009,25 +1107,25 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwb = blockDim.x >> 6;
   unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
-  wave_setup<KIND, NT>(wbase, L, G, lane0);
+  wave_setup<KIND, NT, (FZ > 0)>(wbase, L, G, lane0);
   int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
   for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
     const int64_t e = io.list ? (int64_t)io.list[w] : w;
-    process_event<KIND, STAT, NT, SL, NN>(L, G, io, e, btab, wbase, opaque(lane0));
+    process_event<KIND, STAT, NT, SL, NN, FZ>(L, G, io, e, btab, wbase, opaque(lane0));
   }
 }
 
-template <int KIND, int STAT, int NT, int SL, bool NN>
+template <int KIND, int STAT, int NT, int SL, bool NN, int FZ = 0>
 hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t stream,
                     int max_blocks) {
   int btab_n = 0;
   if (KIND == ANTS_LRF_AXIAL) btab_n = L.ntab * L.nintp;
   if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
-  const int per_wave = wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT);
+  const int per_wave = wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT, FZ ? G.nx * G.ny : 0);
   size_t smem = (size_t)btab_n * 16 + (size_t)kWavesPerBlock * per_wave;
   int64_t nwork = io.n;
   int64_t blocks = (nwork + kWavesPerBlock - 1) / kWavesPerBlock;
-  auto kern = cg_kernel<KIND, STAT, NT, SL, NN>;
+  auto kern = cg_kernel<KIND, STAT, NT, SL, NN, FZ>;
   if (smem > 65536) {
     hipError_t st = hipFuncSetAttribute((const void*)kern,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -1048,8 +1146,25 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   return hipGetLastError();
 }
 
+// column-factored r-z screen for FZ z-planes
+template <int KIND, int STAT, int SL, bool NN, int FZ>
+hipError_t launch_fz(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
+  switch (node_tiles(G.nn)) {
+    case 1: return launch_t<KIND, STAT, 1, SL, NN, FZ>(L, G, io, s, mb);
+    case 2: return launch_t<KIND, STAT, 2, SL, NN, FZ>(L, G, io, s, mb);
+    case 4: return launch_t<KIND, STAT, 4, SL, NN, FZ>(L, G, io, s, mb);
+    case 6: return launch_t<KIND, STAT, 6, SL, NN, FZ>(L, G, io, s, mb);
+    default: return launch_t<KIND, STAT, 8, SL, NN, FZ>(L, G, io, s, mb);
+  }
+}
+
 template <int KIND, int STAT, int SL, bool NN>
 hipError_t launch_kss(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
+  if constexpr (KIND == ANTS_LRF_RZ && STAT == ANTS_STAT_ML && SL == 1) {
+    if (G.nz == 3) return launch_fz<KIND, STAT, SL, NN, 3>(L, G, io, s, mb);
+    if (G.nz == 5) return launch_fz<KIND, STAT, SL, NN, 5>(L, G, io, s, mb);
+    if (G.nz == 7) return launch_fz<KIND, STAT, SL, NN, 7>(L, G, io, s, mb);
+  }
   switch (node_tiles(G.nn)) {
     case 1: return launch_t<KIND, STAT, 1, SL, NN>(L, G, io, s, mb);
     case 2: return launch_t<KIND, STAT, 2, SL, NN>(L, G, io, s, mb);
@@ -1131,7 +1246,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>()))) cg_multi_kernel(M
     const int64_t e0 = (int64_t)(item - P.prefix[lo]) * P.T;
     const int64_t e1 = e0 + P.T < ch.n ? e0 + P.T : ch.n;
     for (int64_t e = e0; e < e1; ++e)
-      process_event<KIND, STAT, NT, SL, NN>(sd.L, sd.G, io, e, tb, wbase, opaque(lane0));
+      process_event<KIND, STAT, NT, SL, NN, 0>(sd.L, sd.G, io, e, tb, wbase, opaque(lane0));
   }
 }
 

@@ -61,10 +61,15 @@ def test_parity_against_oracle(ants, k, n, stat):
 @pytest.mark.parametrize("k,nodes,stat,n", [(0, (5, 5, 1), 0, 3_000), (0, (5, 5, 1), 1, 2_000),
                                              (0, (3, 3, 1), 0, 2_000), (1, (5, 5, 1), 0, 1_000),
                                              (1, (3, 3, 1), 1, 1_000), (2, (3, 3, 3), 0, 2_000),
-                                             (2, (3, 3, 3), 1, 1_000), (2, (5, 5, 1), 0, 1_000)])
+                                             (2, (3, 3, 3), 1, 1_000), (2, (5, 5, 1), 0, 1_000),
+                                             (2, (5, 5, 3), 0, 1_000), (2, (3, 3, 9), 0, 1_000),
+                                             (2, (9, 9, 3), 0, 500)])
 def test_parity_small_grids_split_sensor_loop(ants, k, nodes, stat, n):
     # grids of <= 32 nodes run the screen with the sensors split between the
-    # two halves of a wave (odd and even sensor counts, both statistics)
+    # two halves of a wave (odd and even sensor counts, both statistics);
+    # r-z grids with 2..8 planes run the column-factored screen (sensor
+    # groups per column for 3x3 and 5x5 columns, two passes for 9x9), more
+    # planes the per-node screen
     wl, sig, truth = _events(k, n, seed_off=2)
     grid = W.GridCfg(**{**wl.grid.__dict__, "nodes": nodes, "stat": stat,
                         "iterations": wl.grid.iterations + 2})

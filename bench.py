@@ -31,9 +31,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed), published
-# canonical FP32 operations per (node, sensor) evaluation, ML statistic:
-# distance 5 + sqrt 1 + interval 2 + cubic 6 + clamp 1 + S 2 + log 1 + n*log 2
-FLOP_PER_EVAL_ML = 20
+# Canonical (algorithmic) FP32 operations per (node, sensor) evaluation of
+# the ML statistic, from the formulas the FP64 oracle evaluates (FMA = 2,
+# add/mul = 1, transcendental = 1), fixed once:
+#   axial: distance 5 + sqrt 1 + interval 2 + cubic 6 + clamp 1 + S 2
+#          + log 1 + n*log 2 = 20
+#   r-z:   the bicubic in (r, z): distance and sqrt 6, interval location
+#          in r and z 2 x 6, cubic B-spline weights in r and z 2 x 12,
+#          4 x 4 tensor contraction 32, clamp 1, S 2, log and n*log 3 = 80
+# The library evaluates the r-z case as a cubic in r on z-collapsed plane
+# tables (about 20 operations per evaluation); `impl_flop_per_eval`
+# reports that figure beside the canonical one.
+FLOP_PER_EVAL_AXIAL_ML = 20
+FLOP_PER_EVAL_RZ_ML = 80
+IMPL_FLOP_PER_EVAL_RZ_ML = 20
 
 
 def parse():
@@ -95,7 +106,7 @@ def mixed_stream(args):
                                                      stream=stream), 2, 1, stream)
     evals = sum(int(np.prod(grid.nodes)) * grid.iterations * s.n_active * int(sizes[geoms == g].sum())
                 for g, s in enumerate(sets))
-    flops = evals * FLOP_PER_EVAL_ML
+    flops = evals * FLOP_PER_EVAL_AXIAL_ML
     achieved = flops / (ev * 1e-3) / 1e12
     rec = {"metric": "events/s reconstructed, mixed 19/61/127-sensor stream, one persistent launch",
            "value": total / wall, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -111,7 +122,7 @@ def mixed_stream(args):
            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                         "kernel": "cg_multi_kernel<AXIAL,ML,NT=2,SL=2>", "kernel_ms": ev,
-                        "flop_per_launch": flops}}
+                        "flop_per_launch": flops, "flop_per_eval": FLOP_PER_EVAL_AXIAL_ML}}
     print(json.dumps(rec), flush=True)
 
 
@@ -135,9 +146,15 @@ def cpu_baseline(wl, sig_host):
     t0 = time.perf_counter()
     oracle.reconstruct(wl.lrf, wl.grid, sig_host, threads=threads)
     dt = time.perf_counter() - t0
+    m1 = max(1, len(sig_host) // 16)
+    t1 = time.perf_counter()
+    oracle.reconstruct(wl.lrf, wl.grid, sig_host[:m1], threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": len(sig_host) / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {len(sig_host)} events of the benchmark batch, plain grid, FP64 C "
-                      f"oracle, {threads} threads, {dt:.1f} s"}
+                      f"oracle, {threads} threads, {dt:.1f} s",
+            "value_1_core": m1 / dt1,
+            "sample_1_core": f"first {m1} events, 1 thread, {dt1:.1f} s"}
 
 
 def timed(fn, steps, warmup, stream):
@@ -260,14 +277,15 @@ def main():
     wall_p, ev_p = timed(lambda: ants.reconstruct(lrf, plain, sig, out=out_plain, stream=stream),
                          args.steps, args.warmup, stream)
     evals = int(np.prod(wl.grid.nodes)) * 37 * wl.grid.iterations
-    flops = n * evals * FLOP_PER_EVAL_ML
+    flops = n * evals * FLOP_PER_EVAL_RZ_ML
     achieved = flops / (ev_p * 1e-3) / 1e12
     sp = sigma_xy(out_plain, truth)
     roof_plain = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                   "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                   "traffic": profiled_traffic("plain"),
                   "kernel": "cg_kernel<RZ,ML,NT=6,SL=1> (7x7x7 plain grid)", "kernel_ms": ev_p,
-                  "flop_per_launch": flops}
+                  "flop_per_launch": flops, "flop_per_eval": FLOP_PER_EVAL_RZ_ML,
+                  "impl_flop_per_eval": IMPL_FLOP_PER_EVAL_RZ_ML}
     rec = {
         "metric": "events/s reconstructed (plain grid vs NN-seeded) at equal sigma_xy, 1 MI355X",
         "value": n / wall_p, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -318,13 +336,15 @@ def main():
                                                  stream=stream), args.steps, 1, stream)
         rg = W.seeded_refine_grid(kappa=args.kappa)
         k_ev = seed_iterations(pred[:, 3].cpu().numpy(), rg)
-        flops_r = int(k_ev.sum()) * int(np.prod(rg.nodes)) * 37 * FLOP_PER_EVAL_ML
+        flops_r = int(k_ev.sum()) * int(np.prod(rg.nodes)) * 37 * FLOP_PER_EVAL_RZ_ML
         ach_r = flops_r / (ev_r * 1e-3) / 1e12
         rec["roofline"] = {"bound": "alu", "achieved": ach_r, "peak": PEAK_FP32_TFLOPS,
                            "unit": "TFLOP/s", "frac": ach_r / PEAK_FP32_TFLOPS,
                            "traffic": profiled_traffic("refine"),
                            "kernel": "cg_kernel<RZ,ML,NT=1,SL=1> (3x3x3 seeded refinement)",
                            "kernel_ms": ev_r, "flop_per_launch": flops_r,
+                           "flop_per_eval": FLOP_PER_EVAL_RZ_ML,
+                           "impl_flop_per_eval": IMPL_FLOP_PER_EVAL_RZ_ML,
                            "mean_iterations": float(k_ev.mean())}
         rec["value"] = n / wall_s
         rec["ms_per_step"] = 1e3 * wall_s

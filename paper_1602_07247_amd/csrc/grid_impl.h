@@ -405,6 +405,8 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   bool bad = false;
   float best_n = -1.0f;
   int best_a = 1 << 30;
+  // the centroid is needed only for the centroid start
+  const bool cog = !(G.start == ANTS_START_SEED && io.seeds) && G.start != ANTS_START_MAXSENSOR;
 #pragma unroll
   for (int q = 0; q < SL; ++q) {
     int a = lane + 64 * q;
@@ -415,11 +417,13 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       if (!(n >= 0.f) || !(n < kInf)) {
         bad = true;
       } else {
-        double wgt = (double)n / L.g[a];
         N += (double)n;
-        cw += wgt;
-        cxs += L.X[a] * wgt;
-        cys += L.Y[a] * wgt;
+        if (cog) {
+          double wgt = (double)n / L.g[a];
+          cw += wgt;
+          cxs += L.X[a] * wgt;
+          cys += L.Y[a] * wgt;
+        }
         if (n > best_n) { best_n = n; best_a = a; }
       }
     }
@@ -441,9 +445,11 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     if (io.path && lane < G.K) io.path[e * G.K + lane] = -1;
     return;
   }
-  cw = wsum_d(cw);
-  cxs = wsum_d(cxs);
-  cys = wsum_d(cys);
+  if (cog) {
+    cw = wsum_d(cw);
+    cxs = wsum_d(cxs);
+    cys = wsum_d(cys);
+  }
 
   double cx, cy, cz = G.z_start;
   if (G.start == ANTS_START_SEED && io.seeds) {
@@ -894,7 +900,10 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         float lsr = (rel && Sb > 0.f) ? fabsf(__builtin_amdgcn_logf(Sb * iSc)) : 0.f;
         float E = kU * (kLog2e * (24.f * A1 + 2.f * N32 + (float)(na + 2) * N32 * A3 * iSb) +
                         (float)(na + 4) * A2 + 4.f * N32 * lsr);
-        margin = 4.f * G.margin_scale * E;
+        // twice the bound: on 300 k events each of the r-z plain grid and
+        // the seeded refinement, decisions first differ from all-FP64 ones
+        // at a quarter of the bound
+        margin = 2.f * G.margin_scale * E;
       } else {
         float A1 = 0.f;
         float Ab = Sb > 0.f ? N32 / Sb : 0.f;

@@ -631,16 +631,20 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     // the wave: lanes l and l + 32 both hold node l, each sums over every
     // other sensor, and the halves add their sums
     const bool split = !FA && NT == 1 && G.nn <= 32;
-    const int hb = split ? (lk >> 5) : 0;
+    // with several tiles and at most 32 nodes in the last one (ML screen),
+    // only the last tile is split that way
+    const bool lsplit = !FA && STAT == ANTS_STAT_ML && NT >= 2 && G.nn - 64 * (NT - 1) <= 32;
+    const int hb = (split || lsplit) ? (lk >> 5) : 0;
     const int pstep = split ? 2 : 1;
     NodeF<KIND> nd[NT];
     bool valid[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       double xx, yy, zz;
-      const int j = split ? (lk & 31) : t * 64 + lk;
+      const bool half = split || (lsplit && t == NT - 1);
+      const int j = t * 64 + (half ? (lk & 31) : lk);
       valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, nd[t], xx, yy, zz);
-      if (split) valid[t] = valid[t] && lk < 32;
+      if (half) valid[t] = valid[t] && lk < 32;
     }
 
     // ---- FP32 screen
@@ -731,6 +735,69 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
             T[t] = b;
           }
         }
+      } else if (lsplit) {
+        // full tiles take sensors p and p + 1, the last tile's half-waves
+        // one each
+        constexpr int LT = NT - 1;
+        int p = 0;
+        for (; p + 2 <= npos; p += 2) {
+          const float4 A0 = recA[p], B0 = recB[p], A1 = recA[p + 1], B1 = recB[p + 1];
+          const float4 Ah = recA[p + hb], Bh = recB[p + hb];
+          const int o0 = __float_as_int(B0.z), o1 = __float_as_int(B1.z), oh = __float_as_int(Bh.z);
+#pragma unroll
+          for (int t = 0; t < LT; ++t) {
+            const float L0 = lrf32<KIND, NN>(nd[t], A0.x, A0.y, o0, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B0.x, L0 - B0.y, dS[t]);
+            T[t] = fmaf(A0.z, __builtin_amdgcn_logf(L0 * A0.w), T[t]);
+            const float L1 = lrf32<KIND, NN>(nd[t], A1.x, A1.y, o1, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B1.x, L1 - B1.y, dS[t]);
+            T[t] = fmaf(A1.z, __builtin_amdgcn_logf(L1 * A1.w), T[t]);
+          }
+          const float Lh = lrf32<KIND, NN>(nd[LT], Ah.x, Ah.y, oh, btab, L.c32, L.nc0, finv, nlast);
+          dS[LT] = fmaf(Bh.x, Lh - Bh.y, dS[LT]);
+          T[LT] = fmaf(Ah.z, __builtin_amdgcn_logf(Lh * Ah.w), T[LT]);
+        }
+        if (p < npos) {
+          const float4 A = recA[p], B = recB[p];
+          const int o = __float_as_int(B.z);
+#pragma unroll
+          for (int t = 0; t < LT; ++t) {
+            const float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+            T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
+          }
+          const float w = hb ? 0.f : 1.f;
+          const float Lh = lrf32<KIND, NN>(nd[LT], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+          dS[LT] = fmaf(B.x * w, Lh - B.y, dS[LT]);
+          T[LT] = fmaf(A.z * w, __builtin_amdgcn_logf(Lh * A.w), T[LT]);
+        }
+        for (p = npos; p + 2 <= na; p += 2) {
+          const float4 A0 = recA[p], B0 = recB[p], A1 = recA[p + 1], B1 = recB[p + 1];
+          const float4 Ah = recA[p + hb], Bh = recB[p + hb];
+          const int o0 = __float_as_int(B0.z), o1 = __float_as_int(B1.z), oh = __float_as_int(Bh.z);
+#pragma unroll
+          for (int t = 0; t < LT; ++t) {
+            const float L0 = lrf32<KIND, NN>(nd[t], A0.x, A0.y, o0, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B0.x, L0 - B0.y, dS[t]);
+            const float L1 = lrf32<KIND, NN>(nd[t], A1.x, A1.y, o1, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B1.x, L1 - B1.y, dS[t]);
+          }
+          const float Lh = lrf32<KIND, NN>(nd[LT], Ah.x, Ah.y, oh, btab, L.c32, L.nc0, finv, nlast);
+          dS[LT] = fmaf(Bh.x, Lh - Bh.y, dS[LT]);
+        }
+        if (p < na) {
+          const float4 A = recA[p], B = recB[p];
+          const int o = __float_as_int(B.z);
+#pragma unroll
+          for (int t = 0; t < LT; ++t) {
+            const float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+          }
+          const float Lh = lrf32<KIND, NN>(nd[LT], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+          dS[LT] = fmaf(hb ? 0.f : B.x, Lh - B.y, dS[LT]);
+        }
+        dS[LT] += __shfl_xor(dS[LT], 32);
+        T[LT] += __shfl_xor(T[LT], 32);
       } else {
         int p = 0;
         for (; p + pstep <= npos; p += pstep) {

@@ -63,13 +63,15 @@ def test_parity_against_oracle(ants, k, n, stat):
                                              (1, (3, 3, 1), 1, 1_000), (2, (3, 3, 3), 0, 2_000),
                                              (2, (3, 3, 3), 1, 1_000), (2, (5, 5, 1), 0, 1_000),
                                              (2, (5, 5, 3), 0, 1_000), (2, (3, 3, 9), 0, 1_000),
-                                             (2, (9, 9, 3), 0, 500)])
+                                             (2, (9, 9, 3), 0, 500), (0, (7, 11, 1), 0, 2_000),
+                                             (1, (11, 11, 1), 0, 1_000), (1, (9, 9, 1), 1, 1_000)])
 def test_parity_small_grids_split_sensor_loop(ants, k, nodes, stat, n):
     # grids of <= 32 nodes run the screen with the sensors split between the
     # two halves of a wave (odd and even sensor counts, both statistics);
     # r-z grids with 2..8 planes run the column-factored screen (sensor
     # groups per column for 3x3 and 5x5 columns, two passes for 9x9), more
-    # planes the per-node screen
+    # planes the per-node screen; several tiles with at most 32 nodes in the
+    # last one (7x11, 9x9 with 3 planes) split only the last tile (ML)
     wl, sig, truth = _events(k, n, seed_off=2)
     grid = W.GridCfg(**{**wl.grid.__dict__, "nodes": nodes, "stat": stat,
                         "iterations": wl.grid.iterations + 2})

@@ -131,21 +131,31 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
   const int64_t e0 = (int64_t)blockIdx.x * FR;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
 
-  // inputs x = bf16(n_a * (n_active / N)), as normalize_kernel
+  // inputs x = bf16(n_a * (n_active / N)), as normalize_kernel: the block's
+  // signals are first staged in LDS by all threads (independent loads),
+  // then each event's sum runs in sensor order as there
+  float* stage = (float*)buf0;           // [FR][na] FP32, na <= 64
+  const int na = P.na;
+  for (int i = tid; i < FR * na; i += 256) {
+    const int r = i / na, a = i - r * na;
+    const int64_t e = e0 + r;
+    stage[i] = e < P.n ? P.sig[e * P.ld + P.col[a]] : 0.f;
+  }
+  __syncthreads();
   if (tid < FR) {
     const int64_t e = e0 + tid;
     float sc = 0.f;
     if (e < P.n) {
-      const float* row = P.sig + e * P.ld;
+      const float* row = stage + tid * na;
       float N = 0.f;
       bool ok = true;
-      for (int a = 0; a < P.na; ++a) {
-        const float v = row[P.col[a]];
+      for (int a = 0; a < na; ++a) {
+        const float v = row[a];
         if (!(v >= 0.f) || !(v < __builtin_huge_valf())) ok = false;
         N += v;
       }
       ok = ok && N > 0.f;
-      sc = ok ? (float)P.na / N : 0.f;
+      sc = ok ? (float)na / N : 0.f;
     }
     scl[tid] = sc;
   }
@@ -153,9 +163,8 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
   const int kin = P.kin, pin = kin + 8;
   for (int i = tid; i < FR * kin; i += 256) {
     const int r = i / kin, a = i - r * kin;
-    const int64_t e = e0 + r;
     __bf16 v = (__bf16)0.f;
-    if (e < P.n && a < P.na && scl[r] > 0.f) v = to_bf16(P.sig[e * P.ld + P.col[a]] * scl[r]);
+    if (a < na && scl[r] > 0.f) v = to_bf16(stage[r * na + a] * scl[r]);
     buf1[r * pin + a] = v;
   }
   __syncthreads();
@@ -379,7 +388,8 @@ hipError_t launch_gemm(const GemmP& P, hipStream_t s) {
 }
 hipError_t launch_mlp_fwd(const FwdP& P, hipStream_t s) {
   if (P.n <= 0) return hipSuccess;
-  if (P.kin > FH || P.kin % 32 || P.layers < 1 || P.layers > kFwdMaxLayers)
+  if (P.kin > FH || P.kin % 32 || P.layers < 1 || P.layers > kFwdMaxLayers || P.na > 64 ||
+      P.na > P.kin)
     return hipErrorInvalidValue;
   const size_t smem = (size_t)2 * FR * FPITCH * sizeof(__bf16);
   hipError_t e = hipFuncSetAttribute((const void*)mlp_fwd_kernel,

@@ -7,8 +7,8 @@ z in [0, 50] mm with E_tot uniform in [500, 2000] photoelectrons, Poisson
 counts.  Plain grid: 7 x 7 x 7 nodes, 8 iterations, shrink 0.5, centroid
 start.  Seeded: a 37-256-256-256-4 ReLU network trained (untimed set-up) on
 5 M events drawn from the same LRF model (plus 0.5 M for validation), a
-3 x 3 x 3 refinement grid ending on the plain grid's final step, and the
-plain grid as fallback when chi2/ndf > 2.  All events are drawn on the GPU
+3 x 3 x 3 refinement grid (steps shrinking by 0.4) ending on the plain
+grid's final step, and the plain grid as fallback when chi2/ndf > 2.  All events are drawn on the GPU
 by the library's generator and are resident in HBM before the timed region.
 
 One step = one reconstruction of the whole 10 M-event batch by the seeded
@@ -293,7 +293,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic (flood-field events drawn on the GPU from the LRF model)",
         "config": {"workload": "hex37 r-z LRF, 10M events; plain grid 7x7x7 x 8 iterations vs "
-                               "NN seed + 3x3x3 refinement with chi2/ndf>2 fallback; ML",
+                               "NN seed + 3x3x3 refinement (shrink 0.4) with chi2/ndf>2 fallback; ML",
                    "events": n, "sensors": 37},
         "plain": {"events_per_s": n / wall_p, "ms_per_step": 1e3 * wall_p,
                   "sigma_xy_mm": sp[0], "sigma_xy_fiducial_mm": sp[1], "p95_radial_mm": sp[2],

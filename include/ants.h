@@ -318,8 +318,10 @@ ants_status ants_mlp_load(const char* path, ants_mlp** out);
  * chi2ndf_max (or is not finite, or ndf <= 0) run again with `fallback`
  * (normally the plain grid from the centroid) and get ANTS_EV_FALLBACK.
  * d_n_fallback (one int32, device) receives the number of such events.
- * The library keeps a workspace of 16 bytes per event in the mlp handle
- * (or the LRF set when mlp is NULL) and of 4 bytes per event for the list. */
+ * The network runs as one fused kernel (no activation buffers).  The
+ * library keeps, in the LRF set, a workspace of 16 bytes per event for the
+ * seeds and 4 bytes per event for the fallback list; calls that share a set
+ * must not overlap in time. */
 ants_status ants_reconstruct_seeded(ants_lrfset* set, ants_mlp* mlp,
                                     const ants_grid_cfg* refine, const ants_grid_cfg* fallback,
                                     double chi2ndf_max, int64_t n_events, const float* d_signals,

@@ -24,7 +24,8 @@ __host__ __device__ constexpr int node_tiles(int nn) {
 }
 
 // Per-wave LDS bytes of the event kernels: sensor records (32 B per active
-// sensor, rewritten every iteration, and 32 B of FP64 data per event); for r-z the FP32 plane tables (16 B per plane and interval),
+// sensor, rewritten every iteration, and 32 B of FP64 data per event); for
+// r-z the FP32 plane tables (16 B per plane and interval),
 // which the FP64 spline rows (8 B per plane and r-coefficient) overlay
 // during the FP64 decisions, and the plane weights (16 B FP32 + 32 B FP64
 // + 4 B first z-coefficient per plane); 16-bit candidate list and

@@ -13,18 +13,23 @@
 // Mapping: one wavefront per event, lanes = grid nodes (tiles of 64 nodes),
 // a uniform loop over the event's active sensors.  Per-event sensor records
 // are broadcast from LDS; LRF piecewise-cubic tables sit in LDS (axial and
-// r-z; the r-z table is collapsed along z for the seven z-planes of each
+// r-z; the r-z table is collapsed along z for the z-planes of each
 // iteration so each (node, sensor) pair costs one cubic in r); XY bicubic
-// coefficients are read through the cache.
+// coefficients are read through the cache.  Variants of the screen:
+//  - r-z, ML, 3/5/7 planes: lanes take (x-y column, sensor group) and one
+//    distance serves every plane of the column (column-factored screen);
+//  - grids of at most 32 nodes, or a last tile of at most 32 nodes: the
+//    two half-waves take alternate sensors and add their sums.
 //
 // Precision: nodes are first screened in FP32 with the statistic written
 // relative to the current centre (ratios L/L_centre and S/S_centre), which
 // keeps the rounding error proportional to the distance from the centre.
 // A per-iteration bound on that error is computed at the best screened
-// node; every node whose screened value lies within the bound of the best
-// is re-evaluated in FP64 (the vector FP64 rate equals the unpacked FP32
-// rate on this chip), and the FP64 values decide.  Ties in FP64 go to the
-// lowest node index.
+// node; every node whose screened value lies within (a multiple of) the
+// bound of the best is re-evaluated in FP64 (the vector FP64 rate equals
+// the unpacked FP32 rate on this chip), in lane groups sized by a cost
+// model, and the FP64 values decide.  Ties in FP64 go to the lowest node
+// index.
 #pragma once
 
 #include <math.h>

@@ -278,11 +278,16 @@ SEED_POS_SCALE = (90.0, 90.0, 90.0)
 SEED_POS_OFFSET = (0.0, 0.0, 25.0)
 
 
-def seeded_refine_grid(kappa: float = 0.5, kmin: int = 2, kmax: int = 8) -> GridCfg:
+def seeded_refine_grid(kappa: float = 0.5, kmin: int = 2, kmax: int = 8,
+                       shrink: float = 0.4) -> GridCfg:
     """Refinement grid of the learned-seed path: 3 x 3 x 3 nodes started at
     the seed, ending on the plain grid's final step (workload 2: 10, 10,
     50/6 mm halved over 8 iterations), with the iteration count chosen per
-    event from the seed's predicted spread (kappa * sigma)."""
-    return GridCfg((3, 3, 3), 8, 0.5, (10.0, 10.0, 50.0 / 6.0), 25.0, stat=0, start=2,
+    event from the seed's predicted spread (kappa * sigma).  Steps shrink by
+    0.4 per iteration (a 3-node grid keeps the minimum within reach for any
+    factor >= 1/3: the next grid spans c / (1 - c) >= 1/2 of the step)."""
+    final = [10.0 * 0.5 ** 7, 10.0 * 0.5 ** 7, 50.0 / 6.0 * 0.5 ** 7]
+    step0 = tuple(f / shrink ** (kmax - 1) for f in final)
+    return GridCfg((3, 3, 3), kmax, shrink, step0, 25.0, stat=0, start=2,
                    seed_steps=1, seed_kappa=kappa, seed_kmin=kmin, seed_kmax=kmax,
                    seed_scale=SEED_POS_SCALE)

@@ -106,9 +106,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmP P) {
 
 // ---------------------------------------------------------------------------
 // Fused inference: one block of four waves runs FR events through every
-// layer with the activations held in LDS (two buffers, BF16, rows padded by
-// 8 elements); weights are read from global memory (L2-resident) straight
-// into the MFMA operand registers, one k-step ahead.  Each product is the
+// layer with the activations held in one LDS buffer (BF16, rows padded by
+// 8 elements) that each layer overwrites in place: every wave first reads
+// all of its operands into its accumulators, the block synchronises, then
+// the outputs are written.  Weights are read from global memory
+// (L2-resident) straight into the MFMA operand registers, one k-step ahead.  Each product is the
 // same sequence of 16x16x32 MFMAs as in gemm_kernel (FP32 accumulators from
 // zero, k ascending), so hidden activations and outputs equal that path's.
 // Hidden width 256: wave w owns output columns 64w..64w+63 of every layer.
@@ -122,10 +124,13 @@ __device__ __forceinline__ const float* fwd_b(const FwdP& P, int l) {
   return l == 0 ? P.b[0] : l == 1 ? P.b[1] : l == 2 ? P.b[2] : l == 3 ? P.b[3] : P.b[4];
 }
 
-__global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+mlp_fwd_kernel(FwdP P) {
   extern __shared__ __align__(16) __bf16 fsm[];
-  __bf16* buf0 = fsm;                    // [FR][FPITCH]
-  __bf16* buf1 = fsm + FR * FPITCH;      // [FR][FPITCH]; inputs use its first rows
+  __bf16* buf = fsm;                     // [FR][FPITCH] activations
+  // before the first layer: FP32 signals in the first 16 KiB, the BF16
+  // inputs [FR][kin + 8] after them
+  __bf16* inb = fsm + FR * 64 * 2;
   __shared__ float scl[FR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t e0 = (int64_t)blockIdx.x * FR;
@@ -134,7 +139,7 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
   // inputs x = bf16(n_a * (n_active / N)), as normalize_kernel: the block's
   // signals are first staged in LDS by all threads (independent loads),
   // then each event's sum runs in sensor order as there
-  float* stage = (float*)buf0;           // [FR][na] FP32, na <= 64
+  float* stage = (float*)buf;            // [FR][na] FP32, na <= 64
   const int na = P.na;
   for (int i = tid; i < FR * na; i += 256) {
     const int r = i / na, a = i - r * na;
@@ -165,13 +170,12 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
     const int r = i / kin, a = i - r * kin;
     __bf16 v = (__bf16)0.f;
     if (a < na && scl[r] > 0.f) v = to_bf16(stage[r * na + a] * scl[r]);
-    buf1[r * pin + a] = v;
+    inb[r * pin + a] = v;
   }
   __syncthreads();
 
-  const __bf16* in = buf1;
+  const __bf16* in = inb;
   int pitch = pin, din = kin;
-  __bf16* outb = buf0;
 #pragma unroll
   for (int l = 0; l < kFwdMaxLayers; ++l) {
     if (l >= P.layers) break;
@@ -202,7 +206,8 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[j] = bn[j];
     }
-    // bias, ReLU, BF16 into the other buffer
+    // every wave has read its operands: bias, ReLU, BF16 in place
+    __syncthreads();
     const float* bias = fwd_b(P, l);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -212,13 +217,12 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(FwdP P) {
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          outb[(i * 16 + (lane >> 4) * 4 + r) * FPITCH + c] = to_bf16(fmaxf(acc[i][j][r] + bc, 0.f));
+          buf[(i * 16 + (lane >> 4) * 4 + r) * FPITCH + c] = to_bf16(fmaxf(acc[i][j][r] + bc, 0.f));
     }
     __syncthreads();
-    in = outb;
+    in = buf;
     pitch = FPITCH;
     din = FH;
-    outb = (outb == buf0) ? buf1 : buf0;
   }
 
   // output layer (4 rows of weights, padded to one 16-column tile): wave w
@@ -391,7 +395,7 @@ hipError_t launch_mlp_fwd(const FwdP& P, hipStream_t s) {
   if (P.kin > FH || P.kin % 32 || P.layers < 1 || P.layers > kFwdMaxLayers || P.na > 64 ||
       P.na > P.kin)
     return hipErrorInvalidValue;
-  const size_t smem = (size_t)2 * FR * FPITCH * sizeof(__bf16);
+  const size_t smem = (size_t)FR * FPITCH * sizeof(__bf16);
   hipError_t e = hipFuncSetAttribute((const void*)mlp_fwd_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;

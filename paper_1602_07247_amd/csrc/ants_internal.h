@@ -59,6 +59,7 @@ struct DevLrf {
   double d0, d1;       // breakpoint spacing
   float finv0;         // 1/d0 (axial and r-z: lo0 = 0)
   double inv_d0;       // 1/d0 in FP64 (screen distances are kept in units of d0)
+  double inv_d1;       // 1/d1 in FP64
   int nonneg;          // every FP32 cubic piece is >= 0 on [0, 1] (no clamp needed)
   const int32_t* col;  // [na] column of the active sensor in a signal row
   const int32_t* tab;  // [na] coefficient table of the sensor

@@ -306,6 +306,7 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
   d.d1 = kind == ANTS_LRF_AXIAL ? 1.0 : (d.hi1 - d.lo1) / (nb1 - 1);
   d.finv0 = (float)(1.0 / d.d0);
   d.inv_d0 = 1.0 / d.d0;
+  d.inv_d1 = 1.0 / d.d1;
   // non-negative pieces: the screen can skip the clamp at 0
   d.nonneg = 0;
   if (!pp.empty()) {

@@ -353,8 +353,8 @@ __device__ __forceinline__ bool make_node(const DevLrf& L, const GridP& G, doubl
   if constexpr (KIND == ANTS_LRF_XY) {
     int m0 = 0, m1 = 0;
     double t0 = 0.0, t1 = 0.0, b0[4], b1[4];
-    bool in0 = locate64(x, L.nb0, L.lo0, L.hi0, L.d0, m0, t0);
-    bool in1 = locate64(y, L.nb1, L.lo1, L.hi1, L.d1, m1, t1);
+    bool in0 = locate64(x, L.nb0, L.lo0, L.hi0, L.inv_d0, m0, t0);
+    bool in1 = locate64(y, L.nb1, L.lo1, L.hi1, L.inv_d1, m1, t1);
     valid = valid && in0 && in1;
     bweights64(t0, b0);
     bweights64(t1, b1);
@@ -546,7 +546,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         const double zz = cz + (double)(jz - G.hz) * sz;
         int mz;
         double tz, bz[4];
-        if (locate64(zz, L.nb1, L.lo1, L.hi1, L.d1, mz, tz)) {
+        if (locate64(zz, L.nb1, L.lo1, L.hi1, L.inv_d1, mz, tz)) {
           bweights64(tz, bz);
         } else {
           bz[0] = bz[1] = bz[2] = bz[3] = 0.0;

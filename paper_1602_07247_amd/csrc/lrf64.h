@@ -9,11 +9,13 @@
 namespace ants {
 namespace {
 
-__device__ __forceinline__ bool locate64(double u, int nb, double lo, double hi, double d, int& m,
-                                         double& t) {
+// Interval m and local coordinate t of u on a uniform breakpoint grid
+// (inv_d = 1 / spacing); false outside the domain (relative slack 1e-9).
+__device__ __forceinline__ bool locate64(double u, int nb, double lo, double hi, double inv_d,
+                                         int& m, double& t) {
   double tol = 1e-9 * (hi - lo);
   if (!(u >= lo - tol && u <= hi + tol)) return false;
-  double v = (u - lo) / d;
+  double v = (u - lo) * inv_d;
   int k = (int)floor(v);
   k = k < 0 ? 0 : k;
   k = k > nb - 2 ? nb - 2 : k;
@@ -50,7 +52,7 @@ __device__ __forceinline__ double lrf64s(const DevLrf& L, double X, double Y, in
     double r = sqrt(dx * dx + dy * dy);
     int m;
     double t, b[4];
-    if (!locate64(r, L.nb0, L.lo0, L.hi0, L.d0, m, t)) return 0.0;
+    if (!locate64(r, L.nb0, L.lo0, L.hi0, L.inv_d0, m, t)) return 0.0;
     bweights64(t, b);
     const double* c = L.c64 + coff + m;
     v = c[0] * b[0] + c[1] * b[1] + c[2] * b[2] + c[3] * b[3];
@@ -67,8 +69,8 @@ __device__ __forceinline__ double lrf64s(const DevLrf& L, double X, double Y, in
     }
     int m0, m1;
     double t0, t1, b0[4], b1[4];
-    if (!locate64(u, L.nb0, L.lo0, L.hi0, L.d0, m0, t0)) return 0.0;
-    if (!locate64(w, L.nb1, L.lo1, L.hi1, L.d1, m1, t1)) return 0.0;
+    if (!locate64(u, L.nb0, L.lo0, L.hi0, L.inv_d0, m0, t0)) return 0.0;
+    if (!locate64(w, L.nb1, L.lo1, L.hi1, L.inv_d1, m1, t1)) return 0.0;
     bweights64(t0, b0);
     bweights64(t1, b1);
 #pragma unroll

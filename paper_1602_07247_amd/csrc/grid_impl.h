@@ -190,6 +190,30 @@ struct NodeF<ANTS_LRF_XY> {
   float w[16];           // wy[a] * wx[b]
 };
 
+// Radial kinds: node-sensor distance in units of the breakpoint spacing
+// (v = r / d0, the domain starting at r = 0), the sensor's table (r-z: the
+// node's plane table) and the cubic piece at v; index nlast is an all-zero
+// interval past the end of the domain.
+template <int KIND>
+__device__ __forceinline__ float rad_v(const NodeF<KIND>& nd, float dX, float dY) {
+  const float dx = nd.ox - dX, dy = nd.oy - dY;
+  return __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+}
+template <int KIND>
+__device__ __forceinline__ const float4* rad_tab(const NodeF<KIND>& nd, const float4* btab,
+                                                 int tofs) {
+  if constexpr (KIND == ANTS_LRF_RZ) return nd.tab;
+  else return btab + tofs;
+}
+template <bool NN>
+__device__ __forceinline__ float rad32(const float4* T, float v, int nlast) {
+  const int m = (int)fminf(v, (float)nlast);
+  const float t = __builtin_amdgcn_fractf(v);
+  const float4 c = T[m];
+  const float p = fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
+  return NN ? p : fmaxf(p, 0.f);
+}
+
 // Sensor record broadcast from LDS: A = {dX, dY, n, 1/L_c}, B = {g, L_c, table offset, a}
 template <int KIND, bool NN>
 __device__ __forceinline__ float lrf32(const NodeF<KIND>& nd, float dX, float dY, int tofs,
@@ -220,18 +244,8 @@ __device__ __forceinline__ float lrf32(const NodeF<KIND>& nd, float dX, float dY
     v = fmaf(nd.w[15], r3.w, v);
     return fmaxf(v, 0.f);
   } else {
-    // offsets are in units of the breakpoint spacing: v = r / d0
-    float dx = nd.ox - dX, dy = nd.oy - dY;
-    float r2 = fmaf(dx, dx, dy * dy);
-    float v = __builtin_amdgcn_sqrtf(r2);
-    int m = (int)fminf(v, (float)nlast);
-    float t = __builtin_amdgcn_fractf(v);
-    const float4* T;
-    if constexpr (KIND == ANTS_LRF_RZ) T = nd.tab;
-    else T = btab + tofs;
-    float4 c = T[m];
-    float p = fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
-    return NN ? p : fmaxf(p, 0.f);
+    const float v = rad_v(nd, dX, dY);
+    return rad32<NN>(rad_tab<KIND>(nd, btab, tofs), v, nlast);
   }
 }
 
@@ -250,18 +264,19 @@ __device__ __forceinline__ void fill_nodeidx(const GridP& G, uint16_t* tab, int 
   }
 }
 
-// FP64 data of an active sensor, stored per event in record order.
+// FP64 data of an active sensor, stored per event in sensor order (the
+// FP32 records are re-ordered every iteration).
 struct SensorRec64 {
   double X, Y, g;
   int coff;            // FP64 coefficient offset
-  int tofs;            // FP32 table offset
+  float n;             // signal
 };
 
 // A wave's LDS area (sizes as in wave_lds_bytes).
 struct WaveLds {
   float4* recA;        // per sensor record: dX, dY, n, 1/L_c
   float4* recB;        // g, L_c, table offset, sensor index
-  SensorRec64* rec64;  // X, Y, g, table offsets
+  SensorRec64* rec64;  // X, Y, g, FP64 coefficient offset, signal
   float4* ztab;        // r-z: FP32 plane tables [nz][nintp]
   double* zc64;        // r-z: FP64 spline rows [nz][nc0], overlaying ztab
   float4* pw32;        // r-z: FP32 z-weights per plane
@@ -474,37 +489,42 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   cy = uni(cy);
   cz = uni(cz);
 
-  // sensor records in LDS: sensors with n > 0 first, then n == 0
-  int npos = 0;
+  // record positions with counted sensors first (the order of every
+  // iteration in which no sensor reaches the end of the LRF domain)
+  int posq0[SL], npos0 = 0;
   {
     uint64_t mpos[SL], mzero[SL];
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
-      int a = lane + 64 * q;
+      const int a = lane + 64 * q;
       mpos[q] = __ballot(a < na && nq[q] > 0.f);
       mzero[q] = __ballot(a < na && !(nq[q] > 0.f));
-      npos += __popcll(mpos[q]);
+      npos0 += __popcll(mpos[q]);
     }
-    int bp = 0, bz = npos;
+    int bp = 0, bz = npos0;
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
-      posq[q] = nq[q] > 0.f ? bp + prefix_count(mpos[q]) : bz + prefix_count(mzero[q]);
+      posq0[q] = nq[q] > 0.f ? bp + prefix_count(mpos[q]) : bz + prefix_count(mzero[q]);
       bp += __popcll(mpos[q]);
       bz += __popcll(mzero[q]);
     }
   }
+  // FP64 sensor records in sensor order; FP32 table offsets in registers
   const float N32 = (float)N;
+  int tofq[SL];
 #pragma unroll
   for (int q = 0; q < SL; ++q) {
     const int a = lane + 64 * q;
+    tofq[q] = 0;
     if (a < na) {
       SensorRec64 r;
       r.X = L.X[a];
       r.Y = L.Y[a];
       r.g = L.g[a];
       r.coff = coef_off64<KIND>(L, a);
-      r.tofs = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
-      rec64[posq[q]] = r;
+      r.n = nq[q];
+      rec64[a] = r;
+      tofq[q] = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
     }
   }
 
@@ -599,33 +619,110 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       int jc = (G.hz * G.ny + G.hy) * G.nx + G.hx;
       make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jc, ztab, nodeidx, ndc, xx, yy, zz);
     }
+    // ---- reference values at the centre and order of the FP32 records for
+    // this iteration.  Radial kinds: the LRF jumps to zero at the end of its
+    // domain, where the FP32 and FP64 distances may fall on different sides.
+    // A sensor below the end at every node of the grid (with a band for the
+    // FP32 distance error) is "inside"; one beyond it at every node has a
+    // zero LRF in both precisions and terms equal at every node, so the
+    // screen skips it; any other is an "edge" sensor, screened by loops of
+    // their own that send the nodes within the band to FP64.  Order: counted
+    // inside, counted edge, zero-signal inside, zero-signal edge, beyond.
+    const float vhi = (float)nlast;   // end of the domain, in breakpoint spacings
+    float band = 0.f;
     float Sc = 0.f;
+    float dXq[SL], dYq[SL], Lcq[SL];
+    float ex = 0.f, ey = 0.f, lo2 = 0.f, hi2 = 0.f;
+    bool reach = false;   // some sensor may reach the end of the domain
+    if constexpr (KIND != ANTS_LRF_XY) {
+      ex = (float)((double)(G.nx - 1 - G.hx) * sx * L.inv_d0);
+      ey = (float)((double)(G.ny - 1 - G.hy) * sy * L.inv_d0);
+      band = 4e-6f * (vhi + 2.f * (ex + ey) + 1.f);
+      lo2 = (vhi - band) * (vhi - band);
+      hi2 = (vhi + band) * (vhi + band);
+    }
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
-      int a = lane + 64 * q;
+      const int a = lane + 64 * q;
+      dXq[q] = dYq[q] = Lcq[q] = 0.f;
       if (a < na) {
-        const SensorRec64 r = rec64[posq[q]];
-        float dX = (float)((r.X - cx) * L.inv_d0),
-              dY = (float)((r.Y - cy) * L.inv_d0);
-        int tofs = r.tofs;
-        float Lc = lrf32<KIND, NN>(ndc, dX, dY, tofs, btab, L.c32, L.nc0, finv, nlast);
-        float g = (float)r.g;
-        Sc = fmaf(g, Lc, Sc);
-        recA[posq[q]] = make_float4(dX, dY, nq[q], 1.0f / fmaxf(Lc, flf));
-        recB[posq[q]] = make_float4(g, Lc, __int_as_float(tofs), __int_as_float(a));
+        const SensorRec64 r = rec64[a];
+        const float dX = (float)((r.X - cx) * L.inv_d0), dY = (float)((r.Y - cy) * L.inv_d0);
+        const float Lc = lrf32<KIND, NN>(ndc, dX, dY, tofq[q], btab, L.c32, L.nc0, finv, nlast);
+        Sc = fmaf((float)r.g, Lc, Sc);
+        dXq[q] = dX;
+        dYq[q] = dY;
+        Lcq[q] = Lc;
+        if constexpr (KIND != ANTS_LRF_XY) {
+          const float fx = fabsf(dX) + ex, fy = fabsf(dY) + ey;
+          reach = reach || !(fmaf(fx, fx, fy * fy) < lo2);
+        }
       }
     }
     Sc = uni(wsum_f(Sc));
     const bool rel = Sc > 0.f;   // centre-relative form available
-    if (!rel) {
-      // absolute form: L_c = 0 and 1/L_c = 1 make dS = S and the log terms absolute
+    int n_ci = npos0, n_pos = npos0, z_end = na, n_scr = na;
+    if (__ballot(reach) == 0ull) {
+#pragma unroll
+      for (int q = 0; q < SL; ++q) posq[q] = posq0[q];
+    } else {
+      // categories: 0 counted inside, 1 counted edge, 2 zero-signal inside,
+      // 3 zero-signal edge, 4 beyond
+      int key[SL];
 #pragma unroll
       for (int q = 0; q < SL; ++q) {
-        int a = lane + 64 * q;
-        if (a < na) {
-          recA[posq[q]].w = 1.f;
-          recB[posq[q]].y = 0.f;
+        const float ax = fabsf(dXq[q]), ay = fabsf(dYq[q]);
+        const float nx0 = fmaxf(ax - ex, 0.f), ny0 = fmaxf(ay - ey, 0.f);
+        const float fx = ax + ex, fy = ay + ey;
+        const int cls = fmaf(fx, fx, fy * fy) < lo2 ? 0 : fmaf(nx0, nx0, ny0 * ny0) > hi2 ? 2 : 1;
+        key[q] = cls == 2 ? 4 : (nq[q] > 0.f ? 0 : 2) + cls;
+      }
+      uint64_t mk[SL][5];
+      int cnt[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        const int a = lane + 64 * q;
+        const bool in = a < na;
+        const uint64_t mv = __ballot(in), mc = __ballot(in && (key[q] == 0 || key[q] == 1));
+        const uint64_t me = __ballot(in && (key[q] == 1 || key[q] == 3));
+        const uint64_t mb = __ballot(in && key[q] == 4);
+        mk[q][0] = mc & ~me;
+        mk[q][1] = mc & me;
+        mk[q][2] = mv & ~mc & ~me & ~mb;
+        mk[q][3] = mv & ~mc & me;
+        mk[q][4] = mb;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) cnt[c] += __popcll(mk[q][c]);
+      }
+      int run[5];
+      run[0] = 0;
+#pragma unroll
+      for (int c = 1; c < 5; ++c) run[c] = run[c - 1] + cnt[c - 1];
+      n_ci = run[1];
+      n_pos = run[2];
+      z_end = run[3];
+      n_scr = run[4];
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        int pos = 0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          if (key[q] == c) pos = run[c] + prefix_count(mk[q][c]);
+          run[c] += __popcll(mk[q][c]);
         }
+        posq[q] = pos;
+      }
+    }
+    // absolute form (no centre reference): L_c = 0 and 1/L_c = 1 make dS = S
+    // and the log terms absolute
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      const int a = lane + 64 * q;
+      if (a < na) {
+        const float Lc = rel ? Lcq[q] : 0.f;
+        recA[posq[q]] = make_float4(dXq[q], dYq[q], nq[q], rel ? 1.0f / fmaxf(Lc, flf) : 1.f);
+        recB[posq[q]] = make_float4((float)rec64[a].g, Lc, __int_as_float(tofq[q]),
+                                    __int_as_float(a));
       }
     }
     const float iSc = rel ? 1.0f / Sc : 1.0f;
@@ -680,7 +777,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 #pragma unroll
             for (int q = 0; q < nz; ++q) { aS[q] = 0.f; aT[q] = 0.f; }
             const int pstride = L.nintp;
-            for (int p = grp; p < npos; p += ngrp) {
+            for (int p = grp; p < n_ci; p += ngrp) {
               const float4 A = recA[p], B = recB[p];
               const float dx = ox - A.x, dy = oy - A.y;
               const float v = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
@@ -698,7 +795,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
                 aT[q] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), aT[q]);
               }
             }
-            for (int p = npos + grp; p < na; p += ngrp) {
+            for (int p = n_pos + grp; p < z_end; p += ngrp) {
               const float4 A = recA[p], B = recB[p];
               const float dx = ox - A.x, dy = oy - A.y;
               const float v = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
@@ -715,11 +812,49 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
                 aS[q] = fmaf(B.x, Lv - B.y, aS[q]);
               }
             }
+            // edge sensors: a column within the band of the domain end makes
+            // its nodes non-finite (FP64); beyond the end the LRF is zero and
+            // the logarithm takes the floor, as in FP64
+            bool kn = false;
+            for (int p = n_ci + grp; p < n_pos; p += ngrp) {
+              const float4 A = recA[p], B = recB[p];
+              const float dx = ox - A.x, dy = oy - A.y;
+              const float v = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+              const int m = (int)fminf(v, (float)nlast);
+              const float tt = __builtin_amdgcn_fractf(v);
+              const float4* tp = ztab + m;
+              kn = kn || fabsf(v - vhi) < band;
+              const float fwb = v >= vhi ? flf * A.w : 0.f;
+#pragma unroll
+              for (int q = 0; q < nz; ++q) {
+                const float4 cq = tp[q * pstride];
+                float Lv = fmaf(fmaf(fmaf(cq.w, tt, cq.z), tt, cq.y), tt, cq.x);
+                if (!NN) Lv = fmaxf(Lv, 0.f);
+                aS[q] = fmaf(B.x, Lv - B.y, aS[q]);
+                aT[q] = fmaf(A.z, __builtin_amdgcn_logf(fmaxf(Lv * A.w, fwb)), aT[q]);
+              }
+            }
+            for (int p = z_end + grp; p < n_scr; p += ngrp) {
+              const float4 A = recA[p], B = recB[p];
+              const float dx = ox - A.x, dy = oy - A.y;
+              const float v = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+              const int m = (int)fminf(v, (float)nlast);
+              const float tt = __builtin_amdgcn_fractf(v);
+              const float4* tp = ztab + m;
+              kn = kn || fabsf(v - vhi) < band;
+#pragma unroll
+              for (int q = 0; q < nz; ++q) {
+                const float4 cq = tp[q * pstride];
+                float Lv = fmaf(fmaf(fmaf(cq.w, tt, cq.z), tt, cq.y), tt, cq.x);
+                if (!NN) Lv = fmaxf(Lv, 0.f);
+                aS[q] = fmaf(B.x, Lv - B.y, aS[q]);
+              }
+            }
             float* o = scr + (grp * nxy + c) * nz * 2;
 #pragma unroll
             for (int q = 0; q < nz; ++q) {
               o[2 * q] = aS[q];
-              o[2 * q + 1] = aT[q];
+              o[2 * q + 1] = kn ? __builtin_nanf("") : aT[q];
             }
           }
         }
@@ -745,7 +880,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         // one each
         constexpr int LT = NT - 1;
         int p = 0;
-        for (; p + 2 <= npos; p += 2) {
+        for (; p + 2 <= n_ci; p += 2) {
           const float4 A0 = recA[p], B0 = recB[p], A1 = recA[p + 1], B1 = recB[p + 1];
           const float4 Ah = recA[p + hb], Bh = recB[p + hb];
           const int o0 = __float_as_int(B0.z), o1 = __float_as_int(B1.z), oh = __float_as_int(Bh.z);
@@ -762,7 +897,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           dS[LT] = fmaf(Bh.x, Lh - Bh.y, dS[LT]);
           T[LT] = fmaf(Ah.z, __builtin_amdgcn_logf(Lh * Ah.w), T[LT]);
         }
-        if (p < npos) {
+        if (p < n_ci) {
           const float4 A = recA[p], B = recB[p];
           const int o = __float_as_int(B.z);
 #pragma unroll
@@ -776,7 +911,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           dS[LT] = fmaf(B.x * w, Lh - B.y, dS[LT]);
           T[LT] = fmaf(A.z * w, __builtin_amdgcn_logf(Lh * A.w), T[LT]);
         }
-        for (p = npos; p + 2 <= na; p += 2) {
+        for (p = n_pos; p + 2 <= z_end; p += 2) {
           const float4 A0 = recA[p], B0 = recB[p], A1 = recA[p + 1], B1 = recB[p + 1];
           const float4 Ah = recA[p + hb], Bh = recB[p + hb];
           const int o0 = __float_as_int(B0.z), o1 = __float_as_int(B1.z), oh = __float_as_int(Bh.z);
@@ -790,7 +925,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           const float Lh = lrf32<KIND, NN>(nd[LT], Ah.x, Ah.y, oh, btab, L.c32, L.nc0, finv, nlast);
           dS[LT] = fmaf(Bh.x, Lh - Bh.y, dS[LT]);
         }
-        if (p < na) {
+        if (p < z_end) {
           const float4 A = recA[p], B = recB[p];
           const int o = __float_as_int(B.z);
 #pragma unroll
@@ -805,7 +940,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         T[LT] += __shfl_xor(T[LT], 32);
       } else {
         int p = 0;
-        for (; p + pstep <= npos; p += pstep) {
+        for (; p + pstep <= n_ci; p += pstep) {
           float4 A = recA[p + hb], B = recB[p + hb];
           int tofs = __float_as_int(B.z);
   #pragma unroll
@@ -815,7 +950,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
             T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
           }
         }
-        if (split && p < npos) {
+        if (split && p < n_ci) {
           // odd count: the first half takes the last sensor, the second adds
           // zero (or NaN where the first half's term is infinite already)
           float4 A = recA[p], B = recB[p];
@@ -825,8 +960,8 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
           T[0] = fmaf(A.z * w, __builtin_amdgcn_logf(Lv * A.w), T[0]);
         }
-        p = npos;
-        for (; p + pstep <= na; p += pstep) {
+        p = n_pos;
+        for (; p + pstep <= z_end; p += pstep) {
           float4 A = recA[p + hb], B = recB[p + hb];
           int tofs = __float_as_int(B.z);
   #pragma unroll
@@ -835,7 +970,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
             dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
           }
         }
-        if (split && p < na) {
+        if (split && p < z_end) {
           float4 A = recA[p], B = recB[p];
           const float w = hb ? 0.f : 1.f;
           float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
@@ -847,14 +982,48 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           T[0] += __shfl_xor(T[0], 32);
         }
       }
+      // edge sensors (the factored screen has its own loops), whole sums per
+      // node lane: a distance within the band
+      // of the domain end sends the node to FP64; beyond the end the LRF is
+      // zero and the logarithm takes the floor, as in FP64
+      bool knife[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) knife[t] = false;
+      if constexpr (KIND != ANTS_LRF_XY && !FA) {
+        for (int p = n_ci; p < n_pos; ++p) {
+          const float4 A = recA[p], B = recB[p];
+          const int o = __float_as_int(B.z);
+          const float fw = flf * A.w;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const float v = rad_v(nd[t], A.x, A.y);
+            const float Lv = rad32<NN>(rad_tab<KIND>(nd[t], btab, o), v, nlast);
+            knife[t] = knife[t] || fabsf(v - vhi) < band;
+            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+            T[t] = fmaf(A.z, __builtin_amdgcn_logf(fmaxf(Lv * A.w, v >= vhi ? fw : 0.f)), T[t]);
+          }
+        }
+        for (int p = z_end; p < n_scr; ++p) {
+          const float4 A = recA[p], B = recB[p];
+          const int o = __float_as_int(B.z);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const float v = rad_v(nd[t], A.x, A.y);
+            const float Lv = rad32<NN>(rad_tab<KIND>(nd[t], btab, o), v, nlast);
+            knife[t] = knife[t] || fabsf(v - vhi) < band;
+            dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+          }
+        }
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         float S = rel ? Sc + dS[t] : dS[t];
         float lS = rel ? log2_1p(dS[t] * iSc) : __builtin_amdgcn_logf(dS[t]);
         float d = N32 * lS - T[t];
-        // a sensor with counts where the screened LRF is 0 (or a rounding
-        // hole) makes d infinite or NaN: such nodes go to FP64, untrusted
-        const bool fin = d < kInf && d > -kInf;
+        // a sensor with counts where the screened LRF is 0 (a rounding hole)
+        // makes d infinite or NaN: such nodes go to FP64, untrusted, as do
+        // nodes at the domain end of an edge sensor
+        const bool fin = d < kInf && d > -kInf && !knife[t];
         const bool live = valid[t] && S > 0.f;
         D[t] = (live && fin) ? d : kInf;
         Snode[t] = (live && !fin) ? -1.0f : S;
@@ -864,7 +1033,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 #pragma unroll
       for (int t = 0; t < NT; ++t) { S[t] = 0.f; Q[t] = 0.f; }
       int p = 0;
-      for (; p + pstep <= na; p += pstep) {
+      for (; p + pstep <= n_scr; p += pstep) {
         float4 A = recA[p + hb], B = recB[p + hb];
         int tofs = __float_as_int(B.z);
 #pragma unroll
@@ -873,7 +1042,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           S[t] = fmaf(B.x, Lv, S[t]);
         }
       }
-      if (split && p < na) {
+      if (split && p < n_scr) {
         float4 A = recA[p], B = recB[p];
         float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
                                    finv, nlast);
@@ -882,7 +1051,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       if (split) S[0] += __shfl_xor(S[0], 32);
 #pragma unroll
       for (int t = 0; t < NT; ++t) Ag[t] = S[t] > 0.f ? N32 / S[t] : 0.f;
-      for (p = 0; p + pstep <= na; p += pstep) {
+      for (p = 0; p + pstep <= n_scr; p += pstep) {
         float4 A = recA[p + hb], B = recB[p + hb];
         int tofs = __float_as_int(B.z);
 #pragma unroll
@@ -894,7 +1063,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           Q[t] = fmaf(dd * dd, __builtin_amdgcn_rcpf(v), Q[t]);
         }
       }
-      if (split && p < na) {
+      if (split && p < n_scr) {
         float4 A = recA[p], B = recB[p];
         float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
                                    finv, nlast);
@@ -904,10 +1073,26 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         Q[0] = fmaf(hb ? 0.f : dd * dd, __builtin_amdgcn_rcpf(v), Q[0]);
       }
       if (split) Q[0] += __shfl_xor(Q[0], 32);
+      // nodes at the domain end of an edge sensor go to FP64 (untrusted)
+      bool knife[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) knife[t] = false;
+      if constexpr (KIND != ANTS_LRF_XY) {
+        auto mark = [&](int p0, int p1) {
+          for (int p = p0; p < p1; ++p) {
+            const float4 A = recA[p];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              knife[t] = knife[t] || fabsf(rad_v(nd[t], A.x, A.y) - vhi) < band;
+          }
+        };
+        mark(n_ci, n_pos);
+        mark(z_end, n_scr);
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        Snode[t] = S[t];
-        D[t] = (valid[t] && S[t] > 0.f && Q[t] < kInf) ? Q[t] : kInf;
+        Snode[t] = knife[t] ? -1.0f : S[t];
+        D[t] = (valid[t] && S[t] > 0.f && Q[t] < kInf && !knife[t]) ? Q[t] : kInf;
       }
     }
 
@@ -919,8 +1104,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     int jb = 1 << 30;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      trusted[t] = (STAT == ANTS_STAT_ML && rel) ? (Snode[t] >= 0.01f * Sc)
-                   : (STAT == ANTS_STAT_ML) ? !(Snode[t] < 0.f) : true;
+      trusted[t] = (STAT == ANTS_STAT_ML && rel) ? (Snode[t] >= 0.01f * Sc) : !(Snode[t] < 0.f);
       float v = trusted[t] ? D[t] : kInf;
       int j = t * 64 + lane;
       if (v < best || (v == best && j < jb)) { best = v; jb = j; }
@@ -1049,8 +1233,8 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         double S = 0.0, T = 0.0;
         if (ok) {
           for (int p = sub; p < na; p += 1 << lgs) {
-            const float n = recA[p].z;
             const SensorRec64 r = rec64[p];
+            const float n = r.n;
             double Lv;
             if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
             else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
@@ -1069,8 +1253,8 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           if (ok && S > 0.0) {
             const double Aa = N / S;
             for (int p = sub; p < na; p += 1 << lgs) {
-              const float n = recA[p].z;
               const SensorRec64 r = rec64[p];
+              const float n = r.n;
               double Lv;
               if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
               else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);

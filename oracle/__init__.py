@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY.  Nothing in the library (paper_1602_07247_amd/)
 imports, links or runs anything here; only tests/, the smoke check and the
 CPU-baseline leg of bench.py do.  The grid search itself is plain C
 (ants_oracle.c, double precision, one event at a time); the learned-seed
-network reference is NumPy float64 (mlp.py).  The two share no code with the
+network reference is NumPy float64 (mlp.py), and so is the LRF fit from
+events used by the iterative procedure (lrf_fit.py).  The two share no code with the
 HIP path.
 
 Sections of the paper each function follows are cited in ants_oracle.c.

@@ -328,6 +328,41 @@ ants_status ants_reconstruct_seeded(ants_lrfset* set, ants_mlp* mlp,
                                     const float* d_seeds, ants_out out, int32_t* d_n_fallback,
                                     void* hip_stream);
 
+/* ------------------------------------------------------------------ */
+/* LRF fit from events (Sec. 6: LRFs computed from signals and event    */
+/* positions; Sec. 6.2: one LRF for all sensors with relative gains;    */
+/* Sec. 8: the iterative procedure alternates it with the               */
+/* reconstruction and keeps only events that pass a filter).  Axial LRF,*/
+/* one shared table of nb + 2 cubic B-spline coefficients c: least      */
+/* squares on the estimates n_ie / (E_e g_i) of L(r_ie), one per (event */
+/* e, active sensor i) pair with lo <= r_ie <= hi (relative slack 1e-9  */
+/* of the span), all weighted 1; ridge * (mean diagonal) is added to    */
+/* the diagonal of the normal matrix.  An event enters when its status  */
+/* is 0, 0 < E < inf and, if chi2ndf_max > 0, ndf > 0 and               */
+/* chi2 / ndf <= chi2ndf_max.                                           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t nb;           /* breakpoints of the fitted spline, 4..62           */
+  double lo, hi;        /* domain in mm (lo = 0 for tables the reconstruction reads) */
+  double ridge;         /* relative ridge, >= 0 (1e-9 typical)               */
+  double chi2ndf_max;   /* event filter; <= 0: no chi2 cut                   */
+} ants_fit_cfg;
+
+/* Sensors (positions, gains, active set) are `set`'s; its LRF is not read.
+ * d_signals [n_events][ld] FP32 (ld >= n_sensors); rec: x, y, E, chi2, ndf
+ * and status per event (an ants_reconstruct output; z and lnl are not
+ * read).  Writes d_coef [nb + 2] FP64 and, when not NULL, d_counts [2]
+ * int64 = (events used, pairs used); both device memory, caller-owned.
+ * Everything runs on the device in FP64: per-wave normal equations in LDS,
+ * summed over the waves in a fixed order, then a Cholesky solve.  A normal
+ * matrix that is not positive definite (part of the domain without data
+ * and ridge 0) gives NaN coefficients.  The set keeps a workspace of
+ * 8 (5 (nb + 2) + 2) bytes per wave (at most 8 waves per compute unit);
+ * calls that share a set must not overlap in time. */
+ants_status ants_fit_axial_lrf(ants_lrfset* set, const ants_fit_cfg* cfg, int64_t n_events,
+                               const float* d_signals, int64_t ld, ants_out rec, double* d_coef,
+                               int64_t* d_counts, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,11 @@ class Plan(C.Structure):
                 ("table_in_lds", C.c_int32)]
 
 
+class FitCfg(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("lo", C.c_double), ("hi", C.c_double), ("ridge", C.c_double),
+                ("chi2ndf_max", C.c_double)]
+
+
 class Out(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in
                 ("x", "y", "z", "E", "lnl", "chi2", "ndf", "status", "path", "n_fp64")]
@@ -121,12 +126,15 @@ _lib.ants_autotune_multi.argtypes = [C.POINTER(_vp), C.POINTER(GridCfg), C.c_int
                                      C.POINTER(Chunk), C.c_int32, C.c_int64, Out, C.POINTER(Plan),
                                      C.POINTER(C.c_double), _vp]
 
+_lib.ants_fit_axial_lrf.argtypes = [_vp, C.POINTER(FitCfg), C.c_int64, _vp, C.c_int64, Out, _vp,
+                                    _vp, _vp]
+
 EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfset_destroy",
             "ants_lrfset_info", "ants_reconstruct", "ants_generate", "ants_mlp_create",
             "ants_mlp_destroy", "ants_mlp_num_params", "ants_mlp_get_params",
             "ants_mlp_set_params", "ants_mlp_forward", "ants_mlp_grad", "ants_mlp_train_step",
             "ants_mlp_train", "ants_mlp_save", "ants_mlp_load", "ants_reconstruct_seeded",
-            "ants_reconstruct_multi", "ants_autotune_multi")
+            "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf")
 
 
 def _check(code):
@@ -437,3 +445,64 @@ def autotune_multi(sets, cfgs, chunks, sample_events, stream=None):
                                     ms.ctypes.data_as(C.POINTER(C.c_double)),
                                     _stream_handle(stream)))
     return best, ms
+
+
+def fit_cfg(nb, lo, hi, ridge=1e-9, chi2ndf_max=0.0) -> FitCfg:
+    c = FitCfg()
+    c.nb, c.lo, c.hi, c.ridge, c.chi2ndf_max = int(nb), float(lo), float(hi), float(ridge), \
+        float(chi2ndf_max)
+    return c
+
+
+def fit_axial_lrf(lrfset: LrfSet, cfg: FitCfg, signals, rec, stream=None):
+    """Shared axial LRF fitted to `signals` ([n][n_sensors] float32, GPU) and
+    the reconstruction `rec` (dict of tensors from `reconstruct`) on the
+    sensors of `lrfset`.  Returns (coefficients [nb+2] float64, counts [2]
+    int64 = events, pairs used), device tensors (asynchronous)."""
+    import torch
+    assert signals.dtype == torch.float32 and signals.is_cuda and signals.dim() == 2
+    assert signals.stride(1) == 1 and signals.shape[1] == lrfset.n_sensors
+    n = signals.shape[0]
+    coef = torch.empty(cfg.nb + 2, dtype=torch.float64, device=signals.device)
+    counts = torch.empty(2, dtype=torch.int64, device=signals.device)
+    _check(_lib.ants_fit_axial_lrf(lrfset.handle, C.byref(cfg), n, signals.data_ptr(),
+                                   signals.stride(0), _out_struct(rec), coef.data_ptr(),
+                                   counts.data_ptr(), _stream_handle(stream)))
+    return coef, counts
+
+
+class AxialModel:
+    """Detector model with a shared axial LRF (the fields LrfSet reads)."""
+
+    def __init__(self, sxy, gain, active, nb, lo, hi, coef):
+        self.kind, self.shared = 1, 1
+        self.sxy = np.ascontiguousarray(sxy, np.float64)
+        self.gain = np.ascontiguousarray(gain, np.float64)
+        self.active = np.ascontiguousarray(active, np.uint8)
+        self.nb, self.lo, self.hi = (int(nb), 1), (float(lo), 0.0), (float(hi), 0.0)
+        self.coef = np.ascontiguousarray(coef, np.float64).reshape(1, 1, int(nb) + 2)
+
+
+def iterate_axial_lrf(model, grid: GridCfg, signals, iterations, ridge=1e-9, chi2ndf_max=0.0,
+                      stream=None):
+    """Iterative LRF reconstruction (Sec. 8): reconstruct every event with the
+    current LRF, keep the events that pass the filter, fit the LRF to their
+    signals, reconstructed positions and energies, repeat.  `model` is the
+    initial guess (an axial model with one shared table).  Returns the list
+    of models, the initial one first, and the last reconstruction."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    models = [model]
+    for k in range(iterations + 1):
+        cur = models[-1]
+        ls = LrfSet(cur)
+        rec = reconstruct(ls, grid, signals, stream=st)
+        if k < iterations:
+            coef, _ = fit_axial_lrf(ls, fit_cfg(cur.nb[0], cur.lo[0], cur.hi[0], ridge,
+                                                chi2ndf_max), signals, rec, st)
+        st.synchronize()
+        ls.close()
+        if k < iterations:
+            models.append(AxialModel(cur.sxy, cur.gain, cur.active, cur.nb[0], cur.lo[0],
+                                     cur.hi[0], coef.cpu().numpy()))
+    return models, rec

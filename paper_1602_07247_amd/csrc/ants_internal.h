@@ -242,4 +242,7 @@ struct ants_lrfset {
   // workspace of the multi-detector launch (descriptors, counter)
   void* ws_multi = nullptr;
   size_t ws_multi_bytes = 0;
+  // workspace of the LRF fit (per-wave partial normal equations)
+  void* ws_fit = nullptr;
+  size_t ws_fit_bytes = 0;
 };

@@ -203,6 +203,7 @@ ants_status ants_lrfset_destroy(ants_lrfset* set) {
   if (set->ws_list) (void)hipFree(set->ws_list);
   if (set->ws_count) (void)hipFree(set->ws_count);
   if (set->ws_multi) (void)hipFree(set->ws_multi);
+  if (set->ws_fit) (void)hipFree(set->ws_fit);
   delete set;
   return ANTS_OK;
 }

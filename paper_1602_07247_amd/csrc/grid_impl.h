@@ -1116,12 +1116,27 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     // ---- error bound of the screen at the best node (lane-parallel over sensors)
     float margin = 0.f;
     if (best < kInf) {
+      // the best node's screened S and FP32 node description, from its lane
+      const int tb = jb >> 6, lb = jb & 63;
+      float Sb = 0.f;
       NodeF<KIND> ndb;
-      double xx, yy, zz;
-      make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, nodeidx, ndb, xx, yy, zz);
+      if constexpr (KIND == ANTS_LRF_XY) {
+        double xx, yy, zz;
+        make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, nodeidx, ndb, xx, yy, zz);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t == tb) {
+          Sb = lane_val(Snode[t], lb);
+          if constexpr (KIND != ANTS_LRF_XY) {
+            ndb.ox = lane_val(nd[t].ox, lb);
+            ndb.oy = lane_val(nd[t].oy, lb);
+          }
+          if constexpr (KIND == ANTS_LRF_RZ) ndb.tab = ztab + lane_val((int)(nd[t].tab - ztab), lb);
+        }
+      }
       float Lb[SL];
       float4 RA[SL], RB[SL];
-      float Sb = 0.f;
 #pragma unroll
       for (int q = 0; q < SL; ++q) {
         int a = lane + 64 * q;
@@ -1133,10 +1148,8 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           RB[q] = recB[posq[q]];
           Lb[q] = lrf32<KIND, NN>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab, L.c32,
                               L.nc0, finv, nlast);
-          Sb = fmaf(RB[q].x, Lb[q], Sb);
         }
       }
-      Sb = wsum_f(Sb);
       if (STAT == ANTS_STAT_ML) {
         float A1 = 0.f, A2 = 0.f, A3 = 0.f;
         float iSb = Sb > 0.f ? 1.0f / Sb : 0.f;

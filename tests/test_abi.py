@@ -95,3 +95,13 @@ def test_reconstruct_argument_errors(ants):
     assert ants._lib.ants_reconstruct(None, C.byref(cfg), 10, None, None, out, None) == ants.E_ARG
     assert ants._lib.ants_lrfset_create(None, C.byref(C.c_void_p())) == ants.E_ARG
     assert ants._lib.ants_lrfset_destroy(None) == ants.OK
+
+
+def test_fit_argument_errors(ants):
+    cfg = ants.fit_cfg(20, 0.0, 150.0)
+    out = ants.Out()
+    coef = C.c_void_p(1)
+    assert ants._lib.ants_fit_axial_lrf(None, C.byref(cfg), 0, None, 0, out, coef, None,
+                                        None) == ants.E_ARG
+    assert ants._lib.ants_fit_axial_lrf(None, None, 0, None, 0, out, coef, None,
+                                        None) == ants.E_ARG

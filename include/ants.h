@@ -354,11 +354,11 @@ typedef struct {
  * read).  Writes d_coef [nb + 2] FP64 and, when not NULL, d_counts [2]
  * int64 = (events used, pairs used); both device memory, caller-owned.
  * Everything runs on the device in FP64: per-wave normal equations in LDS,
- * summed over the waves in a fixed order, then a Cholesky solve.  A normal
+ * summed over the waves by a fixed tree, then a Cholesky solve.  A normal
  * matrix that is not positive definite (part of the domain without data
  * and ridge 0) gives NaN coefficients.  The set keeps a workspace of
- * 8 (5 (nb + 2) + 2) bytes per wave (at most 8 waves per compute unit);
- * calls that share a set must not overlap in time. */
+ * 8 (5 (nb + 2) + 2) bytes per wave (at most 32 waves per compute unit, plus
+ * one for the sums); calls that share a set must not overlap in time. */
 ants_status ants_fit_axial_lrf(ants_lrfset* set, const ants_fit_cfg* cfg, int64_t n_events,
                                const float* d_signals, int64_t ld, ants_out rec, double* d_coef,
                                int64_t* d_counts, void* hip_stream);

@@ -7,7 +7,7 @@
 // sensor) pair inside the domain.  The normal matrix is banded (a pair
 // touches four consecutive coefficients), so each wave accumulates its band
 // (4 diagonals) and right-hand side in FP64 in its own LDS area; the waves'
-// partial sums are added in a fixed order and one wave solves the system by
+// partial sums are added by a fixed tree and one wave solves the system by
 // Cholesky.  Results do not depend on the launch's timing.
 #include <math.h>
 #include <string.h>
@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kFitMaxCoef = 64;
 constexpr int kFitWaves = 4;   // waves per block of the accumulation
+constexpr int kFitCopies = 4;  // accumulator copies per wave (lane % 4), fewer same-address atomics
 
 struct FitP {
   const int32_t* col;
@@ -41,8 +42,9 @@ __global__ void __launch_bounds__(64 * kFitWaves) fit_accum_kernel(FitP P) {
   extern __shared__ double fsm[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nc = P.nc;
-  double* acc = fsm + wv * (nc * 5);
-  for (int i = lane; i < nc * 5; i += 64) acc[i] = 0.0;
+  double* wacc = fsm + wv * (nc * 5 * kFitCopies);
+  double* acc = wacc + (lane % kFitCopies) * (nc * 5);
+  for (int i = lane; i < nc * 5 * kFitCopies; i += 64) wacc[i] = 0.0;
   __syncthreads();
   const int64_t gw = (int64_t)blockIdx.x * kFitWaves + wv;
   const int64_t nw = (int64_t)gridDim.x * kFitWaves;
@@ -78,7 +80,11 @@ __global__ void __launch_bounds__(64 * kFitWaves) fit_accum_kernel(FitP P) {
   }
   __syncthreads();
   double* out = P.part + gw * P.stride;
-  for (int i = lane; i < nc * 5; i += 64) out[i] = acc[i];
+  for (int i = lane; i < nc * 5; i += 64) {
+    double v = wacc[i];
+    for (int c = 1; c < kFitCopies; ++c) v += wacc[c * nc * 5 + i];
+    out[i] = v;
+  }
   // pair count of the wave (each lane counted its own pairs)
   for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o);
   if (lane == 0) {
@@ -98,24 +104,34 @@ struct SolveP {
   const double* part;
   int stride, nwaves, nc;
   double ridge;
+  double* sums;      // [stride]: the waves' partials added up
   double* coef;
   int64_t* counts;
 };
 
-__global__ void __launch_bounds__(256) fit_solve_kernel(SolveP P) {
+// One block per entry of the partials: the waves' values added by a fixed
+// tree (thread t takes waves t, t + 256, ...; then pairwise halving).
+__global__ void __launch_bounds__(256) fit_reduce_kernel(SolveP P) {
+  __shared__ double red[256];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int w = tid; w < P.nwaves; w += 256) s += P.part[(int64_t)w * P.stride + i];
+  red[tid] = s;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) P.sums[i] = red[0];
+}
+
+__global__ void __launch_bounds__(64) fit_solve_kernel(SolveP P) {
   __shared__ double band[kFitMaxCoef * 5 + 2];
   __shared__ double A[kFitMaxCoef][kFitMaxCoef + 1];
   __shared__ double y[kFitMaxCoef];
-  const int tid = threadIdx.x, nc = P.nc;
-  // partial sums of the waves, in wave order
-  for (int i = tid; i < nc * 5 + 2; i += blockDim.x) {
-    double s = 0.0;
-    for (int w = 0; w < P.nwaves; ++w) s += P.part[(int64_t)w * P.stride + i];
-    band[i] = s;
-  }
-  __syncthreads();
-  if (tid >= 64) return;   // the solve is one wave's
-  const int lane = tid;
+  const int lane = threadIdx.x, nc = P.nc;
+  for (int i = lane; i < nc * 5 + 2; i += 64) band[i] = P.sums[i];
+  wave_sync();
   // dense symmetric matrix from the band, plus the relative ridge
   for (int i = 0; i < nc; ++i)
     for (int j = lane; j < nc; j += 64) {
@@ -190,11 +206,12 @@ extern "C" ants_status ants_fit_axial_lrf(ants_lrfset* set, const ants_fit_cfg* 
   const int nc = cfg->nb + 2;
   const int stride = nc * 5 + 2;
   int64_t blocks = (n_events + kFitWaves - 1) / kFitWaves;
-  const int64_t cap = (int64_t)num_cu() * 2;
+  const int64_t cap = (int64_t)num_cu() * 8;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   const int nwaves = (int)blocks * kFitWaves;
-  hipError_t e = ensure(&set->ws_fit, &set->ws_fit_bytes, (size_t)nwaves * stride * sizeof(double));
+  hipError_t e = ensure(&set->ws_fit, &set->ws_fit_bytes,
+                        ((size_t)nwaves + 1) * stride * sizeof(double));
   if (e != hipSuccess) return hip_error(e, "ants_fit_axial_lrf workspace");
   FitP P;
   memset(&P, 0, sizeof(P));
@@ -220,7 +237,7 @@ extern "C" ants_status ants_fit_axial_lrf(ants_lrfset* set, const ants_fit_cfg* 
   P.inv_d = (double)(cfg->nb - 1) / (cfg->hi - cfg->lo);
   P.part = (double*)set->ws_fit;
   P.stride = stride;
-  const size_t smem = (size_t)kFitWaves * nc * 5 * sizeof(double);
+  const size_t smem = (size_t)kFitWaves * kFitCopies * nc * 5 * sizeof(double);
   hipLaunchKernelGGL(fit_accum_kernel, dim3((unsigned)blocks), dim3(64 * kFitWaves), smem, s, P);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "ants_fit_axial_lrf accumulation");
@@ -230,9 +247,13 @@ extern "C" ants_status ants_fit_axial_lrf(ants_lrfset* set, const ants_fit_cfg* 
   S.nwaves = nwaves;
   S.nc = nc;
   S.ridge = cfg->ridge;
+  S.sums = P.part + (size_t)nwaves * stride;
   S.coef = d_coef;
   S.counts = d_counts;
-  hipLaunchKernelGGL(fit_solve_kernel, dim3(1), dim3(256), 0, s, S);
+  hipLaunchKernelGGL(fit_reduce_kernel, dim3(stride), dim3(256), 0, s, S);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(e, "ants_fit_axial_lrf reduction");
+  hipLaunchKernelGGL(fit_solve_kernel, dim3(1), dim3(64), 0, s, S);
   e = hipGetLastError();
   return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_fit_axial_lrf solve");
 }

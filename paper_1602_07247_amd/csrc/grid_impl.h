@@ -555,6 +555,14 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     sz = uni(G.nz > 1 ? st[3 * kk + 2] : 0.0);
   }
   int nfp = 0;
+  // LRF values at the previous iteration's best screened node: the next
+  // centre is that node or a near-tie neighbour, so they serve as the next
+  // iteration's reference values (the centre-relative form is exact for any
+  // reference; its rounding only needs the reference near the nodes)
+  float Lprev[SL];
+  bool have_prev = false;
+#pragma unroll
+  for (int q = 0; q < SL; ++q) Lprev[q] = 0.f;
   for (int k = 0; k < Kev; ++k) {
     const int lk = opaque(lane);
     // ---- r-z: collapse the table along z for this iteration's planes
@@ -614,7 +622,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 
     // ---- reference at the centre, per sensor (lane-parallel)
     NodeF<KIND> ndc;
-    {
+    if (!have_prev) {
       double xx, yy, zz;
       int jc = (G.hz * G.ny + G.hy) * G.nx + G.hx;
       make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jc, ztab, nodeidx, ndc, xx, yy, zz);
@@ -648,7 +656,9 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       if (a < na) {
         const SensorRec64 r = rec64[a];
         const float dX = (float)((r.X - cx) * L.inv_d0), dY = (float)((r.Y - cy) * L.inv_d0);
-        const float Lc = lrf32<KIND, NN>(ndc, dX, dY, tofq[q], btab, L.c32, L.nc0, finv, nlast);
+        const float Lc = have_prev ? Lprev[q]
+                                   : lrf32<KIND, NN>(ndc, dX, dY, tofq[q], btab, L.c32, L.nc0,
+                                                     finv, nlast);
         Sc = fmaf((float)r.g, Lc, Sc);
         dXq[q] = dX;
         dYq[q] = dY;
@@ -1115,6 +1125,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 
     // ---- error bound of the screen at the best node (lane-parallel over sensors)
     float margin = 0.f;
+    have_prev = best < kInf;
     if (best < kInf) {
       // the best node's screened S and FP32 node description, from its lane
       const int tb = jb >> 6, lb = jb & 63;
@@ -1149,6 +1160,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           Lb[q] = lrf32<KIND, NN>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab, L.c32,
                               L.nc0, finv, nlast);
         }
+        Lprev[q] = Lb[q];
       }
       if (STAT == ANTS_STAT_ML) {
         float A1 = 0.f, A2 = 0.f, A3 = 0.f;

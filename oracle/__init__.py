@@ -46,7 +46,8 @@ class _Cfg(C.Structure):
                 ("step0", C.c_double * 3), ("z_start", C.c_double), ("stat", C.c_int),
                 ("start", C.c_int), ("l_floor", C.c_double), ("v_floor", C.c_double),
                 ("seed_steps", C.c_int), ("seed_kappa", C.c_double), ("seed_kmin", C.c_int),
-                ("seed_kmax", C.c_int), ("seed_scale", C.c_double * 3)]
+                ("seed_kmax", C.c_int), ("seed_scale", C.c_double * 3),
+                ("cut_signal", C.c_double), ("cut_distance", C.c_double)]
 
 
 _lib = None
@@ -138,6 +139,8 @@ def _cfg(g):
     c.seed_kmax = int(getattr(g, "seed_kmax", 1))
     for k, v in enumerate(getattr(g, "seed_scale", (0.0, 0.0, 0.0))):
         c.seed_scale[k] = float(v)
+    c.cut_signal = float(getattr(g, "cut_signal", 0.0))
+    c.cut_distance = float(getattr(g, "cut_distance", 0.0))
     return c
 
 

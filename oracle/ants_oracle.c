@@ -66,6 +66,10 @@ typedef struct {
   double seed_kappa;
   int seed_kmin, seed_kmax;
   double seed_scale[3];
+  /* sensor cuts (Sec. 5.1.2): ignore sensors with a signal below
+   * cut_signal, or farther (in x-y) than cut_distance from the start
+   * position; <= 0 disables a cut */
+  double cut_signal, cut_distance;
 } o_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -348,6 +352,34 @@ void o_event(const o_lrf* L, const o_cfg* C, const double* n, const double* seed
   }
   if (dim == 2) c[2] = C->z_start;
 
+  /* Sensor cuts (Sec. 5.1.2).  Reading: the start position uses every
+   * active sensor; the ignored ones then leave the statistic, the energy
+   * ratio, the outputs and ndf for the whole event, exactly as if they were
+   * passive. */
+  uint8_t* use = NULL;
+  o_lrf Lcut;
+  if (C->cut_signal > 0.0 || C->cut_distance > 0.0) {
+    use = (uint8_t*)malloc((size_t)ns);
+    int nu = 0;
+    N = 0.0;
+    for (int i = 0; i < ns; ++i) {
+      int u = L->active[i] != 0;
+      if (u && C->cut_signal > 0.0 && n[i] < C->cut_signal) u = 0;
+      if (u && C->cut_distance > 0.0) {
+        double dx = L->sxy[2 * i] - c[0], dy = L->sxy[2 * i + 1] - c[1];
+        if (sqrt(dx * dx + dy * dy) > C->cut_distance) u = 0;
+      }
+      use[i] = (uint8_t)u;
+      if (u) { ++nu; N += n[i]; }
+    }
+    Lcut = *L;
+    Lcut.active = use;
+    L = &Lcut;
+    *ndf = nu - (dim + 1);
+    if (nu == 0) { *status = O_NO_ACTIVE; free(use); return; }
+    if (!(N > 0.0)) { *status = O_EMPTY; free(use); return; }
+  }
+
   int nn = C->nodes[0] * C->nodes[1] * C->nodes[2];
   double s[3] = {C->step0[0], C->step0[1], C->step0[2]};
   int K = C->iterations;
@@ -408,6 +440,7 @@ void o_event(const o_lrf* L, const o_cfg* C, const double* n, const double* seed
   o_node r = o_node_eval(L, C, n, N, c[0], c[1], c[2]);
   out[0] = c[0]; out[1] = c[1]; out[2] = c[2];
   out[3] = r.A; out[4] = r.lnl; out[5] = r.chi2;
+  free(use);
 }
 
 /* Batch over events; signals [n_ev][n_sensors] as double. */

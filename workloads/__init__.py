@@ -126,6 +126,8 @@ class GridCfg:
     seed_kmin: int = 1
     seed_kmax: int = 1
     seed_scale: tuple = (0.0, 0.0, 0.0)
+    cut_signal: float = 0.0    # ignore sensors with a signal below this (0 = off)
+    cut_distance: float = 0.0  # ignore sensors farther than this from the start, mm (0 = off)
 
     @property
     def final_step(self):

@@ -144,6 +144,14 @@ typedef struct {
   double seed_kappa;
   int32_t seed_kmin, seed_kmax;
   double seed_scale[3];
+  /* Sensor cuts (Sec. 5.1.2): an event ignores the active sensors with a
+   * signal below cut_signal, or farther in x-y than cut_distance (mm) from
+   * its start position; 0 disables a cut.  The start position uses every
+   * active sensor; the ignored ones then leave the statistic, the energy
+   * ratio, the outputs and ndf, as if passive for that event.  No sensor
+   * left gives ANTS_EV_NO_ACTIVE, no signal left ANTS_EV_EMPTY. */
+  double cut_signal;
+  double cut_distance;
 } ants_grid_cfg;
 
 /* Caller-owned device arrays of length n_events (path: [n][iterations]).

@@ -47,7 +47,8 @@ class GridCfg(C.Structure):
                 ("start", C.c_int32), ("l_floor", C.c_double), ("v_floor", C.c_double),
                 ("screen_scale", C.c_double), ("seed_steps", C.c_int32),
                 ("seed_kappa", C.c_double), ("seed_kmin", C.c_int32), ("seed_kmax", C.c_int32),
-                ("seed_scale", C.c_double * 3)]
+                ("seed_scale", C.c_double * 3), ("cut_signal", C.c_double),
+                ("cut_distance", C.c_double)]
 
 
 class GenCfg(C.Structure):
@@ -213,6 +214,8 @@ def grid_cfg(g, screen_scale: float = 0.0) -> GridCfg:
     c.seed_kmax = int(getattr(g, "seed_kmax", 1))
     for k, v in enumerate(getattr(g, "seed_scale", (0.0, 0.0, 0.0))):
         c.seed_scale[k] = float(v)
+    c.cut_signal = float(getattr(g, "cut_signal", 0.0))
+    c.cut_distance = float(getattr(g, "cut_distance", 0.0))
     return c
 
 

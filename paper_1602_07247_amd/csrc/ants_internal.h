@@ -91,6 +91,8 @@ struct GridP {
   int kmin, kmax;      // iteration count range
   double sscale[3];    // mm per unit of the seed's standard deviation, per axis
   double sfinal[3];    // final step per axis (= step0 * shrink^(iterations-1))
+  double cut_signal;   // > 0: ignore sensors with a signal below it
+  double cut_dist;     // > 0: ignore sensors farther (x-y) than it from the start
   double fb_thr;       // > 0: events with chi2/ndf above it go to the fallback list
   int or_status;       // status bits OR-ed into every processed event
 };

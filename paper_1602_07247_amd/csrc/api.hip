@@ -158,6 +158,12 @@ ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
   G.vfloor = cfg->v_floor;
   double sc = cfg->screen_scale == 0.0 ? 1.0 : cfg->screen_scale;
   G.margin_scale = sc > 3e38 ? 3e38f : (float)sc;
+  if (!(cfg->cut_signal >= 0.0 && cfg->cut_signal < 1e300) ||
+      !(cfg->cut_distance >= 0.0 && cfg->cut_distance < 1e300))
+    return set_error(ANTS_E_ARG, "cut_signal = %g / cut_distance = %g must be finite and >= 0",
+                     cfg->cut_signal, cfg->cut_distance);
+  G.cut_signal = cfg->cut_signal;
+  G.cut_dist = cfg->cut_distance;
   G.seed_steps = 0;
   if (cfg->start == ANTS_START_SEED && cfg->seed_steps) {
     if (!(cfg->seed_kmin >= 1 && cfg->seed_kmin <= cfg->seed_kmax && cfg->seed_kmax <= G.K &&

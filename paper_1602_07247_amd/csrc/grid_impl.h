@@ -450,7 +450,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   }
   bool any_bad = __ballot(bad) != 0ull;
   N = uni(wsum_d(N));
-  const int ndf = na - (G.dim + 1);
+  int ndf = na - (G.dim + 1);
   int status = 0;
   if (na == 0) status = ANTS_EV_NO_ACTIVE;
   else if (any_bad) status = ANTS_EV_BAD_INPUT;
@@ -489,24 +489,70 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   cy = uni(cy);
   cz = uni(cz);
 
-  // record positions with counted sensors first (the order of every
-  // iteration in which no sensor reaches the end of the LRF domain)
-  int posq0[SL], npos0 = 0;
-  {
-    uint64_t mpos[SL], mzero[SL];
+  // sensor cuts: sensors with a signal below cut_signal or farther (x-y)
+  // than cut_dist from the start are passive for the rest of the event
+  bool ign[SL];
+  int na_ev = na;
+#pragma unroll
+  for (int q = 0; q < SL; ++q) ign[q] = false;
+  if (G.cut_signal > 0.0 || G.cut_dist > 0.0) {
+    double Nk = 0.0;
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
       const int a = lane + 64 * q;
-      mpos[q] = __ballot(a < na && nq[q] > 0.f);
-      mzero[q] = __ballot(a < na && !(nq[q] > 0.f));
-      npos0 += __popcll(mpos[q]);
+      if (a < na) {
+        bool ig = G.cut_signal > 0.0 && (double)nq[q] < G.cut_signal;
+        if (G.cut_dist > 0.0) {
+          const double dx = L.X[a] - cx, dy = L.Y[a] - cy;
+          ig = ig || sqrt(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy))) > G.cut_dist;
+        }
+        ign[q] = ig;
+        if (!ig) Nk += (double)nq[q];
+      }
     }
-    int bp = 0, bz = npos0;
+    int nk = 0;
+#pragma unroll
+    for (int q = 0; q < SL; ++q) nk += __popcll(__ballot(lane + 64 * q < na && !ign[q]));
+    N = uni(wsum_d(Nk));
+    na_ev = nk;
+    ndf = nk - (G.dim + 1);
+    const int st = nk == 0 ? ANTS_EV_NO_ACTIVE : !(N > 0.0) ? ANTS_EV_EMPTY : 0;
+    if (st) {
+      if (lane == 0) {
+        float nan = __builtin_nanf("");
+        io.x[e] = nan; io.y[e] = nan; io.z[e] = nan; io.E[e] = nan;
+        io.lnl[e] = nan; io.chi2[e] = nan; io.ndf[e] = ndf; io.status[e] = st | G.or_status;
+        if (io.nfp) io.nfp[e] = 0;
+      }
+      if (io.path && lane < G.K) io.path[e * G.K + lane] = -1;
+      return;
+    }
+  }
+
+  // record positions with counted sensors first, then silent ones, then the
+  // ignored (the order of every iteration in which no sensor reaches the end
+  // of the LRF domain)
+  int posq0[SL], npos0 = 0;
+  {
+    uint64_t mpos[SL], mzero[SL], mign[SL];
+    int nzero = 0;
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
-      posq0[q] = nq[q] > 0.f ? bp + prefix_count(mpos[q]) : bz + prefix_count(mzero[q]);
+      const int a = lane + 64 * q;
+      mpos[q] = __ballot(a < na && !ign[q] && nq[q] > 0.f);
+      mzero[q] = __ballot(a < na && !ign[q] && !(nq[q] > 0.f));
+      mign[q] = __ballot(a < na && ign[q]);
+      npos0 += __popcll(mpos[q]);
+      nzero += __popcll(mzero[q]);
+    }
+    int bp = 0, bz = npos0, bi = npos0 + nzero;
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      posq0[q] = ign[q] ? bi + prefix_count(mign[q])
+                 : nq[q] > 0.f ? bp + prefix_count(mpos[q]) : bz + prefix_count(mzero[q]);
       bp += __popcll(mpos[q]);
       bz += __popcll(mzero[q]);
+      bi += __popcll(mign[q]);
     }
   }
   // FP64 sensor records in sensor order; FP32 table offsets in registers
@@ -522,7 +568,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       r.Y = L.Y[a];
       r.g = L.g[a];
       r.coff = coef_off64<KIND>(L, a);
-      r.n = nq[q];
+      r.n = ign[q] ? -1.0f : nq[q];   // negative: ignored by the cuts
       rec64[a] = r;
       tofq[q] = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
     }
@@ -659,19 +705,19 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         const float Lc = have_prev ? Lprev[q]
                                    : lrf32<KIND, NN>(ndc, dX, dY, tofq[q], btab, L.c32, L.nc0,
                                                      finv, nlast);
-        Sc = fmaf((float)r.g, Lc, Sc);
+        if (!ign[q]) Sc = fmaf((float)r.g, Lc, Sc);
         dXq[q] = dX;
         dYq[q] = dY;
         Lcq[q] = Lc;
         if constexpr (KIND != ANTS_LRF_XY) {
           const float fx = fabsf(dX) + ex, fy = fabsf(dY) + ey;
-          reach = reach || !(fmaf(fx, fx, fy * fy) < lo2);
+          reach = reach || (!ign[q] && !(fmaf(fx, fx, fy * fy) < lo2));
         }
       }
     }
     Sc = uni(wsum_f(Sc));
     const bool rel = Sc > 0.f;   // centre-relative form available
-    int n_ci = npos0, n_pos = npos0, z_end = na, n_scr = na;
+    int n_ci = npos0, n_pos = npos0, z_end = na_ev, n_scr = na_ev;
     if (__ballot(reach) == 0ull) {
 #pragma unroll
       for (int q = 0; q < SL; ++q) posq[q] = posq0[q];
@@ -685,7 +731,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         const float nx0 = fmaxf(ax - ex, 0.f), ny0 = fmaxf(ay - ey, 0.f);
         const float fx = ax + ex, fy = ay + ey;
         const int cls = fmaf(fx, fx, fy * fy) < lo2 ? 0 : fmaf(nx0, nx0, ny0 * ny0) > hi2 ? 2 : 1;
-        key[q] = cls == 2 ? 4 : (nq[q] > 0.f ? 0 : 2) + cls;
+        key[q] = (cls == 2 || ign[q]) ? 4 : (nq[q] > 0.f ? 0 : 2) + cls;
       }
       uint64_t mk[SL][5];
       int cnt[5] = {0, 0, 0, 0, 0};
@@ -1154,7 +1200,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
         Lb[q] = 0.f;
         RA[q] = make_float4(0.f, 0.f, 0.f, 1.f);
         RB[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (a < na) {
+        if (a < na && !ign[q]) {
           RA[q] = recA[posq[q]];
           RB[q] = recB[posq[q]];
           Lb[q] = lrf32<KIND, NN>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab, L.c32,
@@ -1168,7 +1214,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 #pragma unroll
         for (int q = 0; q < SL; ++q) {
           int a = lane + 64 * q;
-          if (a < na) {
+          if (a < na && !ign[q]) {
             float mu = N32 * RB[q].x * Lb[q] * iSb;
             A1 += fabsf(mu - RA[q].z);
             A2 += fabsf(RA[q].z * __builtin_amdgcn_logf(fmaxf(Lb[q], flf) * RA[q].w));
@@ -1191,7 +1237,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 #pragma unroll
         for (int q = 0; q < SL; ++q) {
           int a = lane + 64 * q;
-          if (a < na) {
+          if (a < na && !ign[q]) {
             float mu = Ab * RB[q].x * Lb[q];
             float dd = RA[q].z - mu;
             float v = fmaxf(mu, fvf);
@@ -1260,6 +1306,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
           for (int p = sub; p < na; p += 1 << lgs) {
             const SensorRec64 r = rec64[p];
             const float n = r.n;
+            if (n < 0.f) continue;   // ignored by the sensor cuts
             double Lv;
             if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
             else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
@@ -1280,6 +1327,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
             for (int p = sub; p < na; p += 1 << lgs) {
               const SensorRec64 r = rec64[p];
               const float n = r.n;
+              if (n < 0.f) continue;   // ignored by the sensor cuts
               double Lv;
               if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
               else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
@@ -1334,7 +1382,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   for (int q = 0; q < SL; ++q) {
     int a = lane + 64 * q;
     Lf[q] = 0.0;
-    if (a < na) {
+    if (a < na && !ign[q]) {
       Lf[q] = lrf64<KIND>(L, a, cx, cy, cz);
       S += L.g[a] * Lf[q];
     }
@@ -1346,7 +1394,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
       int a = lane + 64 * q;
-      if (a < na) {
+      if (a < na && !ign[q]) {
         double mu = Aa * L.g[a] * Lf[q];
         double Lt = Lf[q] > G.lfloor ? Lf[q] : G.lfloor;
         double n = (double)nq[q];

@@ -382,6 +382,11 @@ __device__ __forceinline__ bool make_node(const DevLrf& L, const GridP& G, doubl
   return valid;
 }
 
+// exp(s / 2) of a seed's log-variance, once per event: kept out of line so
+// that the exponential's constants are not held in registers (and spilled)
+// across the event loop
+__device__ __attribute__((noinline)) double seed_sigma(double s) { return exp(0.5 * s); }
+
 // log2(1 + x) with small relative error for small |x| (per node only)
 __device__ __forceinline__ float log2_1p(float x) {
   float u = 1.0f + x;
@@ -581,7 +586,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
     // in [kmin, kmax] whose first step covers kappa * sigma on every axis,
     // ending on the configured final step
     const double lv = io.seeds[e * 4 + 3];
-    const double sg = uni(exp(0.5 * lv) * G.kappa);
+    const double sg = uni(seed_sigma(lv) * G.kappa);
     const double* st = W.sstep;
     int kk = G.kmin - 1;
     if (!(sg < __builtin_huge_val())) {
@@ -1447,9 +1452,25 @@ cg_kernel(DevLrf L, GridP G, IoP io, int64_t waves_total, int per_wave_bytes, in
   unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
   wave_setup<KIND, NT, (FZ > 0)>(wbase, L, G, lane0);
   int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
-  for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
-    const int64_t e = io.list ? (int64_t)io.list[w] : w;
-    process_event<KIND, STAT, NT, SL, NN, FZ>(L, G, io, e, btab, wbase, opaque(lane0));
+  if ((gridDim.x & 7) == 0) {
+    // workgroups go round-robin to the 8 XCDs, each with its own L2: block b
+    // runs on XCD b % 8.  Each XCD takes whole runs of 32 consecutive work
+    // items (a 128-byte line of every 4-byte output array, and neighbouring
+    // signal rows), its waves striding over them, so lines are not split
+    // between L2s.
+    const int64_t x = blockIdx.x & 7;
+    const int64_t nwx = (int64_t)(gridDim.x >> 3) * nwb;
+    for (int64_t i = (int64_t)(blockIdx.x >> 3) * nwb + wv;; i += nwx) {
+      const int64_t w = (((i >> 5) << 3) + x) * 32 + (i & 31);
+      if (w >= nwork) break;
+      const int64_t e = io.list ? (int64_t)io.list[w] : w;
+      process_event<KIND, STAT, NT, SL, NN, FZ>(L, G, io, e, btab, wbase, opaque(lane0));
+    }
+  } else {
+    for (int64_t w = (int64_t)blockIdx.x * nwb + wv; w < nwork; w += waves_total) {
+      const int64_t e = io.list ? (int64_t)io.list[w] : w;
+      process_event<KIND, STAT, NT, SL, NN, FZ>(L, G, io, e, btab, wbase, opaque(lane0));
+    }
   }
 }
 
@@ -1478,6 +1499,7 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
     max_blocks = resident * num_cu();
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
+  if (blocks > 8) blocks = blocks / 8 * 8;   // XCD-aware work order (see cg_kernel)
   int64_t waves_total = blocks * kWavesPerBlock;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), smem, stream, L, G,
                      io, waves_total, per_wave, btab_n);

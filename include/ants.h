@@ -323,7 +323,7 @@ ants_status ants_mlp_load(const char* path, ants_mlp** out);
  * (x, y, z, log-variance) in mm when d_seeds is not NULL, and then mlp may be
  * NULL), a refinement grid `refine` started at the seed (start = SEED,
  * normally seed_steps = 1), and events whose refined chi2/ndf exceeds
- * chi2ndf_max (or is not finite, or ndf <= 0) run again with `fallback`
+ * chi2ndf_max >= 0 (or is not finite, or ndf <= 0) run again with `fallback`
  * (normally the plain grid from the centroid) and get ANTS_EV_FALLBACK.
  * d_n_fallback (one int32, device) receives the number of such events.
  * The network runs as one fused kernel (no activation buffers).  The

@@ -93,7 +93,7 @@ struct GridP {
   double sfinal[3];    // final step per axis (= step0 * shrink^(iterations-1))
   double cut_signal;   // > 0: ignore sensors with a signal below it
   double cut_dist;     // > 0: ignore sensors farther (x-y) than it from the start
-  double fb_thr;       // > 0: events with chi2/ndf above it go to the fallback list
+  double fb_thr;       // >= 0: events with chi2/ndf above it go to the fallback list
   int or_status;       // status bits OR-ed into every processed event
 };
 
@@ -106,7 +106,7 @@ struct IoP {
   int64_t n;           // events (work items when list == NULL)
   const int32_t* list;     // optional: event indices to process
   const int32_t* list_n;   // optional: device count of list entries
-  int32_t* fb_list;        // fallback list (when G.fb_thr > 0)
+  int32_t* fb_list;        // fallback list (when G.fb_thr >= 0)
   int32_t* fb_count;       // its device counter
 };
 

@@ -105,6 +105,7 @@ hipError_t launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t 
 ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
   GridP& G = *Gp;
   memset(&G, 0, sizeof(G));
+  G.fb_thr = -1.0;   // no fallback list unless the seeded path sets a threshold
   G.nx = cfg->nodes[0];
   G.ny = cfg->nodes[1];
   G.nz = cfg->nodes[2];

@@ -1415,7 +1415,7 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
   if (io.path && Kev < G.K && lane >= Kev && lane < G.K) io.path[e * G.K + lane] = -1;
   status |= G.or_status;
   if (lane == 0) {
-    if (G.fb_thr > 0.0 && !(okS && ndf > 0 && q2 / ndf <= G.fb_thr)) {
+    if (G.fb_thr >= 0.0 && !(okS && ndf > 0 && q2 / ndf <= G.fb_thr)) {
       int slot = atomicAdd(io.fb_count, 1);
       io.fb_list[slot] = (int32_t)e;
     }

@@ -525,7 +525,8 @@ ants_status ants_reconstruct_seeded(ants_lrfset* S, ants_mlp* M, const ants_grid
     return set_error(ANTS_E_ARG, "the refinement grid must start at the seed");
   if (fallback->start == ANTS_START_SEED)
     return set_error(ANTS_E_ARG, "the fallback grid cannot start at the seed");
-  if (!(chi2ndf_max > 0.0)) return set_error(ANTS_E_ARG, "chi2ndf_max must be positive");
+  if (!(chi2ndf_max >= 0.0))
+    return set_error(ANTS_E_ARG, "chi2ndf_max must be >= 0 (0: every event falls back)");
   if (n < 0 || n > ((int64_t)1 << 31) - 1) return set_error(ANTS_E_ARG, "n_events out of range");
   GridP Gr, Gf;
   ants_status st = grid_params(S->d, refine, &Gr);

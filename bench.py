@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--kappa", type=float, default=0.5)
     ap.add_argument("--plain-only", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=24_000,
+    ap.add_argument("--cpu-sample", type=int, default=48_000,
                     help="events for the oracle CPU baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=160207247)
     ap.add_argument("--copy-probe", action="store_true",

@@ -145,7 +145,7 @@ struct MultiP {
   int n_chunks;
   int n_items;
   int T;                   // events per work item
-  int* counter;            // work counter (zeroed before the launch)
+  int* counter;            // 8 work counters, 16 ints apart (zeroed before the launch)
   IoP out;                 // output arrays (offset per chunk)
   int per_wave_bytes;
   int btab_n;

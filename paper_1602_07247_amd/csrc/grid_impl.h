@@ -1572,11 +1572,28 @@ __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>()))) cg_multi_kernel(M
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   unsigned char* wbase = (unsigned char*)(smem4 + P.btab_n) + (size_t)wv * P.per_wave_bytes;
   int cur_set = -1;
+  // XCD-aware claims (the grid is a multiple of 8 blocks; block b runs on
+  // XCD b % 8, each with its own L2): runs of G items covering 32 output
+  // rows belong to one XCD, claimed through that XCD's counter; a wave whose
+  // XCD has none left takes the other XCDs' items in turn
+  const int G = P.T >= 32 ? 1 : 32 / P.T;
+  const int x0 = blockIdx.x & 7;
+  int xs = 0;
   for (;;) {
-    int item = 0;
-    if (lane0 == 0) item = atomicAdd(P.counter, 1);
-    item = lane_val(item, 0);
-    if (item >= P.n_items) break;
+    int item = -1;
+    while (xs < 8) {
+      const int x = (x0 + xs) & 7;
+      int k = 0;
+      if (lane0 == 0) k = atomicAdd(P.counter + 16 * x, 1);
+      k = lane_val(k, 0);
+      const int64_t i = ((int64_t)(k / G) * 8 + x) * G + (k % G);
+      if (i < P.n_items) {
+        item = (int)i;
+        break;
+      }
+      ++xs;
+    }
+    if (item < 0) break;
     int lo = 0, hi = P.n_chunks;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;

@@ -107,7 +107,7 @@ ants_status run(ants_lrfset* owner, const Prepared& P, const ants_plan& plan, an
   const size_t b_sets = P.sets.size() * sizeof(SetDesc);
   const size_t b_ch = ch.size() * sizeof(ChunkDesc);
   const size_t b_pre = prefix.size() * sizeof(int32_t);
-  const size_t o1 = 256, o2 = o1 + ((b_sets + 255) & ~(size_t)255),
+  const size_t o1 = 512, o2 = o1 + ((b_sets + 255) & ~(size_t)255),
                o3 = o2 + ((b_ch + 255) & ~(size_t)255), total = o3 + b_pre;
   std::vector<unsigned char> host(total, 0);
   memcpy(host.data() + o1, P.sets.data(), b_sets);
@@ -129,7 +129,7 @@ ants_status run(ants_lrfset* owner, const Prepared& P, const ants_plan& plan, an
   M.n_chunks = (int)ch.size();
   M.n_items = prefix.back();
   M.T = plan.events_per_item;
-  M.counter = (int*)dbase;   // first 256 bytes: work counter
+  M.counter = (int*)dbase;   // first 512 bytes: one work counter per XCD, 64 bytes apart
   M.out.x = out.x;
   M.out.y = out.y;
   M.out.z = out.z;
@@ -141,7 +141,7 @@ ants_status run(ants_lrfset* owner, const Prepared& P, const ants_plan& plan, an
   M.per_wave_bytes = P.per_wave;
   M.btab_n = plan.table_in_lds ? P.btab_n : 0;
   M.tab_in_lds = plan.table_in_lds;
-  e = launch_fill_i32(M.counter, 0, 1, s);
+  e = launch_fill_i32(M.counter, 0, 128, s);
   int blocks = num_cu() * plan.blocks_per_cu;
   int64_t need = ((int64_t)M.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > need) blocks = (int)(need > 0 ? need : 1);

@@ -298,6 +298,15 @@ o_node o_node_eval(const o_lrf* L, const o_cfg* C, const double* n, double N,
   return r;
 }
 
+/* Tie tolerance (reading; the paper is silent on ties).  Two node
+ * statistics count as equal when they differ by at most O_TIE_REL times the
+ * event's summed signal N (for either statistic).  That is far above the
+ * rounding of a double-precision evaluation, which depends on the order of
+ * the sums and on the logarithm's implementation, and far below the gaps
+ * that separate distinct nodes, so mathematically equal nodes are ordered by
+ * index and every other decision is unchanged. */
+#define O_TIE_REL 1e-12
+
 /* Node coordinates on the grid of one iteration (Sec. 5.1.2.2: a regular
  * grid centred at the current centre).  Node index (jz*ny + jy)*nx + jx. */
 static void o_node_pos(const o_cfg* C, const double c[3], const double s[3], int j, double p[3]) {
@@ -414,29 +423,42 @@ void o_event(const o_lrf* L, const o_cfg* C, const double* n, const double* seed
     K = k + 1;
     for (int a = 0; a < 3; ++a) s[a] = sf[a];
   }
+  double* st = (double*)malloc(sizeof(double) * (size_t)nn);
   for (int k = 0; k < K; ++k) {
     double b1 = INFINITY, b2 = INFINITY;
-    int j1 = -1;
     for (int j = 0; j < nn; ++j) {
       double p[3];
       o_node_pos(C, c, s, j, p);
-      o_node r = o_node_eval(L, C, n, N, p[0], p[1], p[2]);
-      /* lexicographic minimum of (statistic, node index) */
-      if (r.stat < b1) { b2 = b1; b1 = r.stat; j1 = j; }
-      else if (r.stat < b2) { b2 = r.stat; }
+      st[j] = o_node_eval(L, C, n, N, p[0], p[1], p[2]).stat;
+      if (st[j] < b1) { b2 = b1; b1 = st[j]; }
+      else if (st[j] < b2) { b2 = st[j]; }
+    }
+    /* The best node: the lowest index among the nodes whose statistic is
+     * within the tie tolerance of the minimum (reading: the paper does not
+     * order equally good nodes; values that differ only by rounding are
+     * equal, and equal nodes go to the lowest index, x fastest). */
+    int j1 = -1, nties = 0;
+    if (b1 < INFINITY) {
+      double tol = O_TIE_REL * N;
+      for (int j = 0; j < nn; ++j)
+        if (st[j] <= b1 + tol) {
+          if (j1 < 0) j1 = j;
+          ++nties;
+        }
     }
     if (path) path[k] = j1;
     if (gaps) gaps[k] = b2 - b1;
     if (j1 < 0) {            /* every node invalid: keep the centre */
       *status |= O_NO_VALID_NODE;
     } else {
-      if (b1 == b2) *status |= O_TIE;   /* exact tie, resolved by index */
+      if (nties > 1) *status |= O_TIE;   /* a tie, resolved by index */
       double p[3];
       o_node_pos(C, c, s, j1, p);
       c[0] = p[0]; c[1] = p[1]; c[2] = p[2];
     }
     s[0] *= C->shrink; s[1] *= C->shrink; s[2] *= C->shrink;
   }
+  free(st);
   o_node r = o_node_eval(L, C, n, N, c[0], c[1], c[2]);
   out[0] = c[0]; out[1] = c[1]; out[2] = c[2];
   out[3] = r.A; out[4] = r.lnl; out[5] = r.chi2;

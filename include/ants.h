@@ -93,6 +93,28 @@ ants_status ants_lrfset_destroy(ants_lrfset* set);   /* NULL is a no-op */
 ants_status ants_lrfset_info(const ants_lrfset* set, int32_t* n_sensors, int32_t* n_active,
                              int32_t* kind);
 
+/* LRF-set file (Sec. 6: LRFs are stored and reloaded with the detector
+ * configuration; here one binary file per set, version 1, little endian):
+ *   char[8]  magic "ANTSLRF1"
+ *   int32    n_sensors, kind, shared, n_knots[0], n_knots[1] (0 for AXIAL),
+ *            reserved (0)
+ *   double   lo[2], hi[2]          (axis 1 = 0 for AXIAL)
+ *   int64    n_coef = (n_knots[0]+2) * (n_knots[1]+2 or 1) * (1 or n_sensors)
+ *   double   sensor_xy[n_sensors][2], gain[n_sensors]
+ *   uint8    active[n_sensors], zero padding to a multiple of 8 bytes
+ *   double   coef[n_coef]          (layout of ants_lrf_desc.coef)
+ *   uint64   FNV-1a (64-bit) hash of every preceding byte.
+ * ants_lrf_write writes a descriptor (NULL gain/active are written as 1);
+ * ants_lrfset_save writes what a set was created from (all sensors, passive
+ * ones included).  Errors: ANTS_E_ARG (NULL, sizes, unwritable path).
+ * ants_lrfset_load reads a file and creates the set on the current device:
+ * ANTS_E_ARG when the file cannot be opened, ANTS_E_FORMAT for a foreign,
+ * truncated, extended or corrupted file (magic, header ranges, size,
+ * checksum) and every error of ants_lrfset_create; *out is NULL on error. */
+ants_status ants_lrf_write(const ants_lrf_desc* desc, const char* path);
+ants_status ants_lrfset_save(const ants_lrfset* set, const char* path);
+ants_status ants_lrfset_load(const char* path, ants_lrfset** out);
+
 /* ------------------------------------------------------------------ */
 /* Contracting-grid search (Sec. 5.1.2.2).  Per event:                  */
 /*  - start at the gain-weighted centroid (Sec. 5.1.1), the strongest    */

@@ -102,6 +102,9 @@ _lib.ants_lrfset_destroy.argtypes = [_vp]
 _lib.ants_lrfset_info.argtypes = [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]
 _lib.ants_reconstruct.argtypes = [_vp, C.POINTER(GridCfg), C.c_int64, _vp, _vp, Out, _vp]
+_lib.ants_lrf_write.argtypes = [C.POINTER(LrfDesc), C.c_char_p]
+_lib.ants_lrfset_save.argtypes = [_vp, C.c_char_p]
+_lib.ants_lrfset_load.argtypes = [C.c_char_p, C.POINTER(_vp)]
 
 _lib.ants_generate.argtypes = [_vp, C.POINTER(GenCfg), C.c_int64, C.c_uint64, C.c_uint64, _vp,
                                _vp, _vp]
@@ -135,7 +138,8 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_mlp_destroy", "ants_mlp_num_params", "ants_mlp_get_params",
             "ants_mlp_set_params", "ants_mlp_forward", "ants_mlp_grad", "ants_mlp_train_step",
             "ants_mlp_train", "ants_mlp_save", "ants_mlp_load", "ants_reconstruct_seeded",
-            "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf")
+            "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf",
+            "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load")
 
 
 def _check(code):
@@ -151,31 +155,56 @@ def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-class LrfSet:
-    """Device copy of a detector model.  `model` has the fields kind, sxy,
-    gain, active, shared, nb, lo, hi, coef (see workloads.LRFSet)."""
+def lrf_desc(model):
+    """(LrfDesc, arrays it points into) for a detector model with the fields
+    kind, sxy, gain, active, shared, nb, lo, hi, coef (see workloads.LRFSet)."""
+    sxy = np.ascontiguousarray(model.sxy, np.float64)
+    gain = np.ascontiguousarray(model.gain, np.float64)
+    active = np.ascontiguousarray(model.active, np.uint8)
+    coef = np.ascontiguousarray(model.coef, np.float64)
+    d = LrfDesc()
+    d.n_sensors = sxy.shape[0]
+    d.sensor_xy = _dptr(sxy)
+    d.gain = _dptr(gain)
+    d.active = active.ctypes.data_as(C.POINTER(C.c_uint8))
+    d.kind = int(model.kind)
+    d.shared = int(model.shared)
+    d.n_knots[0], d.n_knots[1] = int(model.nb[0]), int(model.nb[1])
+    d.lo[0], d.lo[1] = float(model.lo[0]), float(model.lo[1])
+    d.hi[0], d.hi[1] = float(model.hi[0]), float(model.hi[1])
+    d.coef = _dptr(coef)
+    return d, (sxy, gain, active, coef)
 
-    def __init__(self, model):
+
+def write_lrf(model, path):
+    """Write a detector model as an LRF-set file (ants_lrf_write)."""
+    d, keep = lrf_desc(model)
+    _check(_lib.ants_lrf_write(C.byref(d), os.fsencode(path)))
+
+
+class LrfSet:
+    """Device copy of a detector model (see lrf_desc), or of an LRF-set file
+    with LrfSet.load(path)."""
+
+    def __init__(self, model=None, _handle=None):
         self._h = _vp()
-        sxy = np.ascontiguousarray(model.sxy, np.float64)
-        gain = np.ascontiguousarray(model.gain, np.float64)
-        active = np.ascontiguousarray(model.active, np.uint8)
-        coef = np.ascontiguousarray(model.coef, np.float64)
-        d = LrfDesc()
-        d.n_sensors = sxy.shape[0]
-        d.sensor_xy = _dptr(sxy)
-        d.gain = _dptr(gain)
-        d.active = active.ctypes.data_as(C.POINTER(C.c_uint8))
-        d.kind = int(model.kind)
-        d.shared = int(model.shared)
-        d.n_knots[0], d.n_knots[1] = int(model.nb[0]), int(model.nb[1])
-        d.lo[0], d.lo[1] = float(model.lo[0]), float(model.lo[1])
-        d.hi[0], d.hi[1] = float(model.hi[0]), float(model.hi[1])
-        d.coef = _dptr(coef)
-        _check(_lib.ants_lrfset_create(C.byref(d), C.byref(self._h)))
+        if _handle is not None:
+            self._h = _handle
+        else:
+            d, keep = lrf_desc(model)
+            _check(_lib.ants_lrfset_create(C.byref(d), C.byref(self._h)))
         ns, na, kind = C.c_int32(), C.c_int32(), C.c_int32()
         _check(_lib.ants_lrfset_info(self._h, C.byref(ns), C.byref(na), C.byref(kind)))
         self.n_sensors, self.n_active, self.kind = ns.value, na.value, kind.value
+
+    @classmethod
+    def load(cls, path):
+        h = _vp()
+        _check(_lib.ants_lrfset_load(os.fsencode(path), C.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path):
+        _check(_lib.ants_lrfset_save(self._h, os.fsencode(path)))
 
     @property
     def handle(self):

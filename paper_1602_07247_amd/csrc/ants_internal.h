@@ -33,9 +33,21 @@ __host__ __device__ constexpr int node_tiles(int nn) {
 // each iteration count a seed may select; for the column-factored r-z
 // screen (fact_nxy = nodes per z-plane, 0 = not used) the partial sums of
 // every (column, sensor group) and a lane -> (column, group) table.
+// Where a wave keeps the FP64 values of its decision candidates (8 bytes
+// for each of up to 64 * nt nodes): over the FP32 sensor records (32 bytes
+// per sensor) or over the factored screen's partial sums, both dead while
+// the candidates are decided; otherwise in a region of its own.
+// 0 = own region, 1 = sensor records, 2 = factored-screen sums.
+__host__ __device__ inline int cval_place(int na, int nz, int nt, int fact_nxy) {
+  const int need = 512 * nt;
+  if (32 * na >= need) return 1;
+  if (fact_nxy > 0 && 8 * nz * (fact_nxy > 64 ? fact_nxy : 64) >= need) return 2;
+  return 0;
+}
 inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt,
                           int fact_nxy = 0) {
   int b = 64 * na + 256 * nt + 24 * kMaxSeedSteps;
+  if (cval_place(na, nz, nt, fact_nxy) == 0) b += 512 * nt;
   if (fact_nxy > 0) b += 8 * nz * (fact_nxy > 64 ? fact_nxy : 64) + 128;
   if (kind == ANTS_LRF_RZ) {
     const int zt = 16 * nz * nintp, zr = 8 * nz * nc0;
@@ -235,6 +247,11 @@ struct ants_lrfset {
   int device;
   int ns;
   std::vector<void*> allocs;
+  // host copy of the descriptor (ants_lrfset_save)
+  int32_t h_kind = 0, h_shared = 0, h_knots[2] = {0, 0};
+  double h_lo[2] = {0, 0}, h_hi[2] = {0, 0};
+  std::vector<double> h_xy, h_gain, h_coef;
+  std::vector<uint8_t> h_active;
   // workspace of the seeded reconstruction (seeds, fallback list, counter)
   void* ws_seeds = nullptr;
   size_t ws_seeds_bytes = 0;

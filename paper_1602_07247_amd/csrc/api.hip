@@ -41,6 +41,74 @@ hipError_t upload(T** dst, const T* src, size_t n) {
 
 int g_num_cu = 0;
 
+// ---- LRF-set file (see ants_lrf_write in ants.h)
+constexpr char kLrfMagic[8] = {'A', 'N', 'T', 'S', 'L', 'R', 'F', '1'};
+constexpr size_t kLrfHeader = 8 + 6 * 4 + 4 * 8 + 8;   // magic, ints, domain, n_coef
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+size_t coef_count(int kind, int shared, int ns, int nb0, int nb1) {
+  const size_t nc0 = (size_t)nb0 + 2, nc1 = kind == ANTS_LRF_AXIAL ? 1 : (size_t)nb1 + 2;
+  return nc0 * nc1 * (shared ? 1 : (size_t)ns);
+}
+
+size_t pad8(size_t n) { return (n + 7) & ~(size_t)7; }
+
+// file size for a header's counts (0 when they are out of range)
+size_t lrf_file_bytes(int ns, size_t ncoef) {
+  return kLrfHeader + 8 * 3 * (size_t)ns + pad8((size_t)ns) + 8 * ncoef + 8;
+}
+
+template <class T>
+void put(std::vector<unsigned char>& b, const T& v) {
+  const unsigned char* p = (const unsigned char*)&v;
+  b.insert(b.end(), p, p + sizeof(T));
+}
+template <class T>
+T get(const unsigned char*& p) {
+  T v;
+  memcpy(&v, p, sizeof(T));
+  p += sizeof(T);
+  return v;
+}
+
+ants_status write_lrf_file(const char* path, int ns, int kind, int shared, const int32_t nk[2],
+                           const double lo[2], const double hi[2], const double* xy,
+                           const double* gain, const uint8_t* active, const double* coef,
+                           size_t ncoef) {
+  std::vector<unsigned char> b;
+  b.reserve(lrf_file_bytes(ns, ncoef));
+  b.insert(b.end(), kLrfMagic, kLrfMagic + 8);
+  put<int32_t>(b, ns);
+  put<int32_t>(b, kind);
+  put<int32_t>(b, shared);
+  put<int32_t>(b, nk[0]);
+  put<int32_t>(b, nk[1]);
+  put<int32_t>(b, 0);
+  for (int a = 0; a < 2; ++a) put<double>(b, lo[a]);
+  for (int a = 0; a < 2; ++a) put<double>(b, hi[a]);
+  put<int64_t>(b, (int64_t)ncoef);
+  for (int i = 0; i < 2 * ns; ++i) put<double>(b, xy[i]);
+  for (int i = 0; i < ns; ++i) put<double>(b, gain ? gain[i] : 1.0);
+  for (int i = 0; i < ns; ++i) b.push_back(active ? (active[i] ? 1 : 0) : 1);
+  while (b.size() % 8) b.push_back(0);
+  for (size_t i = 0; i < ncoef; ++i) put<double>(b, coef[i]);
+  put<uint64_t>(b, fnv1a(b.data(), b.size()));
+  FILE* f = fopen(path, "wb");
+  if (!f) return ants::set_error(ANTS_E_ARG, "cannot open %s for writing", path);
+  const bool ok = fwrite(b.data(), 1, b.size(), f) == b.size();
+  const bool closed = fclose(f) == 0;
+  if (!ok || !closed) return ants::set_error(ANTS_E_ARG, "writing %s failed", path);
+  return ANTS_OK;
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -366,6 +434,22 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
     ants_lrfset_destroy(S);
     return hip_fail(e, "ants_lrfset_create upload");
   }
+  S->h_kind = kind;
+  S->h_shared = D->shared ? 1 : 0;
+  S->h_knots[0] = D->n_knots[0];
+  S->h_knots[1] = kind == ANTS_LRF_AXIAL ? 0 : D->n_knots[1];
+  for (int a = 0; a < 2; ++a) {
+    S->h_lo[a] = a < naxes ? D->lo[a] : 0.0;
+    S->h_hi[a] = a < naxes ? D->hi[a] : 0.0;
+  }
+  S->h_xy.assign(D->sensor_xy, D->sensor_xy + 2 * ns);
+  S->h_gain.resize(ns);
+  S->h_active.resize(ns);
+  for (int i = 0; i < ns; ++i) {
+    S->h_gain[i] = D->gain ? D->gain[i] : 1.0;
+    S->h_active[i] = (!D->active || D->active[i]) ? 1 : 0;
+  }
+  S->h_coef.assign(D->coef, D->coef + per * ntab);
   d.col = dcol;
   d.tab = dtab;
   d.X = dX;
@@ -376,6 +460,106 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
   d.c64 = dc64;
   *out = S;
   return ANTS_OK;
+}
+
+ants_status ants_lrf_write(const ants_lrf_desc* D, const char* path) {
+  if (!D || !path) return fail(ANTS_E_ARG, "ants_lrf_write: NULL descriptor or path");
+  const int ns = D->n_sensors;
+  if (ns < 1 || ns > kMaxSensors)
+    return fail(ANTS_E_ARG, "n_sensors = %d outside 1..%d", ns, kMaxSensors);
+  if (!D->sensor_xy || !D->coef) return fail(ANTS_E_ARG, "sensor_xy and coef are required");
+  if (D->kind != ANTS_LRF_AXIAL && D->kind != ANTS_LRF_XY && D->kind != ANTS_LRF_RZ)
+    return fail(ANTS_E_ARG, "unknown LRF kind %d", D->kind);
+  const int nb1 = D->kind == ANTS_LRF_AXIAL ? 0 : D->n_knots[1];
+  if (D->n_knots[0] < 2 || D->n_knots[0] > 256 ||
+      (D->kind != ANTS_LRF_AXIAL && (nb1 < 2 || nb1 > 256)))
+    return fail(ANTS_E_ARG, "n_knots (%d, %d) outside 2..256", D->n_knots[0], D->n_knots[1]);
+  const int32_t nk[2] = {D->n_knots[0], nb1};
+  const double lo[2] = {D->lo[0], D->kind == ANTS_LRF_AXIAL ? 0.0 : D->lo[1]};
+  const double hi[2] = {D->hi[0], D->kind == ANTS_LRF_AXIAL ? 0.0 : D->hi[1]};
+  return write_lrf_file(path, ns, D->kind, D->shared ? 1 : 0, nk, lo, hi, D->sensor_xy, D->gain,
+                        D->active, D->coef,
+                        coef_count(D->kind, D->shared, ns, D->n_knots[0], nb1));
+}
+
+ants_status ants_lrfset_save(const ants_lrfset* S, const char* path) {
+  if (!S || !path) return fail(ANTS_E_ARG, "ants_lrfset_save: NULL set or path");
+  return write_lrf_file(path, S->ns, S->h_kind, S->h_shared, S->h_knots, S->h_lo, S->h_hi,
+                        S->h_xy.data(), S->h_gain.data(), S->h_active.data(), S->h_coef.data(),
+                        S->h_coef.size());
+}
+
+ants_status ants_lrfset_load(const char* path, ants_lrfset** out) {
+  if (!out) return fail(ANTS_E_ARG, "ants_lrfset_load: NULL out");
+  *out = nullptr;
+  if (!path) return fail(ANTS_E_ARG, "ants_lrfset_load: NULL path");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(ANTS_E_ARG, "cannot open %s", path);
+  std::vector<unsigned char> b;
+  unsigned char buf[65536];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0) {
+    b.insert(b.end(), buf, buf + got);
+    if (b.size() > ((size_t)1 << 30)) break;
+  }
+  fclose(f);
+  if (b.size() < kLrfHeader + 8) return fail(ANTS_E_FORMAT, "%s is truncated", path);
+  if (memcmp(b.data(), kLrfMagic, 8) != 0)
+    return fail(ANTS_E_FORMAT, "%s is not an LRF-set file (magic)", path);
+  const unsigned char* p = b.data() + 8;
+  const int32_t ns = get<int32_t>(p), kind = get<int32_t>(p), shared = get<int32_t>(p);
+  int32_t nk[2];
+  nk[0] = get<int32_t>(p);
+  nk[1] = get<int32_t>(p);
+  (void)get<int32_t>(p);
+  double lo[2], hi[2];
+  for (int a = 0; a < 2; ++a) lo[a] = get<double>(p);
+  for (int a = 0; a < 2; ++a) hi[a] = get<double>(p);
+  const int64_t ncoef = get<int64_t>(p);
+  if (ns < 1 || ns > kMaxSensors || (kind != ANTS_LRF_AXIAL && kind != ANTS_LRF_XY &&
+                                     kind != ANTS_LRF_RZ) ||
+      (shared != 0 && shared != 1) || nk[0] < 2 || nk[0] > 256 ||
+      (kind != ANTS_LRF_AXIAL && (nk[1] < 2 || nk[1] > 256)))
+    return fail(ANTS_E_FORMAT, "%s: header out of range", path);
+  if (ncoef != (int64_t)coef_count(kind, shared, ns, nk[0], nk[1]))
+    return fail(ANTS_E_FORMAT, "%s: coefficient count %lld does not match the header", path,
+                (long long)ncoef);
+  if (b.size() != lrf_file_bytes(ns, (size_t)ncoef))
+    return fail(ANTS_E_FORMAT, "%s: %zu bytes, expected %zu (truncated or extended)", path,
+                b.size(), lrf_file_bytes(ns, (size_t)ncoef));
+  uint64_t sum;
+  memcpy(&sum, b.data() + b.size() - 8, 8);
+  if (sum != fnv1a(b.data(), b.size() - 8))
+    return fail(ANTS_E_FORMAT, "%s: checksum mismatch", path);
+  std::vector<double> xy(2 * (size_t)ns), gain(ns), coef((size_t)ncoef);
+  std::vector<uint8_t> active(ns);
+  memcpy(xy.data(), p, 16 * (size_t)ns);
+  p += 16 * (size_t)ns;
+  memcpy(gain.data(), p, 8 * (size_t)ns);
+  p += 8 * (size_t)ns;
+  memcpy(active.data(), p, (size_t)ns);
+  p += pad8((size_t)ns);
+  memcpy(coef.data(), p, 8 * (size_t)ncoef);
+  ants_lrf_desc D;
+  memset(&D, 0, sizeof(D));
+  D.n_sensors = ns;
+  D.sensor_xy = xy.data();
+  D.gain = gain.data();
+  D.active = active.data();
+  D.kind = kind;
+  D.shared = shared;
+  D.n_knots[0] = nk[0];
+  D.n_knots[1] = kind == ANTS_LRF_AXIAL ? 1 : nk[1];
+  for (int a = 0; a < 2; ++a) {
+    D.lo[a] = lo[a];
+    D.hi[a] = hi[a];
+  }
+  if (kind == ANTS_LRF_AXIAL) {
+    D.lo[1] = 0.0;
+    D.hi[1] = 1.0;
+  }
+  D.coef = coef.data();
+  return ants_lrfset_create(&D, out);
 }
 
 ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t n_events,

@@ -28,8 +28,8 @@
 // node; every node whose screened value lies within (a multiple of) the
 // bound of the best is re-evaluated in FP64 (the vector FP64 rate equals
 // the unpacked FP32 rate on this chip), in lane groups sized by a cost
-// model, and the FP64 values decide.  Ties in FP64 go to the lowest node
-// index.
+// model, and the FP64 values decide.  FP64 values within 1e-12 N of the
+// best are ties, which go to the lowest node index.
 #pragma once
 
 #include <math.h>
@@ -43,6 +43,10 @@ namespace {
 constexpr float kU = 5.9604645e-8f;  // unit roundoff of FP32
 constexpr float kInf = __builtin_huge_valf();
 constexpr float kLog2e = 1.4426950408889634f;
+// Tie tolerance of the FP64 decisions, relative to the event's summed
+// signal N: node statistics closer than this are equal, and the lowest node
+// index wins (far above double rounding, far below real gaps between nodes).
+constexpr double kTieRel = 1e-12;
 
 // ------------------------------------------------------------ wave helpers
 
@@ -285,6 +289,8 @@ struct WaveLds {
   uint16_t* cand;      // candidate list
   uint16_t* nodeidx;   // packed node indices
   double* sstep;       // seeded refinement: steps per axis after k quotients
+  double* cval;        // FP64 statistic of each candidate (candidate order),
+                       // overlaying storage that is dead during the decisions
   float* fscr;         // factored r-z screen: partial sums [group][column][plane][2]
   uint16_t* lanecg;    // factored r-z screen: column | group << 8 per lane
 };
@@ -307,8 +313,12 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& 
   w.pw32 = w.ztab + zq;
   w.pw64 = (double*)(w.pw32 + nzp);
   w.sstep = w.pw64 + 4 * nzp;
-  w.fscr = (float*)(w.sstep + 3 * kMaxSeedSteps);
   const int nxy = G.nx * G.ny;
+  const int cplace = cval_place(L.na, G.nz, NT, FA ? nxy : 0);
+  w.fscr = (float*)(w.sstep + 3 * kMaxSeedSteps + (cplace == 0 ? 64 * NT : 0));
+  w.cval = cplace == 1   ? (double*)w.recA
+           : cplace == 2 ? (double*)w.fscr
+                         : w.sstep + 3 * kMaxSeedSteps;
   w.pm = (int*)(w.fscr + (FA ? 2 * G.nz * (nxy > 64 ? nxy : 64) : 0));
   w.cand = (uint16_t*)(w.pm + nzp);
   w.nodeidx = w.cand + 64 * NT;
@@ -1277,58 +1287,41 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
       win = jb;
     } else if (ncand > 0) {
       make_rows();
-      // FP64 values of the candidates: groups of gs lanes per candidate,
-      // each lane over every gs-th sensor; gs from a cost model (sensor
-      // terms : group reduction steps : per-candidate work = 9 : 1 : 6)
-      int gs = 64, best_cost = 1 << 30;
-      for (int g = 1; g <= 64; g <<= 1) {
-        const int per_pass = 64 / g;
-        const int cost = ((ncand + per_pass - 1) / per_pass) *
-                         (((na + g - 1) / g) * 9 + (31 - __builtin_clz(g)) + 6);
-        if (cost < best_cost) {
-          best_cost = cost;
-          gs = g;
-        }
-      }
-      const int lgs = uni(31 - __builtin_clz(gs));
-      const int sub = lane & ((1 << lgs) - 1);
-      const int per_pass = 64 >> lgs;
-      double bestd = __builtin_huge_val();
-      int jd = 1 << 30;
-      for (int base = 0; base < ncand; base += per_pass) {
-        const int c = base + (lane >> lgs);
-        const int j = c < ncand ? (int)cand[c] : (1 << 30);
-        double xx = 0.0, yy = 0.0, zz = 0.0;
-        bool ok = false;
-        const double* zrow = zc64;
-        if (c < ncand) {
-          NodeF<KIND> ndd;
-          ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx, yy, zz);
-          if constexpr (KIND == ANTS_LRF_RZ) zrow = zc64 + (nodeidx[j] >> G.shz) * L.nc0;
-        }
-        double S = 0.0, T = 0.0;
-        if (ok) {
-          for (int p = sub; p < na; p += 1 << lgs) {
-            const SensorRec64 r = rec64[p];
-            const float n = r.n;
-            if (n < 0.f) continue;   // ignored by the sensor cuts
-            double Lv;
-            if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
-            else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
-            S += r.g * Lv;
-            if (STAT == ANTS_STAT_ML && n > 0.f)
-              T += (double)n * log(Lv > G.lfloor ? Lv : G.lfloor);
+      // one round over the candidates; after a tie, a second round over
+      // every valid node (the screen's error bound holds at the best screened
+      // node, so a tied node farther out may have screened outside it)
+      for (int round = 0; round < 2; ++round) {
+        // FP64 values of the candidates: groups of gs lanes per candidate,
+        // each lane over every gs-th sensor; gs from a cost model (sensor
+        // terms : group reduction steps : per-candidate work = 9 : 1 : 6)
+        int gs = 64, best_cost = 1 << 30;
+        for (int g = 1; g <= 64; g <<= 1) {
+          const int per_pass = 64 / g;
+          const int cost = ((ncand + per_pass - 1) / per_pass) *
+                           (((na + g - 1) / g) * 9 + (31 - __builtin_clz(g)) + 6);
+          if (cost < best_cost) {
+            best_cost = cost;
+            gs = g;
           }
         }
-        S = gsum(S, lgs, lane);
-        double Dv = __builtin_huge_val();
-        if constexpr (STAT == ANTS_STAT_ML) {
-          T = gsum(T, lgs, lane);
-          if (ok && S > 0.0) Dv = N * log(S) - T;
-        } else {
-          double Q = 0.0;
-          if (ok && S > 0.0) {
-            const double Aa = N / S;
+        const int lgs = uni(31 - __builtin_clz(gs));
+        const int sub = lane & ((1 << lgs) - 1);
+        const int per_pass = 64 >> lgs;
+        double bestd = __builtin_huge_val();
+        double* cval = W.cval;
+        for (int base = 0; base < ncand; base += per_pass) {
+          const int c = base + (lane >> lgs);
+          const int j = c < ncand ? (int)cand[c] : (1 << 30);
+          double xx = 0.0, yy = 0.0, zz = 0.0;
+          bool ok = false;
+          const double* zrow = zc64;
+          if (c < ncand) {
+            NodeF<KIND> ndd;
+            ok = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, ndd, xx, yy, zz);
+            if constexpr (KIND == ANTS_LRF_RZ) zrow = zc64 + (nodeidx[j] >> G.shz) * L.nc0;
+          }
+          double S = 0.0, T = 0.0;
+          if (ok) {
             for (int p = sub; p < na; p += 1 << lgs) {
               const SensorRec64 r = rec64[p];
               const float n = r.n;
@@ -1336,32 +1329,76 @@ __device__ __forceinline__ void process_event(const DevLrf& L, const GridP& G, c
               double Lv;
               if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
               else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
-              const double mu = Aa * r.g * Lv;
-              const double dd = (double)n - mu;
-              Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+              S += r.g * Lv;
+              if (STAT == ANTS_STAT_ML && n > 0.f)
+                T += (double)n * log(Lv > G.lfloor ? Lv : G.lfloor);
             }
           }
-          Q = gsum(Q, lgs, lane);
-          if (ok && S > 0.0) Dv = Q;
+          S = gsum(S, lgs, lane);
+          double Dv = __builtin_huge_val();
+          if constexpr (STAT == ANTS_STAT_ML) {
+            T = gsum(T, lgs, lane);
+            if (ok && S > 0.0) Dv = N * log(S) - T;
+          } else {
+            double Q = 0.0;
+            if (ok && S > 0.0) {
+              const double Aa = N / S;
+              for (int p = sub; p < na; p += 1 << lgs) {
+                const SensorRec64 r = rec64[p];
+                const float n = r.n;
+                if (n < 0.f) continue;   // ignored by the sensor cuts
+                double Lv;
+                if constexpr (KIND == ANTS_LRF_RZ) Lv = lrf64_plane(L, r.X, r.Y, xx, yy, zrow);
+                else Lv = lrf64s<KIND>(L, r.X, r.Y, r.coff, xx, yy, zz);
+                const double mu = Aa * r.g * Lv;
+                const double dd = (double)n - mu;
+                Q += dd * dd / (mu > G.vfloor ? mu : G.vfloor);
+              }
+            }
+            Q = gsum(Q, lgs, lane);
+            if (ok && S > 0.0) Dv = Q;
+          }
+          if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
+          if (sub == 0 && c < ncand) cval[c] = Dv;
+          double v1 = Dv;
+          int j1 = j;
+          wargmin_d(v1, j1);
+          bestd = v1 < bestd ? v1 : bestd;
         }
-        if (!(Dv < __builtin_huge_val())) Dv = __builtin_huge_val();
-        double v1 = Dv;
-        int j1 = j;
-        wargmin_d(v1, j1);
-        const bool fin = v1 < __builtin_huge_val();
-        // candidates are listed in increasing node index, so an earlier
-        // pass's winner keeps priority on equal values
-        const int nsame = __popcll(__ballot(fin && Dv == v1 && sub == 0));
-        if (v1 < bestd) {
-          bestd = v1;
-          jd = j1;
-          tie = nsame > 1;
-        } else if (fin && v1 == bestd) {
-          tie = true;
+        nfp += ncand;
+        wave_sync_lds();
+        // values within kTieRel * N of the minimum are equal (their
+        // differences are rounding of sums taken in different orders); the
+        // lowest node index among them wins.  Candidates are listed in
+        // increasing node index, so the first one in the window is the winner.
+        if (bestd < __builtin_huge_val()) {
+          const double lim = uni(bestd + kTieRel * N);
+          int first = -1, nwin = 0;
+          for (int c0 = 0; c0 < ncand; c0 += 64) {
+            const int c = c0 + lane;
+            const uint64_t m = __ballot(c < ncand && cval[c] <= lim);
+            if (first < 0 && m) first = c0 + __builtin_ctzll(m);
+            nwin += __popcll(m);
+          }
+          win = uni((int)cand[uni(first)]);
+          tie = nwin > 1;
         }
+        if (round == 0 && tie) {
+          int nall = 0;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const uint64_t m = __ballot(valid[t]);
+            if (valid[t]) cand[nall + prefix_count(m)] = (uint16_t)(t * 64 + lane);
+            nall += __popcll(m);
+          }
+          wave_sync_lds();
+          if (nall > ncand) {
+            ncand = nall;
+            continue;
+          }
+        }
+        break;
       }
-      nfp += ncand;
-      win = uni(bestd < __builtin_huge_val() ? jd : -1);
     }
     if (io.path && lane == 0 && k < G.K) io.path[e * G.K + k] = win;
     if (win < 0) {

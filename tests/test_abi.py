@@ -105,3 +105,86 @@ def test_fit_argument_errors(ants):
                                         None) == ants.E_ARG
     assert ants._lib.ants_fit_axial_lrf(None, None, 0, None, 0, out, coef, None,
                                         None) == ants.E_ARG
+
+
+# ------------------------------------------------------------ LRF-set files
+
+
+def _parse_lrf_file(raw):
+    # the layout documented in include/ants.h, read independently here
+    import struct
+    assert raw[:8] == b"ANTSLRF1"
+    ns, kind, shared, nb0, nb1, _ = struct.unpack_from("<6i", raw, 8)
+    lo0, lo1, hi0, hi1 = struct.unpack_from("<4d", raw, 32)
+    (ncoef,) = struct.unpack_from("<q", raw, 64)
+    o = 72
+    xy = np.frombuffer(raw, "<f8", 2 * ns, o).reshape(ns, 2)
+    o += 16 * ns
+    gain = np.frombuffer(raw, "<f8", ns, o)
+    o += 8 * ns
+    active = np.frombuffer(raw, np.uint8, ns, o)
+    o += (ns + 7) // 8 * 8
+    coef = np.frombuffer(raw, "<f8", ncoef, o)
+    o += 8 * ncoef
+    (h,) = struct.unpack_from("<Q", raw, o)
+    fnv = 1469598103934665603
+    for b in raw[:o]:
+        fnv = ((fnv ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    assert h == fnv and o + 8 == len(raw)
+    return dict(ns=ns, kind=kind, shared=shared, nb=(nb0, nb1), lo=(lo0, lo1), hi=(hi0, hi1),
+                xy=xy, gain=gain, active=active, coef=coef)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_lrf_file_layout(ants, k, tmp_path):
+    m = W.workload(k).lrf
+    m.active = np.ones(m.sxy.shape[0], np.uint8)
+    m.active[1] = 0
+    f = tmp_path / "set.lrf"
+    ants.write_lrf(m, str(f))
+    got = _parse_lrf_file(f.read_bytes())
+    assert got["ns"] == m.sxy.shape[0] and got["kind"] == m.kind and got["shared"] == m.shared
+    assert got["nb"][0] == m.nb[0] and got["nb"][1] == (0 if m.kind == 1 else m.nb[1])
+    np.testing.assert_array_equal(got["xy"], m.sxy)
+    np.testing.assert_array_equal(got["gain"], m.gain)
+    np.testing.assert_array_equal(got["active"], m.active)
+    np.testing.assert_array_equal(got["coef"], np.asarray(m.coef).reshape(-1))
+
+
+def _load_code(ants, path):
+    h = C.c_void_p()
+    code = ants._lib.ants_lrfset_load(os.fsencode(str(path)), C.byref(h))
+    assert not h.value or code == ants.OK
+    return code
+
+
+def test_lrf_file_errors(ants, tmp_path):
+    m = W.workload(0).lrf
+    f = tmp_path / "set.lrf"
+    ants.write_lrf(m, str(f))
+    raw = f.read_bytes()
+    bad = tmp_path / "bad.lrf"
+    cases = {
+        "truncated": raw[:-1],
+        "extended": raw + b"\0",
+        "header only": raw[:72],
+        "empty": b"",
+        "foreign": b"ANTSMLP1" + raw[8:],
+        "flipped coefficient": raw[:-20] + bytes([raw[-20] ^ 1]) + raw[-19:],
+    }
+    for name, data in cases.items():
+        bad.write_bytes(data)
+        assert _load_code(ants, bad) == ants.E_FORMAT, name
+        assert ants._lib.ants_last_error(), name
+    # a header out of range, with a valid checksum
+    import struct
+    b = bytearray(raw)
+    struct.pack_into("<i", b, 12, 7)          # kind 7
+    fnv = 1469598103934665603
+    for x in b[:-8]:
+        fnv = ((fnv ^ x) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    struct.pack_into("<Q", b, len(b) - 8, fnv)
+    bad.write_bytes(bytes(b))
+    assert _load_code(ants, bad) == ants.E_FORMAT
+    assert _load_code(ants, tmp_path / "missing.lrf") == ants.E_ARG
+    assert ants._lib.ants_lrf_write(None, b"x") == ants.E_ARG

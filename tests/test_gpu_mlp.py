@@ -67,11 +67,14 @@ def test_forward_matches_reference(ants, det):
     torch.cuda.synchronize()
     got = pred.cpu().numpy()
     ref, _ = R.forward(lay, p, sig, emulate=True)
-    err = np.abs(got - ref)
-    scale = 1 + np.abs(ref)
-    print("forward max rel", (err / scale).max(), "median", np.median(err / scale))
-    assert np.median(err / scale) < 1e-3
-    assert (err / scale).max() < 5e-2
+    err = np.abs(got - ref) / (1 + np.abs(ref))
+    # BF16 storage is emulated at the same places; what remains is FP32 vs
+    # FP64 accumulation, which can flip a stored BF16 rounding (one unit =
+    # 2^-8 relative) and carry it through later layers
+    q = np.quantile(err, [0.5, 0.999, 1.0])
+    print("forward error / (1+|ref|): median %.2e, 99.9%% %.2e, max %.2e" % tuple(q))
+    assert (err <= 4e-3).mean() >= 0.999
+    assert err.max() < 2e-2
 
 
 def test_fused_forward_tails_and_training_path(ants, det):
@@ -127,8 +130,11 @@ def test_network_seeds_equal_explicit_seeds(ants, det, trained):
     torch.cuda.synchronize()
     ga, gb = to_np(a), to_np(b)
     same = (ga["x"] == gb["x"]) & (ga["y"] == gb["y"]) & (ga["z"] == gb["z"])
-    print("identical positions", same.mean(), "fallbacks", na_.item(), nb_.item())
-    assert same.mean() >= 0.998
+    # the kernel's FP32 seed and NumPy's may differ in the last bit, which
+    # moves every node by that much: parity within the 1e-3 mm criterion
+    res = compare(gb, ga, sig[:n], three_d=True)
+    print("identical positions", same.mean(), summary(res), "fallbacks", na_.item(), nb_.item())
+    assert res["frac"] >= 0.999, summary(res)
     assert na_.item() < n // 2          # most events keep the refined seed
 
 
@@ -144,13 +150,18 @@ def test_gradient_matches_reference(ants, det):
     ref_loss, ref_g = R.loss_and_grad(lay, p, sig[:n], truth["pos"][:n], W.SEED_POS_SCALE,
                                       W.SEED_POS_OFFSET, emulate=True)
     assert abs(loss.item() - ref_loss) < 1e-3 * (1 + abs(ref_loss))
+    # element-wise: |g - g_ref| <= atol + rtol |g_ref| on >= 99.9% of every
+    # parameter block, atol = 1e-3 of the block's largest |g_ref|
+    rtol = 2e-2
     for l, (off, do, di) in enumerate(lay.shapes):
         for a, b in ((off, off + do * di), (off + do * di, off + do * di + do)):
             x, y = g[a:b], ref_g[a:b]
-            cos = x @ y / (np.linalg.norm(x) * np.linalg.norm(y) + 1e-30)
-            rel = np.linalg.norm(x - y) / (np.linalg.norm(y) + 1e-30)
-            print(f"layer {l} block [{a}:{b}] cos {cos:.6f} rel {rel:.2e}")
-            assert cos > 0.999 and rel < 0.03
+            atol = 1e-3 * np.abs(y).max()
+            r = np.abs(x - y) / (atol + rtol * np.abs(y))
+            frac = (r <= 1.0).mean()
+            print(f"layer {l} block [{a}:{b}] within {frac:.5f}, 99.9% of ratio "
+                  f"{np.quantile(r, 0.999):.3f}, max {r.max():.3f}")
+            assert frac >= 0.999, (l, a, b, frac)
 
 
 def test_training_reduces_loss_and_seeds_the_grid(ants, det, trained):
@@ -189,6 +200,6 @@ def test_seeded_refinement_matches_oracle(ants, det):
     res = compare(ref, got, sig[:n], three_d=True)
     fb_ref = int(((ref["status"] & 16) != 0).sum())
     print(summary(res), "fallbacks", nfb.item(), fb_ref)
-    assert res["frac"] >= 0.998, summary(res)
+    assert res["frac"] >= 0.999, summary(res)
     assert abs(nfb.item() - fb_ref) <= 2
     assert fb_ref >= 40

@@ -168,30 +168,42 @@ def test_passive_sensors(ants):
     assert (gpu["status"] == 4).all()
 
 
-def test_degenerate_flat_likelihood(ants):
-    # a constant LRF makes every node equally good: lnL, E and chi2 are the
-    # same at every node (unique, compared), while the path is decided by
-    # rounding and is only checked to be a valid path of the grid
+def test_degenerate_ties_follow_lowest_index(ants):
+    # a constant LRF makes every node equally good: the FP64 values differ
+    # only by rounding, within the tie tolerance, so the corner node (index 0)
+    # wins every iteration, as in the oracle, and TIE is set
     sxy = W.hex_array(2, 30.0)
     lrf = W.axial_lrf(sxy)
     lrf.coef = np.ones_like(lrf.coef)
     lrf.hi = (1000.0, 0.0)
-    g = W.GridCfg((9, 9, 1), 4, 0.5, (2.0, 2.0, 0.0), 0.0)
-    sig = np.random.default_rng(9).poisson(40.0, size=(70, 19)).astype(np.float32)
+    for stat in (0, 1):
+        g = W.GridCfg((9, 9, 1), 4, 0.5, (2.0, 2.0, 0.0), 0.0, stat=stat)
+        sig = np.random.default_rng(9).poisson(40.0, size=(70, 19)).astype(np.float32)
+        ref = oracle.reconstruct(lrf, g, sig)
+        gpu = _run(ants, W.Workload(0, "constant-lrf", lrf, g, None, 70), sig, g)
+        assert np.all(ref["path"] == 0) and np.all(ref["status"] & 32)
+        np.testing.assert_array_equal(gpu["path"], ref["path"])
+        np.testing.assert_array_equal(gpu["status"], ref["status"])
+        res = compare(ref, gpu, sig, stat)
+        assert res["ok"].all(), summary(res)
+
+
+@pytest.mark.parametrize("stat", [0, 1])
+def test_single_sensor_ring_of_ties(ants, stat):
+    # one sensor: every node inside the LRF domain ties; the grid reaches
+    # past the domain, so each iteration's winner is the lowest index inside
+    # the disc r <= 150 mm around the sensor (a node on the far side of the
+    # FP32 screen's error bound included)
+    lrf = W.axial_lrf(np.array([[0.0, 0.0]]))
+    g = W.GridCfg((9, 9, 1), 3, 0.5, (32.0, 32.0, 0.0), 0.0, stat=stat)
+    sig = np.random.default_rng(11).poisson(60.0, size=(40, 1)).astype(np.float32) + 1
     ref = oracle.reconstruct(lrf, g, sig)
-    gpu = _run(ants, W.Workload(0, "constant-lrf", lrf, g, None, 70), sig, g)
-    N = sig.astype(np.float64).sum(1)
-    np.testing.assert_allclose(gpu["lnl"], ref["lnl"], rtol=0, atol=1e-5 * N.max())
-    np.testing.assert_allclose(gpu["E"], ref["E"], rtol=1e-6)
-    np.testing.assert_allclose(gpu["chi2"], ref["chi2"], rtol=1e-5, atol=1e-4)
-    start = oracle.reconstruct(lrf, W.GridCfg(**{**g.__dict__, "iterations": 0}), sig)
-    path = gpu["path"]
-    assert ((path >= 0) & (path < 81)).all()
-    steps = 2.0 * 0.5 ** np.arange(4)
-    x = start["x"] + ((path % 9 - 4) * steps).sum(1)
-    y = start["y"] + ((path // 9 - 4) * steps).sum(1)
-    np.testing.assert_allclose(gpu["x"], x, atol=1e-4)
-    np.testing.assert_allclose(gpu["y"], y, atol=1e-4)
+    gpu = _run(ants, W.Workload(0, "one-sensor", lrf, g, None, 40), sig, g)
+    assert np.all(ref["path"][:, 0] == 2) and np.all(ref["status"] & 32)
+    np.testing.assert_array_equal(gpu["path"], ref["path"])
+    np.testing.assert_array_equal(gpu["status"], ref["status"])
+    res = compare(ref, gpu, sig, stat)
+    assert res["ok"].all(), summary(res)
 
 
 def test_full_size_r_z_batch_sampled_against_oracle(ants):
@@ -207,11 +219,11 @@ def test_full_size_r_z_batch_sampled_against_oracle(ants):
     out = ants.reconstruct(L, ants.grid_cfg(wl.grid), d)
     torch.cuda.synchronize()
     rng = np.random.default_rng(0)
-    idx = np.unique(np.concatenate([rng.integers(0, n, 600), [0, n - 1, n // 2]]))
+    idx = np.unique(np.concatenate([rng.integers(0, n, 12_000), [0, n - 1, n // 2]]))
     got = {k: v[torch.from_numpy(idx).cuda()].cpu().numpy() for k, v in out.items()}
     rows = base[idx % len(base)]
     ref = oracle.reconstruct(wl.lrf, wl.grid, rows)
     res = compare(ref, got, rows, three_d=True)
-    assert res["frac"] >= 0.995, summary(res)
+    assert res["frac"] >= 0.999, summary(res)
     del d, out
     torch.cuda.empty_cache()

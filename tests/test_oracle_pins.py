@@ -338,6 +338,21 @@ def test_single_sensor_likelihood_is_flat():
     assert r["lnl"][0] == pytest.approx(57 * math.log(57) - 57, rel=1e-13)
 
 
+def test_single_sensor_ring_of_ties_lowest_valid_index():
+    # one sensor, a grid reaching past the LRF domain (r <= 150 mm): every
+    # node inside the domain ties (A g L = N at each of them), the nodes
+    # outside are invalid, so the winner is the lowest index inside the disc
+    lrf = W.axial_lrf(np.array([[0.0, 0.0]]))
+    for stat in (0, 1):
+        g = W.GridCfg((9, 9, 1), 1, 0.5, (32.0, 32.0, 0.0), 0.0, stat=stat)
+        r = oracle.reconstruct(lrf, g, np.array([[57.0]]))
+        off = (np.arange(81) % 9 - 4) * 32.0, (np.arange(81) // 9 - 4) * 32.0
+        inside = np.hypot(*off) <= 150.0
+        j = int(np.argmax(inside))
+        assert j == 2 and r["path"][0, 0] == j and r["status"][0] & 32
+        assert r["x"][0] == off[0][j] and r["y"][0] == off[1][j]
+
+
 # ---------------------------------------------------------- per-event status
 
 

@@ -358,6 +358,24 @@ ants_status ants_reconstruct_seeded(ants_lrfset* set, ants_mlp* mlp,
                                     const float* d_seeds, ants_out out, int32_t* d_n_fallback,
                                     void* hip_stream);
 
+/* Allocation-free variant of ants_reconstruct_seeded, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving
+ * loops that forbid hipMalloc).  Same arguments, checks, results and status
+ * bits; it calls no hipMalloc/hipFree.  Its workspace (fallback counter,
+ * fallback list, network seeds) is one fixed array per device, 20 MiB for
+ * ANTS_NOALLOC_MAX_EVENTS events, held from the first call on a device until
+ * the process ends.  n_events above ANTS_NOALLOC_MAX_EVENTS gives ANTS_E_ARG
+ * (split the batch).  Every call on a device shares that device's array:
+ * calls that overlap in time on one device race (use one stream, or
+ * serialise them). */
+#define ANTS_NOALLOC_MAX_EVENTS (1 << 20)
+ants_status ants_reconstruct_seeded_noalloc(ants_lrfset* set, ants_mlp* mlp,
+                                            const ants_grid_cfg* refine,
+                                            const ants_grid_cfg* fallback, double chi2ndf_max,
+                                            int64_t n_events, const float* d_signals,
+                                            const float* d_seeds, ants_out out,
+                                            int32_t* d_n_fallback, void* hip_stream);
+
 /* ------------------------------------------------------------------ */
 /* LRF fit from events (Sec. 6: LRFs computed from signals and event    */
 /* positions; Sec. 6.2: one LRF for all sensors with relative gains;    */

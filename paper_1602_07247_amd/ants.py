@@ -123,6 +123,8 @@ _lib.ants_mlp_save.argtypes = [_vp, C.c_char_p]
 _lib.ants_mlp_load.argtypes = [C.c_char_p, C.POINTER(_vp)]
 _lib.ants_reconstruct_seeded.argtypes = [_vp, _vp, C.POINTER(GridCfg), C.POINTER(GridCfg),
                                          C.c_double, C.c_int64, _vp, _vp, Out, _vp, _vp]
+_lib.ants_reconstruct_seeded_noalloc.argtypes = _lib.ants_reconstruct_seeded.argtypes
+NOALLOC_MAX_EVENTS = 1 << 20
 
 _lib.ants_reconstruct_multi.argtypes = [C.POINTER(_vp), C.POINTER(GridCfg), C.c_int32,
                                         C.POINTER(Chunk), C.c_int32, C.POINTER(Plan), Out, _vp]
@@ -138,6 +140,7 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_mlp_destroy", "ants_mlp_num_params", "ants_mlp_get_params",
             "ants_mlp_set_params", "ants_mlp_forward", "ants_mlp_grad", "ants_mlp_train_step",
             "ants_mlp_train", "ants_mlp_save", "ants_mlp_load", "ants_reconstruct_seeded",
+            "ants_reconstruct_seeded_noalloc",
             "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf",
             "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load")
 
@@ -421,23 +424,26 @@ class Mlp:
 
 
 def reconstruct_seeded(lrfset, mlp, refine: GridCfg, fallback: GridCfg, chi2ndf_max, signals,
-                       seeds=None, out=None, stream=None, n_fp64=False):
+                       seeds=None, out=None, stream=None, n_fp64=False, noalloc=False, nfb=None):
     """Seeded reconstruction (network seeds, or explicit seeds [n][4] in mm
     with a log-variance).  Returns (outputs, device tensor with the number of
-    fallback events)."""
+    fallback events).  noalloc=True calls the allocation-free entry point
+    (at most NOALLOC_MAX_EVENTS events; pass `out` and `nfb` to allocate
+    nothing here either)."""
     import torch
     n = signals.shape[0]
     if out is None:
         out = alloc_out(n, refine.iterations, signals.device, False, n_fp64)
-    nfb = torch.zeros(1, dtype=torch.int32, device=signals.device)
+    if nfb is None:
+        nfb = torch.zeros(1, dtype=torch.int32, device=signals.device)
     sp = None
     if seeds is not None:
         assert seeds.shape == (n, 4) and seeds.dtype == torch.float32 and seeds.is_contiguous()
         sp = seeds.data_ptr()
-    _check(_lib.ants_reconstruct_seeded(lrfset.handle, mlp.handle if mlp is not None else None,
-                                        C.byref(refine), C.byref(fallback), float(chi2ndf_max), n,
-                                        signals.data_ptr(), sp, _out_struct(out), nfb.data_ptr(),
-                                        _stream_handle(stream)))
+    fn = _lib.ants_reconstruct_seeded_noalloc if noalloc else _lib.ants_reconstruct_seeded
+    _check(fn(lrfset.handle, mlp.handle if mlp is not None else None, C.byref(refine),
+              C.byref(fallback), float(chi2ndf_max), n, signals.data_ptr(), sp, _out_struct(out),
+              nfb.data_ptr(), _stream_handle(stream)))
     return out, nfb
 
 

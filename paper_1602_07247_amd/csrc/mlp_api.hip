@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "ants_internal.h"
@@ -512,10 +513,15 @@ ants_status ants_mlp_load(const char* path, ants_mlp** out) {
   return ANTS_OK;
 }
 
-ants_status ants_reconstruct_seeded(ants_lrfset* S, ants_mlp* M, const ants_grid_cfg* refine,
-                                    const ants_grid_cfg* fallback, double chi2ndf_max,
-                                    int64_t n, const float* d_signals, const float* d_seeds,
-                                    ants_out out, int32_t* d_n_fallback, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by both seeded entry points; fills Gr and Gf.
+ants_status seeded_check(ants_lrfset* S, ants_mlp* M, const ants_grid_cfg* refine,
+                         const ants_grid_cfg* fallback, double chi2ndf_max, int64_t n,
+                         const float* d_signals, const float* d_seeds, const ants_out& out,
+                         GridP* Gr, GridP* Gf) {
   if (!S || !refine || !fallback) return set_error(ANTS_E_ARG, "NULL set or grid configuration");
   if (!d_seeds) {
     ants_status st = check_pair(M, S);
@@ -528,10 +534,9 @@ ants_status ants_reconstruct_seeded(ants_lrfset* S, ants_mlp* M, const ants_grid
   if (!(chi2ndf_max >= 0.0))
     return set_error(ANTS_E_ARG, "chi2ndf_max must be >= 0 (0: every event falls back)");
   if (n < 0 || n > ((int64_t)1 << 31) - 1) return set_error(ANTS_E_ARG, "n_events out of range");
-  GridP Gr, Gf;
-  ants_status st = grid_params(S->d, refine, &Gr);
+  ants_status st = grid_params(S->d, refine, Gr);
   if (st != ANTS_OK) return st;
-  st = grid_params(S->d, fallback, &Gf);
+  st = grid_params(S->d, fallback, Gf);
   if (st != ANTS_OK) return st;
   if (n == 0) return ANTS_OK;
   if (!d_signals || !out.x || !out.y || !out.z || !out.E || !out.lnl || !out.chi2 || !out.ndf ||
@@ -540,20 +545,23 @@ ants_status ants_reconstruct_seeded(ants_lrfset* S, ants_mlp* M, const ants_grid
   int dev = 0;
   hipGetDevice(&dev);
   if (dev != S->device) return set_error(ANTS_E_ARG, "LRF set lives on another device");
-  hipStream_t s = (hipStream_t)hip_stream;
+  return ANTS_OK;
+}
+
+// The seeded path on caller-provided workspace: count (one int32, cleared
+// here by a fill kernel), list [n] int32, seeds_ws [n][4] FP32 (unused when
+// d_seeds is given).  Allocates nothing.
+hipError_t seeded_run(ants_lrfset* S, ants_mlp* M, GridP Gr, GridP Gf, double chi2ndf_max,
+                      int64_t n, const float* d_signals, const float* d_seeds, const ants_out& out,
+                      int32_t* d_n_fallback, hipStream_t s, int32_t* count, int32_t* list,
+                      float* seeds_ws) {
   hipError_t e = hipSuccess;
-  if (!S->ws_count) e = hipMalloc((void**)&S->ws_count, 16);
-  if (e == hipSuccess) e = ensure(&S->ws_list, &S->ws_list_bytes, (size_t)n * 4);
   const float* seeds = d_seeds;
-  if (!seeds && e == hipSuccess) {
-    e = ensure(&S->ws_seeds, &S->ws_seeds_bytes, (size_t)n * 16);
-    if (e == hipSuccess) {
-      e = infer(M, S, d_signals, n, (float*)S->ws_seeds, true, s);
-      seeds = (float*)S->ws_seeds;
-    }
+  if (!seeds) {
+    e = infer(M, S, d_signals, n, seeds_ws, true, s);
+    seeds = seeds_ws;
   }
-  if (e != hipSuccess) return hip_error(e, "ants_reconstruct_seeded (seeds)");
-  if (e == hipSuccess) e = launch_fill_i32(S->ws_count, 0, 1, s);
+  if (e == hipSuccess) e = launch_fill_i32(count, 0, 1, s);
   IoP io;
   memset(&io, 0, sizeof(io));
   io.sig = d_signals;
@@ -570,22 +578,98 @@ ants_status ants_reconstruct_seeded(ants_lrfset* S, ants_mlp* M, const ants_grid
   io.path = nullptr;
   io.nfp = out.n_fp64;
   io.n = n;
-  io.fb_list = (int32_t*)S->ws_list;
-  io.fb_count = S->ws_count;
+  io.fb_list = list;
+  io.fb_count = count;
   Gr.fb_thr = chi2ndf_max;
   if (e == hipSuccess) e = launch_grid(S->d, Gr, io, s, num_cu() * 8);
   // fallback pass over the listed events
   IoP io2 = io;
   io2.seeds = nullptr;
-  io2.list = (const int32_t*)S->ws_list;
-  io2.list_n = S->ws_count;
+  io2.list = list;
+  io2.list_n = count;
   io2.fb_list = nullptr;
   io2.fb_count = nullptr;
   io2.nfp = nullptr;
   Gf.or_status = ANTS_EV_FALLBACK;
   if (e == hipSuccess) e = launch_grid(S->d, Gf, io2, s, num_cu() * 8);
-  if (e == hipSuccess && d_n_fallback) e = launch_copy_i32(S->ws_count, d_n_fallback, 1, s);
+  if (e == hipSuccess && d_n_fallback) e = launch_copy_i32(count, d_n_fallback, 1, s);
+  return e;
+}
+
+// Workspace of the allocation-free seeded entry point: one fixed array per
+// device, [counter, padded to 256 B][list: kNoAllocMax int32][seeds:
+// kNoAllocMax x 4 FP32].  In host code `scratch` names a host-side stand-in;
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kNoAllocMax = ANTS_NOALLOC_MAX_EVENTS;
+constexpr size_t kScratchList = 256;
+constexpr size_t kScratchSeeds = kScratchList + (size_t)kNoAllocMax * 4;
+constexpr size_t kScratchBytes = kScratchSeeds + (size_t)kNoAllocMax * 16;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array (looked up once per device)
+hipError_t scratch_ptr(int dev, unsigned char** p) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* q = nullptr;
+    hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!q) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = q;
+  }
+  *p = (unsigned char*)g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+ants_status ants_reconstruct_seeded(ants_lrfset* S, ants_mlp* M, const ants_grid_cfg* refine,
+                                    const ants_grid_cfg* fallback, double chi2ndf_max,
+                                    int64_t n, const float* d_signals, const float* d_seeds,
+                                    ants_out out, int32_t* d_n_fallback, void* hip_stream) {
+  GridP Gr, Gf;
+  ants_status st = seeded_check(S, M, refine, fallback, chi2ndf_max, n, d_signals, d_seeds, out,
+                                &Gr, &Gf);
+  if (st != ANTS_OK || n == 0) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = hipSuccess;
+  if (!S->ws_count) e = hipMalloc((void**)&S->ws_count, 16);
+  if (e == hipSuccess) e = ensure(&S->ws_list, &S->ws_list_bytes, (size_t)n * 4);
+  if (!d_seeds && e == hipSuccess) e = ensure(&S->ws_seeds, &S->ws_seeds_bytes, (size_t)n * 16);
+  if (e != hipSuccess) return hip_error(e, "ants_reconstruct_seeded (workspace)");
+  e = seeded_run(S, M, Gr, Gf, chi2ndf_max, n, d_signals, d_seeds, out, d_n_fallback, s,
+                 S->ws_count, (int32_t*)S->ws_list, (float*)S->ws_seeds);
   return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_reconstruct_seeded");
+}
+
+ants_status ants_reconstruct_seeded_noalloc(ants_lrfset* S, ants_mlp* M,
+                                            const ants_grid_cfg* refine,
+                                            const ants_grid_cfg* fallback, double chi2ndf_max,
+                                            int64_t n, const float* d_signals,
+                                            const float* d_seeds, ants_out out,
+                                            int32_t* d_n_fallback, void* hip_stream) {
+  GridP Gr, Gf;
+  ants_status st = seeded_check(S, M, refine, fallback, chi2ndf_max, n, d_signals, d_seeds, out,
+                                &Gr, &Gf);
+  if (st != ANTS_OK || n == 0) return st;
+  if (n > kNoAllocMax)
+    return set_error(ANTS_E_ARG,
+                     "ants_reconstruct_seeded_noalloc: n_events = %lld exceeds the fixed "
+                     "workspace of %lld events (split the batch)",
+                     (long long)n, (long long)kNoAllocMax);
+  unsigned char* base = nullptr;
+  hipError_t e = scratch_ptr(S->device, &base);
+  if (e != hipSuccess) return hip_error(e, "ants_reconstruct_seeded_noalloc (scratch address)");
+  e = seeded_run(S, M, Gr, Gf, chi2ndf_max, n, d_signals, d_seeds, out, d_n_fallback,
+                 (hipStream_t)hip_stream, (int32_t*)base, (int32_t*)(base + kScratchList),
+                 (float*)(base + kScratchSeeds));
+  return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_reconstruct_seeded_noalloc");
 }
 
 }  // extern "C"

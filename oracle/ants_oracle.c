@@ -690,3 +690,166 @@ void o_reconstruct_seeded(const o_lrf* L, const o_cfg* R, const o_cfg* F, double
     status[e] |= O_FALLBACK;
   }
 }
+
+/* ------------------------------------------------------------------ */
+/* Simplex search (Sec. 5.1.2.1: the Minuit2 Simplex minimiser over x, y  */
+/* or x, y, z from the centroid or the strongest sensor).  Minuit2 itself */
+/* is not available; this is the Nelder-Mead method as defined by         */
+/* Lagarias, Reeds, Wright and Wright (SIAM J. Optim. 9, 1998), with the  */
+/* standard coefficients: reflection 1, expansion 2, contraction 1/2,     */
+/* shrink 1/2.  Readings:                                                 */
+/*  - the energy is not a free parameter: at every point it is the ratio  */
+/*    of the sums (as for the grid), so the search is over position only; */
+/*  - initial simplex: the start point and the start point moved by       */
+/*    step0[a] along each searched axis a;                                 */
+/*  - values within the tie tolerance (O_TIE_REL * N) are equal; vertices */
+/*    are kept ordered by value, a new vertex going after the vertices    */
+/*    whose value equals its own, and the best vertex staying first after */
+/*    a shrink when tied;                                                  */
+/*  - stop when every vertex lies within tol (mm) of the best one on      */
+/*    every searched axis, or after max_iter iterations (an iteration is  */
+/*    one reflection step with its expansion, contraction or shrink).     */
+/* Arithmetic is written out step by step (no fused multiply-add).        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int dims;             /* 2: x, y;  3: x, y, z                          */
+  int stat;             /* 0 ML, 1 chi2                                  */
+  int start;            /* 0 CoG, 1 strongest sensor, 2 seed             */
+  double step0[3];      /* initial simplex edge per axis (mm)            */
+  double z_start;
+  double tol;           /* convergence size (mm)                          */
+  int max_iter;
+  double l_floor, v_floor;
+} o_scfg;
+
+typedef struct { double p[3]; double f; } o_vtx;
+
+static int o_lt(double a, double b, double tol) { return a < b - tol; }
+
+/* insert w into v[0..n-1] (ordered) after every vertex whose value is not
+ * above w's (within the tolerance): v becomes n+1 ordered vertices */
+static void o_sx_insert(o_vtx* v, int n, o_vtx w, double tol) {
+  int pos = n;
+  while (pos > 0 && o_lt(w.f, v[pos - 1].f, tol)) { v[pos] = v[pos - 1]; --pos; }
+  v[pos] = w;
+}
+
+void o_simplex_event(const o_lrf* L, const o_scfg* S, const double* n, const double* seed,
+                     double out[6], int* ndf, int* status, int* iters) {
+  int ns = L->n_sensors, na = 0, bad = 0, d = S->dims;
+  double N = 0.0;
+  *status = 0;
+  *iters = 0;
+  for (int i = 0; i < ns; ++i) {
+    if (!L->active[i]) continue;
+    ++na;
+    if (!isfinite(n[i]) || n[i] < 0.0) bad = 1;
+    else N += n[i];
+  }
+  *ndf = na - (d + 1);
+  for (int k = 0; k < 6; ++k) out[k] = NAN;
+  if (na == 0) { *status = O_NO_ACTIVE; return; }
+  if (bad) { *status = O_BAD_INPUT; return; }
+  if (!(N > 0.0)) { *status = O_EMPTY; return; }
+  /* statistic settings shared with the grid's node evaluation */
+  o_cfg C;
+  memset(&C, 0, sizeof(C));
+  C.stat = S->stat;
+  C.l_floor = S->l_floor;
+  C.v_floor = S->v_floor;
+  /* start (Sec. 5.1.1 centroid, Sec. 5.1.2.1 strongest sensor, or seed) */
+  double c0[3] = {0.0, 0.0, S->z_start};
+  if (S->start == 2 && seed) {
+    c0[0] = seed[0]; c0[1] = seed[1];
+    if (d == 3) c0[2] = seed[2];
+  } else if (S->start == 1) {
+    int best = -1;
+    for (int i = 0; i < ns; ++i)
+      if (L->active[i] && (best < 0 || n[i] > n[best])) best = i;
+    c0[0] = L->sxy[2 * best]; c0[1] = L->sxy[2 * best + 1];
+  } else {
+    double sw = 0.0, sx = 0.0, sy = 0.0;
+    for (int i = 0; i < ns; ++i) {
+      if (!L->active[i]) continue;
+      double w = n[i] / L->gain[i];
+      sw += w; sx += L->sxy[2 * i] * w; sy += L->sxy[2 * i + 1] * w;
+    }
+    c0[0] = sx / sw; c0[1] = sy / sw;
+  }
+  const double tf = O_TIE_REL * N;
+  o_vtx v[4];
+  for (int i = 0; i <= d; ++i) {
+    o_vtx w;
+    for (int a = 0; a < 3; ++a) w.p[a] = c0[a];
+    if (i > 0) w.p[i - 1] = c0[i - 1] + S->step0[i - 1];
+    w.f = o_node_eval(L, &C, n, N, w.p[0], w.p[1], w.p[2]).stat;
+    o_sx_insert(v, i, w, tf);
+  }
+  int it = 0;
+  for (;;) {
+    int conv = 1;
+    for (int i = 1; i <= d; ++i)
+      for (int a = 0; a < d; ++a)
+        if (fabs(v[i].p[a] - v[0].p[a]) > S->tol) conv = 0;
+    if (conv) break;
+    if (!(v[0].f < INFINITY)) { *status |= O_NO_VALID_NODE; break; }
+    if (it >= S->max_iter) break;
+    ++it;
+    /* centroid of the d best vertices */
+    double c[3];
+    for (int a = 0; a < 3; ++a) {
+      double s = 0.0;
+      for (int i = 0; i < d; ++i) s += v[i].p[a];
+      c[a] = (a < d) ? s / (double)d : v[0].p[a];
+    }
+    o_vtx r, acc;
+    int shrink = 0;
+    for (int a = 0; a < 3; ++a) r.p[a] = (a < d) ? c[a] + (c[a] - v[d].p[a]) : c[a];
+    r.f = o_node_eval(L, &C, n, N, r.p[0], r.p[1], r.p[2]).stat;
+    if (!o_lt(r.f, v[0].f, tf) && o_lt(r.f, v[d - 1].f, tf)) {
+      acc = r;                                       /* reflection */
+    } else if (o_lt(r.f, v[0].f, tf)) {
+      o_vtx e;                                       /* expansion */
+      for (int a = 0; a < 3; ++a) e.p[a] = (a < d) ? c[a] + 2.0 * (r.p[a] - c[a]) : c[a];
+      e.f = o_node_eval(L, &C, n, N, e.p[0], e.p[1], e.p[2]).stat;
+      acc = o_lt(e.f, r.f, tf) ? e : r;
+    } else if (o_lt(r.f, v[d].f, tf)) {
+      o_vtx k;                                       /* outside contraction */
+      for (int a = 0; a < 3; ++a) k.p[a] = (a < d) ? c[a] + 0.5 * (r.p[a] - c[a]) : c[a];
+      k.f = o_node_eval(L, &C, n, N, k.p[0], k.p[1], k.p[2]).stat;
+      if (!o_lt(r.f, k.f, tf)) acc = k; else shrink = 1;
+    } else {
+      o_vtx k;                                       /* inside contraction */
+      for (int a = 0; a < 3; ++a) k.p[a] = (a < d) ? c[a] + 0.5 * (v[d].p[a] - c[a]) : c[a];
+      k.f = o_node_eval(L, &C, n, N, k.p[0], k.p[1], k.p[2]).stat;
+      if (o_lt(k.f, v[d].f, tf)) acc = k; else shrink = 1;
+    }
+    if (!shrink) {
+      o_sx_insert(v, d, acc, tf);
+    } else {
+      o_vtx w[4];
+      w[0] = v[0];
+      for (int i = 1; i <= d; ++i) {
+        for (int a = 0; a < 3; ++a)
+          w[i].p[a] = (a < d) ? v[0].p[a] + 0.5 * (v[i].p[a] - v[0].p[a]) : v[0].p[a];
+        w[i].f = o_node_eval(L, &C, n, N, w[i].p[0], w[i].p[1], w[i].p[2]).stat;
+      }
+      v[0] = w[0];
+      for (int i = 1; i <= d; ++i) o_sx_insert(v, i, w[i], tf);
+    }
+  }
+  *iters = it;
+  o_node fin = o_node_eval(L, &C, n, N, v[0].p[0], v[0].p[1], v[0].p[2]);
+  out[0] = v[0].p[0]; out[1] = v[0].p[1]; out[2] = v[0].p[2];
+  out[3] = fin.A; out[4] = fin.lnl; out[5] = fin.chi2;
+  if (!(fin.S > 0.0)) *status |= O_NO_VALID_NODE;
+}
+
+void o_reconstruct_simplex(const o_lrf* L, const o_scfg* S, int64_t n_ev, const double* sig,
+                           const double* seeds, double* out6, int* ndf, int* status, int* iters,
+                           int n_threads) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+  for (int64_t e = 0; e < n_ev; ++e)
+    o_simplex_event(L, S, sig + e * L->n_sensors, seeds ? seeds + 4 * e : NULL, out6 + 6 * e,
+                    ndf + e, status + e, iters + e);
+}

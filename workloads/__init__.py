@@ -136,6 +136,21 @@ class GridCfg:
 
 
 @dataclass
+class SimplexCfg:
+    """Simplex (Nelder-Mead) search settings: searched axes, statistic,
+    start, initial simplex edge per axis, convergence size, iteration cap."""
+    dims: int = 2              # 2: x, y; 3: x, y, z
+    stat: int = 0              # 0 ML, 1 chi2
+    start: int = 0             # 0 CoG, 1 strongest sensor, 2 seed
+    step0: tuple = (7.5, 7.5, 0.0)
+    z_start: float = 0.0
+    tol: float = 1e-3          # mm: every vertex within tol of the best, per axis
+    max_iter: int = 200
+    l_floor: float = 1e-9
+    v_floor: float = 1.0
+
+
+@dataclass
 class EventRecipe:
     region: str                # "disc" or "square"
     extent: float              # disc radius or square half-width (mm)

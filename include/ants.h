@@ -199,6 +199,39 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
                              void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Simplex search (Sec. 5.1.2.1: the Minuit2 Simplex minimiser over the  */
+/* position, x, y or x, y, z, from the centroid or the strongest        */
+/* sensor; here also from a seed).  The Nelder-Mead method as defined by */
+/* Lagarias, Reeds, Wright and Wright (SIAM J. Optim. 9, 1998):         */
+/* coefficients 1 (reflection), 2 (expansion), 1/2 (contraction), 1/2   */
+/* (shrink); initial simplex = the start and the start moved by step0[a] */
+/* along each searched axis a; vertices ordered by the statistic of the */
+/* grid search (same definitions, energy A = N/S at every point), values */
+/* within 1e-12 N equal and a new vertex placed after the vertices equal */
+/* to it; stop when every vertex is within tol of the best on every     */
+/* searched axis, or after max_iter iterations.  Everything is FP64.    */
+/* Outputs as for ants_reconstruct at the best vertex (z = z_start for  */
+/* dims = 2); d_iters [n] (optional, device) receives the iterations    */
+/* run per event.  ANTS_EV_NO_VALID_NODE: the search ended on a point   */
+/* with S <= 0 (outputs NaN).                                           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t dims;          /* 2: x, y;  3: x, y, z (r-z LRFs only)             */
+  int32_t stat;          /* ants_stat                                        */
+  int32_t start;         /* ants_start; SEED reads d_seeds [n][4] (x, y, z, -) */
+  double step0[3];       /* initial simplex edge per searched axis, mm (> 0)  */
+  double z_start;        /* start z (also the output z of 2-D searches)      */
+  double tol;            /* convergence size, mm (> 0)                       */
+  int32_t max_iter;      /* iteration cap, 0 .. 100000                       */
+  double l_floor, v_floor;
+} ants_simplex_cfg;
+
+ants_status ants_reconstruct_simplex(ants_lrfset* set, const ants_simplex_cfg* cfg,
+                                     int64_t n_events, const float* d_signals,
+                                     const float* d_seeds, ants_out out, int32_t* d_iters,
+                                     void* hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* One persistent launch over event chunks from several detectors (one  */
 /* LRF set and grid configuration per detector; every set must have the */
 /* same LRF kind and the same statistic).  Chunk c holds n_events rows   */
@@ -215,7 +248,10 @@ typedef struct {
 
 /* Launch plan: events per work item, resident blocks per compute unit,
  * and whether the LRF tables are staged in LDS (1) or read through the
- * cache (0).  NULL plan = {32, 8, 1}. */
+ * cache (0), for every set.  NULL plan = each set's part of the plan that
+ * ants_autotune_multi stored in its handle for its configuration, else
+ * {32, 8, 1}.  Within one launch each set also runs with the fewest sensor
+ * slots per lane that hold its sensors. */
 typedef struct {
   int32_t events_per_item;   /* 1 .. 4096 */
   int32_t blocks_per_cu;     /* 1 .. 32   */
@@ -223,18 +259,27 @@ typedef struct {
 } ants_plan;
 
 /* ants_out.path is ignored (n_fp64 likewise).  Up to 64 sets and 2^24 chunks.
- * The library keeps descriptor workspace in sets[0]; calls sharing
- * sets[0] must not overlap. */
+ * The library keeps descriptor workspace in sets[0] (device memory and a
+ * pinned host staging area); the descriptors are copied on the stream and
+ * the call does not wait for the device, except that it waits for the
+ * previous call's descriptor copy before reusing the staging area.  Calls
+ * sharing sets[0] must not overlap on different streams. */
 ants_status ants_reconstruct_multi(ants_lrfset* const* sets, const ants_grid_cfg* cfgs,
                                    int32_t n_sets, const ants_chunk* chunks, int32_t n_chunks,
                                    const ants_plan* plan, ants_out out, void* hip_stream);
 
-/* Autotuner: times every candidate plan (events per item 8/32/128, blocks
- * per CU 4/8/16, tables in LDS or not) on the first `sample_events` events
- * of the chunk stream, writing into `scratch` (rows 0 .. sample_events-1),
- * and returns the fastest in *best; host_ms [18] receives each candidate's
- * time in the order above (table outermost) or NULL.  Synchronises the
- * stream.  The choice depends on timing; the reconstructed values do not. */
+/* Autotuner: times candidate plans on a sample of `sample_events` events
+ * made of whole chunks taken at an even stride through the stream (every
+ * detector in proportion), writing into `scratch` (rows 0 ..
+ * sample_events-1).  Only the kernel is timed (HIP events around the
+ * launch, descriptors uploaded before).  Search: blocks per CU 4/8/16 with
+ * the default per-set plan, then for each set in turn events per item
+ * 8/32/128 x tables in LDS or not, keeping the best so far.  Each set's
+ * part of the result is stored in its handle for its configuration (used
+ * when ants_reconstruct_multi gets a NULL plan); *best receives the first
+ * set's part; host_ms [3 + 6 n_sets] (or NULL) each candidate's time in
+ * search order.  Synchronises the stream.  The choice depends on timing;
+ * the reconstructed values do not. */
 ants_status ants_autotune_multi(ants_lrfset* const* sets, const ants_grid_cfg* cfgs,
                                 int32_t n_sets, const ants_chunk* chunks, int32_t n_chunks,
                                 int64_t sample_events, ants_out scratch, ants_plan* best,

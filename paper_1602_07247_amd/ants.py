@@ -84,6 +84,12 @@ class Plan(C.Structure):
                 ("table_in_lds", C.c_int32)]
 
 
+class SimplexCfg(C.Structure):
+    _fields_ = [("dims", C.c_int32), ("stat", C.c_int32), ("start", C.c_int32),
+                ("step0", C.c_double * 3), ("z_start", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("l_floor", C.c_double), ("v_floor", C.c_double)]
+
+
 class FitCfg(C.Structure):
     _fields_ = [("nb", C.c_int32), ("lo", C.c_double), ("hi", C.c_double), ("ridge", C.c_double),
                 ("chi2ndf_max", C.c_double)]
@@ -132,6 +138,9 @@ _lib.ants_autotune_multi.argtypes = [C.POINTER(_vp), C.POINTER(GridCfg), C.c_int
                                      C.POINTER(Chunk), C.c_int32, C.c_int64, Out, C.POINTER(Plan),
                                      C.POINTER(C.c_double), _vp]
 
+_lib.ants_reconstruct_simplex.argtypes = [_vp, C.POINTER(SimplexCfg), C.c_int64, _vp, _vp, Out,
+                                          _vp, _vp]
+
 _lib.ants_fit_axial_lrf.argtypes = [_vp, C.POINTER(FitCfg), C.c_int64, _vp, C.c_int64, Out, _vp,
                                     _vp, _vp]
 
@@ -142,7 +151,8 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_mlp_train", "ants_mlp_save", "ants_mlp_load", "ants_reconstruct_seeded",
             "ants_reconstruct_seeded_noalloc",
             "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf",
-            "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load")
+            "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load",
+            "ants_reconstruct_simplex")
 
 
 def _check(code):
@@ -296,6 +306,42 @@ def reconstruct(lrfset: LrfSet, cfg: GridCfg, signals, seeds=None, out=None, str
         sp = seeds.data_ptr()
     _check(_lib.ants_reconstruct(lrfset.handle, C.byref(cfg), n, signals.data_ptr(), sp,
                                  _out_struct(out), _stream_handle(stream)))
+    return out
+
+
+def simplex_cfg(g) -> SimplexCfg:
+    """SimplexCfg from an object with dims, stat, start, step0, z_start, tol,
+    max_iter, l_floor, v_floor (see workloads.SimplexCfg)."""
+    c = SimplexCfg()
+    c.dims, c.stat, c.start = int(g.dims), int(g.stat), int(g.start)
+    for k in range(3):
+        c.step0[k] = float(g.step0[k])
+    c.z_start, c.tol, c.max_iter = float(g.z_start), float(g.tol), int(g.max_iter)
+    c.l_floor, c.v_floor = float(g.l_floor), float(g.v_floor)
+    return c
+
+
+def reconstruct_simplex(lrfset: LrfSet, cfg: SimplexCfg, signals, seeds=None, out=None,
+                        stream=None, iters=True):
+    """Simplex search per event (ants_reconstruct_simplex).  Returns the
+    dict of output tensors, with "iters" (iterations per event) when
+    iters=True (asynchronous)."""
+    import torch
+    assert signals.dtype == torch.float32 and signals.is_cuda and signals.is_contiguous()
+    n = signals.shape[0]
+    assert signals.dim() == 2 and signals.shape[1] == lrfset.n_sensors, signals.shape
+    if out is None:
+        out = alloc_out(n, 0, signals.device)
+    if iters and "iters" not in out:
+        out["iters"] = torch.empty(n, dtype=torch.int32, device=signals.device)
+    sp = None
+    if seeds is not None:
+        assert seeds.dtype == torch.float32 and seeds.is_cuda and seeds.is_contiguous()
+        assert seeds.shape == (n, 4)
+        sp = seeds.data_ptr()
+    it = out["iters"].data_ptr() if "iters" in out else None
+    _check(_lib.ants_reconstruct_simplex(lrfset.handle, C.byref(cfg), n, signals.data_ptr(), sp,
+                                         _out_struct(out), it, _stream_handle(stream)))
     return out
 
 
@@ -472,12 +518,14 @@ def reconstruct_multi(sets, cfgs, chunks, n_out, plan=None, out=None, stream=Non
 
 
 def autotune_multi(sets, cfgs, chunks, sample_events, stream=None):
-    """Time the candidate plans on the first sample_events events; returns
-    (best Plan, per-candidate milliseconds)."""
+    """Time the candidate plans on a sample of sample_events events spread
+    over the stream and store each set's part of the best plan in its
+    handle (used by reconstruct_multi with plan=None); returns (best Plan
+    for the first set, per-candidate milliseconds)."""
     hs, cs, ch = _multi_args(sets, cfgs, chunks)
     scratch = alloc_out(sample_events, 0, chunks[0][1].device)
     best = Plan()
-    ms = np.zeros(18, np.float64)
+    ms = np.zeros(3 + 6 * len(sets), np.float64)
     _check(_lib.ants_autotune_multi(hs, cs, len(sets), ch, len(chunks), sample_events,
                                     _out_struct(scratch), C.byref(best),
                                     ms.ctypes.data_as(C.POINTER(C.c_double)),

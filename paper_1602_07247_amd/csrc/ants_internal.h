@@ -139,8 +139,9 @@ hipError_t launch_gen(const DevLrf& L, const GenP& P, hipStream_t stream, int ma
 struct SetDesc {
   DevLrf L;
   GridP G;
-  int tab_off;         // float4 offset of the set's table in the block's LDS
-  int pad_;
+  int tab_off;         // float4 offset of the set's table in the block's LDS, or -1:
+                       // the table is read through the cache
+  int T;               // events per work item of this set's chunks
 };
 struct ChunkDesc {
   const float* sig;    // [n][ns of its set]
@@ -156,12 +157,11 @@ struct MultiP {
   const int32_t* prefix;   // [n_chunks + 1] first work item of each chunk
   int n_chunks;
   int n_items;
-  int T;                   // events per work item
+  int xg;                  // work items per run claimed on one XCD
   int* counter;            // 8 work counters, 16 ints apart (zeroed before the launch)
   IoP out;                 // output arrays (offset per chunk)
   int per_wave_bytes;
-  int btab_n;
-  int tab_in_lds;
+  int btab_n;              // float4 entries of the sets' tables staged in LDS
 };
 hipError_t launch_multi(const MultiP& P, int kind, int stat, int max_nn, int max_na, bool nonneg,
                         int blocks, hipStream_t s);
@@ -258,9 +258,18 @@ struct ants_lrfset {
   void* ws_list = nullptr;
   size_t ws_list_bytes = 0;
   int32_t* ws_count = nullptr;
-  // workspace of the multi-detector launch (descriptors, counter)
+  // workspace of the multi-detector launch (descriptors, counter), its
+  // pinned host staging and the event that marks the end of the last copy
+  // from it
   void* ws_multi = nullptr;
   size_t ws_multi_bytes = 0;
+  void* ms_host = nullptr;
+  size_t ms_host_bytes = 0;
+  hipEvent_t ms_copied = nullptr;
+  // this set's part of a multi-detector plan (from ants_autotune_multi),
+  // valid for the grid configuration whose hash is mplan_key
+  uint64_t mplan_key = 0;
+  int32_t mplan_T = 0, mplan_lds = 1, mplan_bpc = 0;
   // workspace of the LRF fit (per-wave partial normal equations)
   void* ws_fit = nullptr;
   size_t ws_fit_bytes = 0;

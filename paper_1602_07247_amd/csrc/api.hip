@@ -278,6 +278,11 @@ ants_status ants_lrfset_destroy(ants_lrfset* set) {
   if (set->ws_list) (void)hipFree(set->ws_list);
   if (set->ws_count) (void)hipFree(set->ws_count);
   if (set->ws_multi) (void)hipFree(set->ws_multi);
+  if (set->ms_copied) {
+    (void)hipEventSynchronize(set->ms_copied);
+    (void)hipEventDestroy(set->ms_copied);
+  }
+  if (set->ms_host) (void)hipHostFree(set->ms_host);
   if (set->ws_fit) (void)hipFree(set->ws_fit);
   delete set;
   return ANTS_OK;

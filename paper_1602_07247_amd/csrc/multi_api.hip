@@ -13,9 +13,38 @@ namespace {
 struct Prepared {
   std::vector<SetDesc> sets;
   std::vector<ChunkDesc> chunks;
-  int kind = 0, stat = 0, max_nn = 0, max_na = 0, btab_n = 0, per_wave = 0;
+  std::vector<int> tab_n;   // float4 entries of each set's table
+  int kind = 0, stat = 0, max_nn = 0, max_na = 0, per_wave = 0;
   bool nonneg = true;
 };
+
+// A plan with a part per set (events per work item, table in LDS) and a
+// launch-wide part (resident blocks per compute unit).
+struct MPlan {
+  int bpc = 8;
+  std::vector<int> T, lds;
+};
+
+// Key of a grid configuration in a set's plan (the fields that change the
+// work per event).
+uint64_t cfg_key(const ants_grid_cfg& c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(c.nodes, sizeof(c.nodes));
+  mix(&c.iterations, sizeof(c.iterations));
+  mix(&c.stat, sizeof(c.stat));
+  mix(&c.start, sizeof(c.start));
+  mix(&c.screen_scale, sizeof(c.screen_scale));
+  mix(&c.cut_signal, sizeof(c.cut_signal));
+  mix(&c.cut_distance, sizeof(c.cut_distance));
+  return h | 1;   // never 0 (0 = no plan)
+}
 
 ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets,
                     const ants_chunk* ch, int n_chunks, Prepared* P) {
@@ -25,7 +54,7 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
     return set_error(ANTS_E_ARG, "n_chunks = %d out of range", n_chunks);
   int dev = 0;
   hipGetDevice(&dev);
-  int tab = 0, per_wave = 0;
+  int per_wave = 0;
   for (int i = 0; i < n_sets; ++i) {
     if (!S[i]) return set_error(ANTS_E_ARG, "sets[%d] is NULL", i);
     if (S[i]->device != dev) return set_error(ANTS_E_ARG, "sets[%d] lives on another device", i);
@@ -42,11 +71,9 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
     } else if (d.L.kind != P->kind || d.G.stat != P->stat) {
       return set_error(ANTS_E_UNSUPPORTED, "all sets must share LRF kind and statistic");
     }
-    d.tab_off = tab;
-    const int n = d.L.kind == ANTS_LRF_AXIAL ? d.L.ntab * d.L.nintp
-                  : d.L.kind == ANTS_LRF_RZ  ? d.L.nc1 * d.L.nintp
-                                             : 0;
-    tab += n;
+    P->tab_n.push_back(d.L.kind == ANTS_LRF_AXIAL ? d.L.ntab * d.L.nintp
+                       : d.L.kind == ANTS_LRF_RZ  ? d.L.nc1 * d.L.nintp
+                                                  : 0);
     P->nonneg = P->nonneg && d.L.nonneg;
     P->max_nn = d.G.nn > P->max_nn ? d.G.nn : P->max_nn;
     P->max_na = d.L.na > P->max_na ? d.L.na : P->max_na;
@@ -58,9 +85,6 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
                                   node_tiles(P->max_nn));
     per_wave = pw > per_wave ? pw : per_wave;
   }
-  if ((size_t)tab * 16 > 96 * 1024)
-    return set_error(ANTS_E_UNSUPPORTED, "LRF tables of all sets exceed 96 KiB of LDS");
-  P->btab_n = tab;
   P->per_wave = (per_wave + 15) & ~15;
   for (int c = 0; c < n_chunks; ++c) {
     if (ch[c].set < 0 || ch[c].set >= n_sets)
@@ -80,77 +104,119 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
   return ANTS_OK;
 }
 
-ants_status run(ants_lrfset* owner, const Prepared& P, const ants_plan& plan, ants_out out,
-                int64_t limit_events, hipStream_t s) {
-  if (plan.events_per_item < 1 || plan.events_per_item > 4096 || plan.blocks_per_cu < 1 ||
-      plan.blocks_per_cu > 32 || (plan.table_in_lds != 0 && plan.table_in_lds != 1))
-    return set_error(ANTS_E_ARG, "invalid plan {%d, %d, %d}", plan.events_per_item,
-                     plan.blocks_per_cu, plan.table_in_lds);
-  // chunk list truncated to `limit_events` (autotuning samples)
-  std::vector<ChunkDesc> ch;
-  int64_t left = limit_events;
-  for (const ChunkDesc& c : P.chunks) {
-    if (left <= 0) break;
-    ChunkDesc d = c;
-    if (d.n > left) d.n = left;
-    left -= d.n;
-    if (d.n > 0) ch.push_back(d);
+ants_status check_plan(const MPlan& pl) {
+  if (pl.bpc < 1 || pl.bpc > 32) return set_error(ANTS_E_ARG, "blocks_per_cu = %d outside 1..32", pl.bpc);
+  for (size_t i = 0; i < pl.T.size(); ++i)
+    if (pl.T[i] < 1 || pl.T[i] > 4096 || (pl.lds[i] != 0 && pl.lds[i] != 1))
+      return set_error(ANTS_E_ARG, "invalid plan for set %zu: {%d events, lds %d}", i, pl.T[i],
+                       pl.lds[i]);
+  return ANTS_OK;
+}
+
+// Descriptors of `ch` under plan `pl` copied to the device workspace of
+// `owner`, stream-ordered: the pinned staging is reused only after the copy
+// that last read it has finished (an event, not a stream synchronisation).
+ants_status upload(ants_lrfset* owner, const Prepared& P, const MPlan& pl,
+                   const std::vector<ChunkDesc>& ch, ants_out out, hipStream_t s, MultiP* M) {
+  std::vector<SetDesc> sets = P.sets;
+  int tab = 0, tmin = 4096;
+  for (size_t i = 0; i < sets.size(); ++i) {
+    sets[i].T = pl.T[i];
+    tmin = pl.T[i] < tmin ? pl.T[i] : tmin;
+    sets[i].tab_off = -1;
+    if (pl.lds[i] && P.tab_n[i] > 0) {
+      sets[i].tab_off = tab;
+      tab += P.tab_n[i];
+    }
   }
+  if ((size_t)tab * 16 > 96 * 1024)
+    return set_error(ANTS_E_UNSUPPORTED, "LRF tables staged in LDS exceed 96 KiB");
   std::vector<int32_t> prefix(ch.size() + 1, 0);
   for (size_t c = 0; c < ch.size(); ++c) {
-    int64_t items = (ch[c].n + plan.events_per_item - 1) / plan.events_per_item;
-    int64_t next = prefix[c] + items;
+    const int T = pl.T[ch[c].set];
+    int64_t next = prefix[c] + (ch[c].n + T - 1) / T;
     if (next > ((int64_t)1 << 31) - 2) return set_error(ANTS_E_ARG, "too many work items");
     prefix[c + 1] = (int32_t)next;
   }
-  if (ch.empty()) return ANTS_OK;
-  const size_t b_sets = P.sets.size() * sizeof(SetDesc);
+  const size_t b_sets = sets.size() * sizeof(SetDesc);
   const size_t b_ch = ch.size() * sizeof(ChunkDesc);
   const size_t b_pre = prefix.size() * sizeof(int32_t);
   const size_t o1 = 512, o2 = o1 + ((b_sets + 255) & ~(size_t)255),
                o3 = o2 + ((b_ch + 255) & ~(size_t)255), total = o3 + b_pre;
-  std::vector<unsigned char> host(total, 0);
-  memcpy(host.data() + o1, P.sets.data(), b_sets);
-  memcpy(host.data() + o2, ch.data(), b_ch);
-  memcpy(host.data() + o3, prefix.data(), b_pre);
-  hipError_t e = ensure(&owner->ws_multi, &owner->ws_multi_bytes, total);
+  hipError_t e = hipSuccess;
+  if (!owner->ms_copied) e = hipEventCreateWithFlags(&owner->ms_copied, hipEventDisableTiming);
+  // the previous call's copy from the staging must be done before reuse
+  if (e == hipSuccess) e = hipEventSynchronize(owner->ms_copied);
+  if (e == hipSuccess && owner->ms_host_bytes < total) {
+    if (owner->ms_host) (void)hipHostFree(owner->ms_host);
+    owner->ms_host = nullptr;
+    owner->ms_host_bytes = 0;
+    e = hipHostMalloc(&owner->ms_host, total, hipHostMallocDefault);
+    if (e == hipSuccess) owner->ms_host_bytes = total;
+  }
+  if (e == hipSuccess) e = ensure(&owner->ws_multi, &owner->ws_multi_bytes, total);
+  if (e != hipSuccess) return hip_error(e, "multi-detector workspace");
+  unsigned char* host = (unsigned char*)owner->ms_host;
+  memset(host, 0, o1);
+  memcpy(host + o1, sets.data(), b_sets);
+  memcpy(host + o2, ch.data(), b_ch);
+  memcpy(host + o3, prefix.data(), b_pre);
   unsigned char* dbase = (unsigned char*)owner->ws_multi;
-  // the host staging vector dies on return: wait for the copy (it is queued
-  // behind earlier work on the stream, which may still read the workspace)
-  if (e == hipSuccess) e = hipMemcpyAsync(dbase, host.data(), total, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  e = hipMemcpyAsync(dbase, host, total, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(owner->ms_copied, s);
   if (e != hipSuccess) return hip_error(e, "multi-detector descriptors");
-  MultiP M;
-  memset(&M, 0, sizeof(M));
-  M.sets = (const SetDesc*)(dbase + o1);
-  M.n_sets = (int)P.sets.size();
-  M.chunks = (const ChunkDesc*)(dbase + o2);
-  M.prefix = (const int32_t*)(dbase + o3);
-  M.n_chunks = (int)ch.size();
-  M.n_items = prefix.back();
-  M.T = plan.events_per_item;
-  M.counter = (int*)dbase;   // first 512 bytes: one work counter per XCD, 64 bytes apart
-  M.out.x = out.x;
-  M.out.y = out.y;
-  M.out.z = out.z;
-  M.out.E = out.E;
-  M.out.lnl = out.lnl;
-  M.out.chi2 = out.chi2;
-  M.out.ndf = out.ndf;
-  M.out.status = out.status;
-  M.per_wave_bytes = P.per_wave;
-  M.btab_n = plan.table_in_lds ? P.btab_n : 0;
-  M.tab_in_lds = plan.table_in_lds;
-  e = launch_fill_i32(M.counter, 0, 128, s);
-  int blocks = num_cu() * plan.blocks_per_cu;
+  memset(M, 0, sizeof(*M));
+  M->sets = (const SetDesc*)(dbase + o1);
+  M->n_sets = (int)sets.size();
+  M->chunks = (const ChunkDesc*)(dbase + o2);
+  M->prefix = (const int32_t*)(dbase + o3);
+  M->n_chunks = (int)ch.size();
+  M->n_items = prefix.back();
+  M->xg = tmin >= 32 ? 1 : 32 / tmin;
+  M->counter = (int*)dbase;   // first 512 bytes: one work counter per XCD, 64 bytes apart
+  M->out.x = out.x;
+  M->out.y = out.y;
+  M->out.z = out.z;
+  M->out.E = out.E;
+  M->out.lnl = out.lnl;
+  M->out.chi2 = out.chi2;
+  M->out.ndf = out.ndf;
+  M->out.status = out.status;
+  M->per_wave_bytes = P.per_wave;
+  M->btab_n = tab;
+  return ANTS_OK;
+}
+
+// counters zeroed by a kernel, then the persistent launch
+hipError_t launch(const Prepared& P, const MPlan& pl, const MultiP& M, hipStream_t s,
+                  hipEvent_t before = nullptr, hipEvent_t after = nullptr) {
+  if (M.n_chunks == 0) return hipSuccess;
+  hipError_t e = launch_fill_i32(M.counter, 0, 128, s);
+  int blocks = num_cu() * pl.bpc;
   int64_t need = ((int64_t)M.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > need) blocks = (int)(need > 0 ? need : 1);
+  if (e == hipSuccess && before) e = hipEventRecord(before, s);
   if (e == hipSuccess) e = launch_multi(M, P.kind, P.stat, P.max_nn, P.max_na, P.nonneg, blocks, s);
-  return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_reconstruct_multi launch");
+  if (e == hipSuccess && after) e = hipEventRecord(after, s);
+  return e;
 }
 
 bool outputs_ok(const ants_out& o) {
   return o.x && o.y && o.z && o.E && o.lnl && o.chi2 && o.ndf && o.status;
+}
+
+// the plan stored in the sets for these configurations (defaults elsewhere)
+MPlan stored_plan(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n) {
+  MPlan pl;
+  pl.T.assign(n, 32);
+  pl.lds.assign(n, 1);
+  for (int i = 0; i < n; ++i)
+    if (S[i]->mplan_key == cfg_key(cfgs[i]) && S[i]->mplan_T > 0) {
+      pl.T[i] = S[i]->mplan_T;
+      pl.lds[i] = S[i]->mplan_lds;
+    }
+  if (S[0]->mplan_key == cfg_key(cfgs[0]) && S[0]->mplan_bpc > 0) pl.bpc = S[0]->mplan_bpc;
+  return pl;
 }
 
 }  // namespace
@@ -164,8 +230,26 @@ ants_status ants_reconstruct_multi(ants_lrfset* const* sets, const ants_grid_cfg
   ants_status st = prepare(sets, cfgs, n_sets, chunks, n_chunks, &P);
   if (st != ANTS_OK) return st;
   if (!outputs_ok(out)) return set_error(ANTS_E_ARG, "an output array is NULL");
-  ants_plan pl = plan ? *plan : ants_plan{32, 8, 1};
-  return run(sets[0], P, pl, out, INT64_MAX, (hipStream_t)hip_stream);
+  MPlan pl;
+  if (plan) {
+    pl.bpc = plan->blocks_per_cu;
+    pl.T.assign(n_sets, plan->events_per_item);
+    pl.lds.assign(n_sets, plan->table_in_lds);
+  } else {
+    pl = stored_plan(sets, cfgs, n_sets);
+  }
+  st = check_plan(pl);
+  if (st != ANTS_OK) return st;
+  std::vector<ChunkDesc> ch;
+  for (const ChunkDesc& c : P.chunks)
+    if (c.n > 0) ch.push_back(c);
+  if (ch.empty()) return ANTS_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  MultiP M;
+  st = upload(sets[0], P, pl, ch, out, s, &M);
+  if (st != ANTS_OK) return st;
+  hipError_t e = launch(P, pl, M, s);
+  return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_reconstruct_multi launch");
 }
 
 ants_status ants_autotune_multi(ants_lrfset* const* sets, const ants_grid_cfg* cfgs,
@@ -178,38 +262,95 @@ ants_status ants_autotune_multi(ants_lrfset* const* sets, const ants_grid_cfg* c
   if (!best || !outputs_ok(scratch) || sample_events < 1)
     return set_error(ANTS_E_ARG, "autotune needs outputs, a plan pointer and a sample > 0");
   hipStream_t s = (hipStream_t)hip_stream;
-  // scratch rows are 0 .. sample-1: rewrite chunk output offsets
-  int64_t row = 0;
-  for (ChunkDesc& c : P.chunks) {
-    c.out_off = row;
-    row += c.n;
+  // sample: whole chunks taken at an even stride through the stream (every
+  // detector in proportion), written to scratch rows 0 .. sample-1
+  int64_t total = 0;
+  for (const ChunkDesc& c : P.chunks) total += c.n;
+  std::vector<ChunkDesc> ch;
+  if (total > 0) {
+    const double stride = (double)total / (double)(sample_events < total ? sample_events : total);
+    int64_t row = 0, pos = 0;
+    double next = 0.0;
+    for (const ChunkDesc& c : P.chunks) {
+      if (c.n > 0 && (double)pos + (double)c.n > next && row < sample_events) {
+        ChunkDesc d = c;
+        if (d.n > sample_events - row) d.n = sample_events - row;
+        d.out_off = row;
+        row += d.n;
+        ch.push_back(d);
+        next += (double)c.n * stride;
+      }
+      pos += c.n;
+    }
   }
+  if (ch.empty()) return set_error(ANTS_E_ARG, "autotune: no events in the chunk list");
   hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+  if (hipEventCreate(&a) != hipSuccess) return set_error(ANTS_E_DEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
     return set_error(ANTS_E_DEVICE, "hipEventCreate failed");
-  const int Ts[3] = {8, 32, 128}, Bs[3] = {4, 8, 16};
-  double best_ms = HUGE_VAL;
+  }
   int k = 0;
-  for (int lds = 1; lds >= 0 && st == ANTS_OK; --lds)
-    for (int ti = 0; ti < 3 && st == ANTS_OK; ++ti)
-      for (int bi = 0; bi < 3 && st == ANTS_OK; ++bi, ++k) {
-        ants_plan pl{Ts[ti], Bs[bi], lds};
-        st = run(sets[0], P, pl, scratch, sample_events, s);   // warm-up
-        hipEventRecord(a, s);
-        if (st == ANTS_OK) st = run(sets[0], P, pl, scratch, sample_events, s);
-        hipEventRecord(b, s);
-        hipEventSynchronize(b);
+  // one candidate: descriptors uploaded, a warm-up launch, then the kernel
+  // alone timed between events on the stream
+  auto time_plan = [&](const MPlan& pl, float* ms) -> ants_status {
+    MultiP M;
+    ants_status r = upload(sets[0], P, pl, ch, scratch, s, &M);
+    if (r != ANTS_OK) return r;
+    hipError_t e = launch(P, pl, M, s);
+    if (e == hipSuccess) e = launch(P, pl, M, s, a, b);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    if (e != hipSuccess) return hip_error(e, "ants_autotune_multi");
+    if (host_ms) host_ms[k] = *ms;
+    ++k;
+    return ANTS_OK;
+  };
+  MPlan cur;
+  cur.T.assign(n_sets, 32);
+  cur.lds.assign(n_sets, 1);
+  float best_ms = HUGE_VALF;
+  // stage 1: resident blocks per compute unit
+  const int Bs[3] = {4, 8, 16};
+  int bpc = 8;
+  for (int bi = 0; bi < 3 && st == ANTS_OK; ++bi) {
+    MPlan pl = cur;
+    pl.bpc = Bs[bi];
+    float ms = 0.f;
+    st = time_plan(pl, &ms);
+    if (st == ANTS_OK && ms < best_ms) {
+      best_ms = ms;
+      bpc = Bs[bi];
+    }
+  }
+  cur.bpc = bpc;
+  // stage 2: each set in turn, events per item x table in LDS, the other
+  // sets at their current choice
+  const int Ts[3] = {8, 32, 128};
+  for (int i = 0; i < n_sets && st == ANTS_OK; ++i)
+    for (int lds = 1; lds >= 0 && st == ANTS_OK; --lds)
+      for (int ti = 0; ti < 3 && st == ANTS_OK; ++ti) {
+        MPlan pl = cur;
+        pl.T[i] = Ts[ti];
+        pl.lds[i] = lds;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, a, b);
-        if (host_ms) host_ms[k] = ms;
+        st = time_plan(pl, &ms);
         if (st == ANTS_OK && ms < best_ms) {
           best_ms = ms;
-          *best = pl;
+          cur = pl;
         }
       }
   hipEventDestroy(a);
   hipEventDestroy(b);
-  return st;
+  if (st != ANTS_OK) return st;
+  for (int i = 0; i < n_sets; ++i) {
+    sets[i]->mplan_key = cfg_key(cfgs[i]);
+    sets[i]->mplan_T = cur.T[i];
+    sets[i]->mplan_lds = cur.lds[i];
+    sets[i]->mplan_bpc = cur.bpc;
+  }
+  *best = ants_plan{cur.T[0], cur.bpc, cur.lds[0]};
+  return ANTS_OK;
 }
 
 }  // extern "C"

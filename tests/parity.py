@@ -35,7 +35,11 @@ def compare(ref, gpu, signals, stat=0, three_d=False):
         e_ok = np.abs(gpu["E"] - ref["E"]) <= 1e-5 * np.abs(ref["E"])
     good = pos_ok & l_ok & c_ok & e_ok
     nan_ok = np.isnan(gpu["x"]) & np.isnan(gpu["E"]) & np.isnan(gpu["lnl"])
-    ok &= np.where(bad, nan_ok, good)
+    # no valid point at the end (e.g. a search that never entered the LRF
+    # domain): position as the oracle's, energy and statistics NaN on both
+    none_ok = pos_ok & np.isnan(gpu["E"]) & np.isnan(gpu["lnl"]) & np.isnan(gpu["chi2"])
+    none = ~bad & np.isnan(ref["E"])
+    ok &= np.where(bad, nan_ok, np.where(none, none_ok, good))
     ok &= gpu["ndf"] == ref["ndf"]
     cls = {"tie": 0, "other": 0}
     first_div = np.full(n, -1)

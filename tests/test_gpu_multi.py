@@ -70,9 +70,14 @@ def test_every_plan_gives_identical_results(ants, stream):
     best, ms = ants.autotune_multi(sets, cfgs, chunks, min(total, 20000))
     print("autotuned plan", best.events_per_item, best.blocks_per_cu, best.table_in_lds,
           "ms", np.round(ms, 3).tolist())
-    assert np.all(ms > 0)
+    assert np.all(ms > 0) and len(ms) == 3 + 6 * len(sets)
     got = to_np(ants.reconstruct_multi(sets, cfgs, chunks, total, plan=best))
     np.testing.assert_array_equal(got["x"], ref["x"])
+    # no plan: each set runs its own stored part of the tuned plan
+    for _ in range(2):
+        got = to_np(ants.reconstruct_multi(sets, cfgs, chunks, total))
+        for k in ("x", "y", "z", "E", "lnl", "chi2", "ndf", "status"):
+            np.testing.assert_array_equal(got[k], ref[k])
 
 
 def test_rejects_mixed_kinds(ants, stream):

@@ -212,8 +212,9 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
 /* searched axis, or after max_iter iterations.  Everything is FP64.    */
 /* Outputs as for ants_reconstruct at the best vertex (z = z_start for  */
 /* dims = 2); d_iters [n] (optional, device) receives the iterations    */
-/* run per event.  ANTS_EV_NO_VALID_NODE: the search ended on a point   */
-/* with S <= 0 (outputs NaN).                                           */
+/* run per event and out.n_fp64 (optional) the statistic evaluations    */
+/* (all FP64).  ANTS_EV_NO_VALID_NODE: the search ended on a point with */
+/* S <= 0 (outputs NaN).                                                */
 /* ------------------------------------------------------------------ */
 typedef struct {
   int32_t dims;          /* 2: x, y;  3: x, y, z (r-z LRFs only)             */

@@ -91,7 +91,8 @@ def lib():
         _lib.o_reconstruct_seeded.argtypes = [P(_Lrf), P(_Cfg), P(_Cfg), d, i64, P(d), P(d),
                                               P(d), P(C.c_int), P(C.c_int), C.c_int]
         _lib.o_reconstruct_simplex.argtypes = [P(_Lrf), P(_SCfg), i64, P(d), P(d), P(d),
-                                               P(C.c_int), P(C.c_int), P(C.c_int), C.c_int]
+                                               P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int),
+                                               C.c_int]
         u32 = C.c_uint32
         _lib.o_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
         _lib.o_poisson.restype = d
@@ -346,7 +347,8 @@ def _scfg(g):
 
 def reconstruct_simplex(lrf, scfg, signals, seeds=None, threads=None):
     """Simplex (Nelder-Mead) search per event (FP64).  Returns a dict: x, y,
-    z, E, lnl, chi2, ndf, status and iters (iterations run)."""
+    z, E, lnl, chi2, ndf, status, iters (iterations run) and evals
+    (statistic evaluations)."""
     m = lrf if isinstance(lrf, Model) else Model(lrf)
     sig = np.ascontiguousarray(signals, dtype=np.float64)
     n = sig.shape[0]
@@ -355,6 +357,7 @@ def reconstruct_simplex(lrf, scfg, signals, seeds=None, threads=None):
     ndf = np.empty(n, np.int32)
     status = np.empty(n, np.int32)
     iters = np.empty(n, np.int32)
+    evals = np.empty(n, np.int32)
     sd = None
     if seeds is not None:
         sd = np.ascontiguousarray(seeds, dtype=np.float64)
@@ -362,7 +365,7 @@ def reconstruct_simplex(lrf, scfg, signals, seeds=None, threads=None):
     c = _scfg(scfg)
     lib().o_reconstruct_simplex(C.byref(m.c), C.byref(c), n, _dp(sig),
                                 _dp(sd) if sd is not None else None, _dp(out6), _ip(ndf),
-                                _ip(status), _ip(iters), _threads(threads))
+                                _ip(status), _ip(iters), _ip(evals), _threads(threads))
     return {"x": out6[:, 0], "y": out6[:, 1], "z": out6[:, 2], "E": out6[:, 3],
             "lnl": out6[:, 4], "chi2": out6[:, 5], "ndf": ndf, "status": status,
-            "iters": iters}
+            "iters": iters, "evals": evals}

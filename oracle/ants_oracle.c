@@ -735,11 +735,12 @@ static void o_sx_insert(o_vtx* v, int n, o_vtx w, double tol) {
 }
 
 void o_simplex_event(const o_lrf* L, const o_scfg* S, const double* n, const double* seed,
-                     double out[6], int* ndf, int* status, int* iters) {
+                     double out[6], int* ndf, int* status, int* iters, int* evals) {
   int ns = L->n_sensors, na = 0, bad = 0, d = S->dims;
   double N = 0.0;
   *status = 0;
   *iters = 0;
+  *evals = 0;
   for (int i = 0; i < ns; ++i) {
     if (!L->active[i]) continue;
     ++na;
@@ -785,7 +786,7 @@ void o_simplex_event(const o_lrf* L, const o_scfg* S, const double* n, const dou
     w.f = o_node_eval(L, &C, n, N, w.p[0], w.p[1], w.p[2]).stat;
     o_sx_insert(v, i, w, tf);
   }
-  int it = 0;
+  int it = 0, nev = d + 1;
   for (;;) {
     int conv = 1;
     for (int i = 1; i <= d; ++i)
@@ -806,22 +807,26 @@ void o_simplex_event(const o_lrf* L, const o_scfg* S, const double* n, const dou
     int shrink = 0;
     for (int a = 0; a < 3; ++a) r.p[a] = (a < d) ? c[a] + (c[a] - v[d].p[a]) : c[a];
     r.f = o_node_eval(L, &C, n, N, r.p[0], r.p[1], r.p[2]).stat;
+    ++nev;
     if (!o_lt(r.f, v[0].f, tf) && o_lt(r.f, v[d - 1].f, tf)) {
       acc = r;                                       /* reflection */
     } else if (o_lt(r.f, v[0].f, tf)) {
       o_vtx e;                                       /* expansion */
       for (int a = 0; a < 3; ++a) e.p[a] = (a < d) ? c[a] + 2.0 * (r.p[a] - c[a]) : c[a];
       e.f = o_node_eval(L, &C, n, N, e.p[0], e.p[1], e.p[2]).stat;
+      ++nev;
       acc = o_lt(e.f, r.f, tf) ? e : r;
     } else if (o_lt(r.f, v[d].f, tf)) {
       o_vtx k;                                       /* outside contraction */
       for (int a = 0; a < 3; ++a) k.p[a] = (a < d) ? c[a] + 0.5 * (r.p[a] - c[a]) : c[a];
       k.f = o_node_eval(L, &C, n, N, k.p[0], k.p[1], k.p[2]).stat;
+      ++nev;
       if (!o_lt(r.f, k.f, tf)) acc = k; else shrink = 1;
     } else {
       o_vtx k;                                       /* inside contraction */
       for (int a = 0; a < 3; ++a) k.p[a] = (a < d) ? c[a] + 0.5 * (v[d].p[a] - c[a]) : c[a];
       k.f = o_node_eval(L, &C, n, N, k.p[0], k.p[1], k.p[2]).stat;
+      ++nev;
       if (o_lt(k.f, v[d].f, tf)) acc = k; else shrink = 1;
     }
     if (!shrink) {
@@ -833,12 +838,14 @@ void o_simplex_event(const o_lrf* L, const o_scfg* S, const double* n, const dou
         for (int a = 0; a < 3; ++a)
           w[i].p[a] = (a < d) ? v[0].p[a] + 0.5 * (v[i].p[a] - v[0].p[a]) : v[0].p[a];
         w[i].f = o_node_eval(L, &C, n, N, w[i].p[0], w[i].p[1], w[i].p[2]).stat;
+        ++nev;
       }
       v[0] = w[0];
       for (int i = 1; i <= d; ++i) o_sx_insert(v, i, w[i], tf);
     }
   }
   *iters = it;
+  *evals = nev;
   o_node fin = o_node_eval(L, &C, n, N, v[0].p[0], v[0].p[1], v[0].p[2]);
   out[0] = v[0].p[0]; out[1] = v[0].p[1]; out[2] = v[0].p[2];
   out[3] = fin.A; out[4] = fin.lnl; out[5] = fin.chi2;
@@ -847,9 +854,9 @@ void o_simplex_event(const o_lrf* L, const o_scfg* S, const double* n, const dou
 
 void o_reconstruct_simplex(const o_lrf* L, const o_scfg* S, int64_t n_ev, const double* sig,
                            const double* seeds, double* out6, int* ndf, int* status, int* iters,
-                           int n_threads) {
+                           int* evals, int n_threads) {
 #pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
   for (int64_t e = 0; e < n_ev; ++e)
     o_simplex_event(L, S, sig + e * L->n_sensors, seeds ? seeds + 4 * e : NULL, out6 + 6 * e,
-                    ndf + e, status + e, iters + e);
+                    ndf + e, status + e, iters + e, evals + e);
 }

@@ -322,16 +322,17 @@ def simplex_cfg(g) -> SimplexCfg:
 
 
 def reconstruct_simplex(lrfset: LrfSet, cfg: SimplexCfg, signals, seeds=None, out=None,
-                        stream=None, iters=True):
+                        stream=None, iters=True, n_eval=False):
     """Simplex search per event (ants_reconstruct_simplex).  Returns the
     dict of output tensors, with "iters" (iterations per event) when
-    iters=True (asynchronous)."""
+    iters=True and "n_fp64" (statistic evaluations) when n_eval=True
+    (asynchronous)."""
     import torch
     assert signals.dtype == torch.float32 and signals.is_cuda and signals.is_contiguous()
     n = signals.shape[0]
     assert signals.dim() == 2 and signals.shape[1] == lrfset.n_sensors, signals.shape
     if out is None:
-        out = alloc_out(n, 0, signals.device)
+        out = alloc_out(n, 0, signals.device, n_fp64=n_eval)
     if iters and "iters" not in out:
         out["iters"] = torch.empty(n, dtype=torch.int32, device=signals.device)
     sp = None

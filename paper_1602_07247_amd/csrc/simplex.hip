@@ -144,6 +144,7 @@ __device__ void sx_event(const SxP& P, int64_t e, int lane) {
       io.x[e] = nan; io.y[e] = nan; io.z[e] = nan; io.E[e] = nan;
       io.lnl[e] = nan; io.chi2[e] = nan; io.ndf[e] = ndf; io.status[e] = status;
       if (P.iters) P.iters[e] = 0;
+      if (io.nfp) io.nfp[e] = 0;
     }
     return;
   }
@@ -187,7 +188,7 @@ __device__ void sx_event(const SxP& P, int64_t e, int lane) {
     sx_insert<2>(v, w[2], tf);
     if constexpr (d == 3) sx_insert<3>(v, w[3], tf);
   }
-  int it = 0;
+  int it = 0, nev = d + 1;
   for (;;) {
     bool conv = true;
 #pragma unroll
@@ -216,6 +217,7 @@ __device__ void sx_event(const SxP& P, int64_t e, int lane) {
     const Vtx& wv = v[d];
     Vtx r{cx + (cx - wv.x), cy + (cy - wv.y), d == 3 ? cz + (cz - wv.z) : cz, 0.0};
     r.f = sx_eval<KIND, STAT, SL>(P, nq, N, r.x, r.y, r.z, lane);
+    ++nev;
     Vtx acc = r;
     bool shrink = false;
     if (!lt(r.f, v[0].f, tf) && lt(r.f, v[d - 1].f, tf)) {
@@ -224,17 +226,20 @@ __device__ void sx_event(const SxP& P, int64_t e, int lane) {
       Vtx x{cx + 2.0 * (r.x - cx), cy + 2.0 * (r.y - cy), d == 3 ? cz + 2.0 * (r.z - cz) : cz,
             0.0};                                         // expansion
       x.f = sx_eval<KIND, STAT, SL>(P, nq, N, x.x, x.y, x.z, lane);
+      ++nev;
       acc = lt(x.f, r.f, tf) ? x : r;
     } else if (lt(r.f, wv.f, tf)) {
       Vtx k{cx + 0.5 * (r.x - cx), cy + 0.5 * (r.y - cy), d == 3 ? cz + 0.5 * (r.z - cz) : cz,
             0.0};                                         // outside contraction
       k.f = sx_eval<KIND, STAT, SL>(P, nq, N, k.x, k.y, k.z, lane);
+      ++nev;
       if (!lt(r.f, k.f, tf)) acc = k;
       else shrink = true;
     } else {
       Vtx k{cx + 0.5 * (wv.x - cx), cy + 0.5 * (wv.y - cy),
             d == 3 ? cz + 0.5 * (wv.z - cz) : cz, 0.0};  // inside contraction
       k.f = sx_eval<KIND, STAT, SL>(P, nq, N, k.x, k.y, k.z, lane);
+      ++nev;
       if (lt(k.f, wv.f, tf)) acc = k;
       else shrink = true;
     }
@@ -249,6 +254,7 @@ __device__ void sx_event(const SxP& P, int64_t e, int lane) {
         w[i].z = d == 3 ? v[0].z + 0.5 * (v[i].z - v[0].z) : v[0].z;
         w[i].f = sx_eval<KIND, STAT, SL>(P, nq, N, w[i].x, w[i].y, w[i].z, lane);
       }
+      nev += d;
       // the best vertex stays first; the others re-enter in order
       sx_insert<1>(v, w[1], tf);
       sx_insert<2>(v, w[2], tf);
@@ -299,6 +305,7 @@ __device__ void sx_event(const SxP& P, int64_t e, int lane) {
     io.ndf[e] = ndf;
     io.status[e] = status;
     if (P.iters) P.iters[e] = it;
+    if (io.nfp) io.nfp[e] = nev;
   }
 }
 
@@ -396,6 +403,7 @@ extern "C" ants_status ants_reconstruct_simplex(ants_lrfset* set, const ants_sim
   P.io.chi2 = out.chi2;
   P.io.ndf = out.ndf;
   P.io.status = out.status;
+  P.io.nfp = out.n_fp64;
   P.io.n = n_events;
   P.iters = d_iters;
   int64_t blocks = (n_events + 3) / 4;

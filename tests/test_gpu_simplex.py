@@ -1,7 +1,7 @@
 """GPU parity of the simplex search (Sec. 5.1.2.1; Nelder-Mead, FP64)
 against the FP64 oracle: 99.9% of events with every coordinate within
 1e-3 mm and lnL / chi2 within 1e-5 of their scale, equal status and ndf,
-and the same iteration count.  Calls go through the C ABI."""
+and the same iteration and evaluation counts.  Calls go through the C ABI."""
 import numpy as np
 import pytest
 
@@ -29,7 +29,7 @@ def _run(ants, lrf, sc, sig, seeds=None):
     d = torch.from_numpy(np.ascontiguousarray(sig, np.float32)).cuda()
     s = torch.from_numpy(np.ascontiguousarray(seeds, np.float32)).cuda() if seeds is not None \
         else None
-    out = ants.reconstruct_simplex(L, ants.simplex_cfg(sc), d, seeds=s)
+    out = ants.reconstruct_simplex(L, ants.simplex_cfg(sc), d, seeds=s, n_eval=True)
     torch.cuda.synchronize()
     return to_np(out)
 
@@ -53,7 +53,7 @@ def test_simplex_matches_oracle(ants, k, n, dims, stat, start, step0, z0):
     ref = oracle.reconstruct_simplex(wl.lrf, sc, sig)
     gpu = _run(ants, wl.lrf, sc, sig)
     res = compare(ref, gpu, sig, stat, three_d=dims == 3)
-    same_it = gpu["iters"] == ref["iters"]
+    same_it = (gpu["iters"] == ref["iters"]) & (gpu["n_fp64"] == ref["evals"])
     print(summary(res), "| iterations equal", same_it.mean(), "mean", ref["iters"].mean())
     assert res["frac"] >= 0.999, summary(res)
     assert (same_it | ~res["ok"]).mean() >= 0.999
@@ -80,7 +80,7 @@ def test_simplex_from_seeds_ragged_and_statuses(ants):
     assert res["ok"].all(), summary(res)
     for n in (1, 63, 65, 200):
         part = _run(ants, wl.lrf, sc, sig[:n], seeds[:n])
-        for key in ("x", "y", "z", "E", "lnl", "chi2", "ndf", "status", "iters"):
+        for key in ("x", "y", "z", "E", "lnl", "chi2", "ndf", "status", "iters", "n_fp64"):
             np.testing.assert_array_equal(part[key], gpu[key][:n], err_msg=key)
 
 
@@ -90,6 +90,7 @@ def test_simplex_flat_likelihood_and_zero_iterations(ants):
     sc = W.SimplexCfg(step0=(7.5, 7.5, 0.0), tol=1e-3)
     gpu = _run(ants, lrf, sc, sig)
     assert (gpu["x"] == 3.0).all() and (gpu["y"] == -2.0).all() and (gpu["iters"] == 13).all()
+    assert (gpu["n_fp64"] == 3 + 4 * 13).all()
     wl = W.workload(0)
     sig, _ = oracle.make_events(wl.lrf, wl.events, 50, W.streams(6200))
     sc0 = W.SimplexCfg(max_iter=0)

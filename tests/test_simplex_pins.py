@@ -155,7 +155,9 @@ def test_flat_likelihood_shrinks_onto_the_start():
     sc = W.SimplexCfg(step0=(7.5, 7.5, 0.0), tol=1e-3)
     r = oracle.reconstruct_simplex(lrf, sc, np.array([[57.0]]))
     assert r["x"][0] == 3.0 and r["y"][0] == -2.0
-    assert r["iters"][0] == math.ceil(math.log2(7.5 / 1e-3))
+    k = math.ceil(math.log2(7.5 / 1e-3))
+    # each iteration: reflection, inside contraction, shrink of two vertices
+    assert r["iters"][0] == k and r["evals"][0] == 3 + 4 * k
     assert r["lnl"][0] == pytest.approx(57 * math.log(57) - 57, rel=1e-13)
 
 

@@ -90,6 +90,10 @@ def lib():
         _lib.o_crb.argtypes = [P(_Lrf), C.c_int, i64, P(d), P(d), P(d)]
         _lib.o_reconstruct_seeded.argtypes = [P(_Lrf), P(_Cfg), P(_Cfg), d, i64, P(d), P(d),
                                               P(d), P(C.c_int), P(C.c_int), C.c_int]
+        _lib.o_knn_prepare.argtypes = [P(_Lrf), i64, P(d), P(C.c_float), P(C.c_uint8), C.c_int]
+        _lib.o_knn_reconstruct.argtypes = [P(_Lrf), i64, P(C.c_float), P(C.c_uint8), P(d),
+                                           C.c_int, i64, P(d), P(d), P(C.c_int), P(i64),
+                                           P(C.c_float), C.c_int]
         _lib.o_reconstruct_simplex.argtypes = [P(_Lrf), P(_SCfg), i64, P(d), P(d), P(d),
                                                P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int),
                                                C.c_int]
@@ -369,3 +373,41 @@ def reconstruct_simplex(lrf, scfg, signals, seeds=None, threads=None):
     return {"x": out6[:, 0], "y": out6[:, 1], "z": out6[:, 2], "E": out6[:, 3],
             "lnl": out6[:, 4], "chi2": out6[:, 5], "ndf": ndf, "status": status,
             "iters": iters, "evals": evals}
+
+
+class KnnCal:
+    """Calibration set of the k-NN reconstruction: normalised signals of the
+    active sensors (single precision, as defined in the oracle) and the
+    known positions."""
+
+    def __init__(self, lrf, signals, positions, threads=None):
+        self.m = lrf if isinstance(lrf, Model) else Model(lrf)
+        sig = np.ascontiguousarray(signals, dtype=np.float64)
+        self.n = sig.shape[0]
+        self.na = int(np.count_nonzero(self.m.active))
+        self.cal = np.empty((self.n, max(self.na, 1)), np.float32)
+        self.valid = np.empty(self.n, np.uint8)
+        self.pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(self.n, 3)
+        lib().o_knn_prepare(C.byref(self.m.c), self.n, _dp(sig),
+                            self.cal.ctypes.data_as(C.POINTER(C.c_float)),
+                            self.valid.ctypes.data_as(C.POINTER(C.c_uint8)), _threads(threads))
+
+
+def knn_reconstruct(cal, k, signals, threads=None):
+    """k-NN positions of events (Sec. 5.1.4).  Returns a dict: x, y, z,
+    status, idx [n][k] (neighbours in order, -1 past the valid ones) and
+    dist [n][k] (their single-precision squared distances)."""
+    sig = np.ascontiguousarray(signals, dtype=np.float64)
+    n = sig.shape[0]
+    out3 = np.empty((n, 3), np.float64)
+    status = np.empty(n, np.int32)
+    idx = np.empty((n, k), np.int64)
+    dist = np.empty((n, k), np.float32)
+    lib().o_knn_reconstruct(C.byref(cal.m.c), cal.n,
+                            cal.cal.ctypes.data_as(C.POINTER(C.c_float)),
+                            cal.valid.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(cal.pos), int(k),
+                            n, _dp(sig), _dp(out3), _ip(status),
+                            idx.ctypes.data_as(C.POINTER(C.c_int64)),
+                            dist.ctypes.data_as(C.POINTER(C.c_float)), _threads(threads))
+    return {"x": out3[:, 0], "y": out3[:, 1], "z": out3[:, 2], "status": status, "idx": idx,
+            "dist": dist}

@@ -860,3 +860,117 @@ void o_reconstruct_simplex(const o_lrf* L, const o_scfg* S, int64_t n_ev, const 
     o_simplex_event(L, S, sig + e * L->n_sensors, seeds ? seeds + 4 * e : NULL, out6 + 6 * e,
                     ndf + e, status + e, iters + e, evals + e);
 }
+
+/* ------------------------------------------------------------------ */
+/* k-NN reconstruction (Sec. 5.1.4): each event is a point whose        */
+/* coordinates are the normalised signals of the sensors; the position  */
+/* is the centroid of the known positions of the k calibration events   */
+/* closest to it.  Readings:                                            */
+/*  - normalised signal of active sensor i: n_i / N, N = sum over the    */
+/*    active sensors (in sensor order), divided in double precision and */
+/*    rounded to single precision;                                      */
+/*  - distance: squared Euclidean over the active sensors, accumulated  */
+/*    in sensor order in single precision with each subtraction,        */
+/*    square and sum rounded as written.  The distance decides which    */
+/*    events are neighbours (an integer result), so it is defined in    */
+/*    the precision the GPU kernel computes it in;                      */
+/*  - order: (distance, calibration index), the lower index first on    */
+/*    equal distances; the k first are the neighbours;                  */
+/*  - calibration events with N <= 0 or a non-finite or negative active */
+/*    signal never become neighbours; a query with such signals gets    */
+/*    NaN and the grid's status bits;                                   */
+/*  - position: the mean of the k (or fewer, if fewer calibration       */
+/*    events are valid) neighbours' positions, summed in double in      */
+/*    neighbour order.                                                  */
+/* ------------------------------------------------------------------ */
+
+/* normalised signals of one event: q[na]; returns the status bits */
+static int o_knn_norm(const o_lrf* L, const double* n, float* q) {
+  int na = 0, bad = 0;
+  double N = 0.0;
+  for (int i = 0; i < L->n_sensors; ++i) {
+    if (!L->active[i]) continue;
+    ++na;
+    if (!isfinite(n[i]) || n[i] < 0.0) bad = 1;
+    else N += n[i];
+  }
+  if (na == 0) return O_NO_ACTIVE;
+  if (bad) return O_BAD_INPUT;
+  if (!(N > 0.0)) return O_EMPTY;
+  int a = 0;
+  for (int i = 0; i < L->n_sensors; ++i)
+    if (L->active[i]) q[a++] = (float)(n[i] / N);
+  return 0;
+}
+
+static float o_knn_dist(const float* q, const float* c, int na) {
+  float s = 0.0f;
+  for (int a = 0; a < na; ++a) {
+    float d = q[a] - c[a];
+    float d2 = d * d;
+    s = s + d2;
+  }
+  return s;
+}
+
+typedef struct { float d; int64_t i; } o_nb;
+
+static int o_nb_cmp(const void* A, const void* B) {
+  const o_nb* a = (const o_nb*)A;
+  const o_nb* b = (const o_nb*)B;
+  if (a->d < b->d) return -1;
+  if (a->d > b->d) return 1;
+  return (a->i > b->i) - (a->i < b->i);
+}
+
+/* Normalised calibration points [m][na] (rows of invalid events are
+ * flagged in valid[]). */
+void o_knn_prepare(const o_lrf* L, int64_t m, const double* sig, float* cal, uint8_t* valid,
+                   int n_threads) {
+  int na = 0;
+  for (int i = 0; i < L->n_sensors; ++i) na += L->active[i] != 0;
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+  for (int64_t c = 0; c < m; ++c)
+    valid[c] = o_knn_norm(L, sig + c * L->n_sensors, cal + c * na) == 0;
+}
+
+/* Queries: out3 [n][3] positions, status [n], nb_idx / nb_dist [n][k] the
+ * neighbours in order (-1 / +inf past the valid ones). */
+void o_knn_reconstruct(const o_lrf* L, int64_t m, const float* cal, const uint8_t* valid,
+                       const double* cal_pos /* [m][3] */, int k, int64_t n, const double* sig,
+                       double* out3, int* status, int64_t* nb_idx, float* nb_dist,
+                       int n_threads) {
+  int na = 0;
+  for (int i = 0; i < L->n_sensors; ++i) na += L->active[i] != 0;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(n_threads)
+  for (int64_t e = 0; e < n; ++e) {
+    float* q = (float*)malloc(sizeof(float) * (size_t)(na > 0 ? na : 1));
+    o_nb* all = (o_nb*)malloc(sizeof(o_nb) * (size_t)(m > 0 ? m : 1));
+    for (int a = 0; a < 3; ++a) out3[3 * e + a] = NAN;
+    for (int j = 0; j < k; ++j) { nb_idx[e * k + j] = -1; nb_dist[e * k + j] = INFINITY; }
+    status[e] = o_knn_norm(L, sig + e * L->n_sensors, q);
+    if (status[e] == 0) {
+      int64_t cnt = 0;
+      for (int64_t c = 0; c < m; ++c) {
+        if (!valid[c]) continue;
+        all[cnt].d = o_knn_dist(q, cal + c * na, na);
+        all[cnt].i = c;
+        ++cnt;
+      }
+      qsort(all, (size_t)cnt, sizeof(o_nb), o_nb_cmp);
+      int kk = cnt < k ? (int)cnt : k;
+      double s[3] = {0.0, 0.0, 0.0};
+      for (int j = 0; j < kk; ++j) {
+        nb_idx[e * k + j] = all[j].i;
+        nb_dist[e * k + j] = all[j].d;
+        for (int a = 0; a < 3; ++a) s[a] += cal_pos[3 * all[j].i + a];
+      }
+      if (kk > 0)
+        for (int a = 0; a < 3; ++a) out3[3 * e + a] = s[a] / (double)kk;
+      else
+        status[e] = O_NO_VALID_NODE;
+    }
+    free(q);
+    free(all);
+  }
+}

@@ -63,12 +63,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=160207247)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="rz", choices=["rz", "mixed", "lrf_fit", "simplex"],
+    ap.add_argument("--workload", default="rz",
+                    choices=["rz", "mixed", "lrf_fit", "simplex", "knn"],
                     help="rz: the headline comparison; mixed: 19/61/127-sensor stream in one "
                          "persistent launch; lrf_fit: one step of the iterative LRF "
                          "reconstruction (reconstruct + refit) on the 61-sensor detector; "
                          "simplex: the simplex search against the plain grid on the r-z "
-                         "events")
+                         "events; knn: k-NN reconstruction of r-z events against a "
+                         "calibration set")
     return ap.parse_args()
 
 
@@ -285,6 +287,81 @@ def simplex_vs_grid(args):
     print(json.dumps(rec), flush=True)
 
 
+def knn_step(args):
+    """k-NN reconstruction (Sec. 5.1.4) of hex37 r-z events: a calibration
+    set of 200k events with known positions (drawn by the generator, like a
+    flood-field calibration run), 1M query events, k = 16; exact brute force
+    in single precision.  Beside it, the plain 7x7x7 grid on the same
+    queries (sigma_xy of both)."""
+    import torch
+    import workloads as W
+    from paper_1602_07247_amd import ants
+    wl = W.workload(2)
+    n = args.events if args.events != 10_000_000 else 1_000_000
+    m, k = 200_000, 16
+    stream = torch.cuda.current_stream()
+    lrf = ants.LrfSet(wl.lrf)
+    cal_sig, cal_truth = ants.generate(lrf, ants.gen_cfg(wl.events), m, args.seed + 17)
+    sig, truth = ants.generate(lrf, ants.gen_cfg(wl.events), n, args.seed)
+    knn = ants.Knn(lrf, cal_sig, cal_truth[:, :3].contiguous(), stream=stream)
+    torch.cuda.synchronize()
+    holder = {}
+
+    def step():
+        holder["o"] = knn.reconstruct(k, sig, stream=stream)
+
+    wall, ev = timed(step, args.steps, args.warmup, stream)
+    o = holder["o"]
+    out_k = {"x": o["xyz"][:, 0], "y": o["xyz"][:, 1]}
+    sk = sigma_xy(out_k, truth)
+    out_p = ants.reconstruct(lrf, ants.grid_cfg(wl.grid), sig, stream=stream)
+    torch.cuda.synchronize()
+    sp = sigma_xy(out_p, truth)
+    pairs = n * m
+    na = lrf.n_active
+    flops = pairs * na * 3          # subtract, square, add per sensor
+    achieved = flops / (ev * 1e-3) / 1e12
+    rec = {"metric": "events/s reconstructed by k-NN (k=16, 200k calibration events), hex37 "
+                     "r-z, 1 MI355X",
+           "value": n / wall, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * wall, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (flood-field events drawn on the GPU from the LRF model)",
+           "config": {"workload": "hex37 r-z LRF, %d queries, %d calibration events, k=%d, "
+                                  "exact brute force" % (n, m, k), "events": n},
+           "knn": {"sigma_xy_mm": sk[0], "sigma_xy_fiducial_mm": sk[1], "p95_radial_mm": sk[2],
+                   "pairs_per_s": pairs / (ev * 1e-3)},
+           "plain": {"sigma_xy_mm": sp[0], "sigma_xy_fiducial_mm": sp[1], "p95_radial_mm": sp[2]},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                        "kernel": "knn_kernel<NAP=40,KMAX=16>", "kernel_ms": ev,
+                        "flop_per_launch": flops, "flop_per_pair_and_sensor": 3}}
+    if args.cpu_sample > 0:
+        import oracle
+        q = max(1, min(n, args.cpu_sample // 100))
+        threads = host_threads()
+        oracle.build()
+        cal = oracle.KnnCal(wl.lrf, cal_sig.cpu().numpy(),
+                            cal_truth[:, :3].cpu().numpy().astype(np.float64), threads=threads)
+        sig_host = sig[:q].cpu().numpy()
+        t0 = time.perf_counter()
+        ref = oracle.knn_reconstruct(cal, k, sig_host, threads=threads)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": q / dt, "unit": "events/s", "cores": threads,
+                               "kind": "oracle", "host_cpu": host_cpu_model(),
+                               "sample": f"first {q} queries against the {m} calibration events, "
+                                         f"FP32 distances, C oracle ({oracle.BUILD_FLAGS}), "
+                                         f"{threads} threads, {dt:.1f} s"}
+        g = knn.reconstruct(k, sig[:q].contiguous(), neighbours=True, stream=stream)
+        torch.cuda.synchronize()
+        same_idx = (g["idx"].cpu().numpy() == ref["idx"]).all(1)
+        same_pos = np.abs(g["xyz"].cpu().numpy() - np.stack([ref["x"], ref["y"], ref["z"]], 1)
+                          ).max(1) <= 1e-4
+        rec["parity"] = {"knn": {"events": q, "match_frac": float((same_idx & same_pos).mean()),
+                                 "neighbour_sets_equal": float(same_idx.mean())}}
+    print(json.dumps(rec), flush=True)
+
+
 def copy_probe():
     import torch
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
@@ -469,6 +546,9 @@ def main():
         return
     if args.workload == "simplex":
         simplex_vs_grid(args)
+        return
+    if args.workload == "knn":
+        knn_step(args)
         return
     import torch
     import workloads as W

@@ -233,6 +233,38 @@ ants_status ants_reconstruct_simplex(ants_lrfset* set, const ants_simplex_cfg* c
                                      void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* k-NN reconstruction (Sec. 5.1.4): an event is the point of its       */
+/* normalised active-sensor signals n_i / N (N = sum over the active    */
+/* sensors; divided in double, rounded to single precision); its        */
+/* position is the mean of the known positions of the k calibration    */
+/* events closest to it.  Distance: squared Euclidean over the active   */
+/* sensors in single precision, accumulated in sensor order with every  */
+/* operation rounded as written (it decides an integer result, so it is */
+/* exactly reproducible); neighbours ordered by (distance, calibration  */
+/* index).  Exact brute force over the whole calibration set.           */
+/* ------------------------------------------------------------------ */
+typedef struct ants_knn ants_knn;   /* opaque; owns the normalised calibration set */
+
+/* Calibration set of n_cal events of `set`'s detector (at most 128 active
+ * sensors): d_signals [n_cal][n_sensors] and d_pos [n_cal][3] (x, y, z)
+ * FP32 device arrays, copied and normalised on `hip_stream` (usable on
+ * that stream right away; the caller's arrays may be freed once the
+ * stream has passed this call).  Calibration events with N <= 0 or a
+ * non-finite or negative active signal never become neighbours. */
+ants_status ants_knn_create(ants_lrfset* set, int64_t n_cal, const float* d_signals,
+                            const float* d_pos, ants_knn** out, void* hip_stream);
+ants_status ants_knn_destroy(ants_knn* knn);   /* NULL is a no-op */
+/* k in 1..32.  d_xyz [n][3] FP32 positions (the mean of the neighbours'
+ * positions in double), d_status [n] the grid's input status bits
+ * (EMPTY, BAD_INPUT, NO_ACTIVE; NO_VALID_NODE when no calibration event is
+ * valid), NaN positions for those events.  Optional d_idx [n][k] int32 and
+ * d_dist [n][k] FP32: the neighbours in order (-1 / +inf past the valid
+ * calibration events). */
+ants_status ants_knn_reconstruct(ants_knn* knn, int32_t k, int64_t n_events,
+                                 const float* d_signals, float* d_xyz, int32_t* d_status,
+                                 int32_t* d_idx, float* d_dist, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* One persistent launch over event chunks from several detectors (one  */
 /* LRF set and grid configuration per detector; every set must have the */
 /* same LRF kind and the same statistic).  Chunk c holds n_events rows   */

@@ -141,6 +141,10 @@ _lib.ants_autotune_multi.argtypes = [C.POINTER(_vp), C.POINTER(GridCfg), C.c_int
 _lib.ants_reconstruct_simplex.argtypes = [_vp, C.POINTER(SimplexCfg), C.c_int64, _vp, _vp, Out,
                                           _vp, _vp]
 
+_lib.ants_knn_create.argtypes = [_vp, C.c_int64, _vp, _vp, C.POINTER(_vp), _vp]
+_lib.ants_knn_destroy.argtypes = [_vp]
+_lib.ants_knn_reconstruct.argtypes = [_vp, C.c_int32, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
+
 _lib.ants_fit_axial_lrf.argtypes = [_vp, C.POINTER(FitCfg), C.c_int64, _vp, C.c_int64, Out, _vp,
                                     _vp, _vp]
 
@@ -152,7 +156,8 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_reconstruct_seeded_noalloc",
             "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf",
             "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load",
-            "ants_reconstruct_simplex")
+            "ants_reconstruct_simplex", "ants_knn_create", "ants_knn_destroy",
+            "ants_knn_reconstruct")
 
 
 def _check(code):
@@ -344,6 +349,53 @@ def reconstruct_simplex(lrfset: LrfSet, cfg: SimplexCfg, signals, seeds=None, ou
     _check(_lib.ants_reconstruct_simplex(lrfset.handle, C.byref(cfg), n, signals.data_ptr(), sp,
                                          _out_struct(out), it, _stream_handle(stream)))
     return out
+
+
+class Knn:
+    """k-NN calibration set (ants_knn_create): signals [m][n_sensors] and
+    positions [m][3], FP32 device tensors of `lrfset`'s detector."""
+
+    def __init__(self, lrfset: LrfSet, signals, positions, stream=None):
+        import torch
+        assert signals.dtype == torch.float32 and signals.is_cuda and signals.is_contiguous()
+        assert signals.shape[1] == lrfset.n_sensors
+        pos = positions.to(torch.float32).contiguous()
+        assert pos.shape == (signals.shape[0], 3) and pos.is_cuda
+        self._h = _vp()
+        self.m = signals.shape[0]
+        _check(_lib.ants_knn_create(lrfset.handle, self.m, signals.data_ptr(), pos.data_ptr(),
+                                    C.byref(self._h), _stream_handle(stream)))
+        self._keep = (signals, pos)   # until the stream has copied them
+
+    def reconstruct(self, k, signals, neighbours=False, stream=None):
+        """Positions [n][3] and status [n] (and idx, dist [n][k] when
+        neighbours=True) as device tensors (asynchronous)."""
+        import torch
+        assert signals.dtype == torch.float32 and signals.is_cuda and signals.is_contiguous()
+        n = signals.shape[0]
+        dev = signals.device
+        out = {"xyz": torch.empty((n, 3), dtype=torch.float32, device=dev),
+               "status": torch.empty(n, dtype=torch.int32, device=dev)}
+        if neighbours:
+            out["idx"] = torch.empty((n, k), dtype=torch.int32, device=dev)
+            out["dist"] = torch.empty((n, k), dtype=torch.float32, device=dev)
+        _check(_lib.ants_knn_reconstruct(self._h, int(k), n, signals.data_ptr(),
+                                         out["xyz"].data_ptr(), out["status"].data_ptr(),
+                                         out["idx"].data_ptr() if neighbours else None,
+                                         out["dist"].data_ptr() if neighbours else None,
+                                         _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.ants_knn_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gen_cfg(recipe, noiseless=False) -> GenCfg:

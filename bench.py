@@ -45,6 +45,12 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed), published
 FLOP_PER_EVAL_AXIAL_ML = 20
 FLOP_PER_EVAL_RZ_ML = 80
 IMPL_FLOP_PER_EVAL_RZ_ML = 20
+# XY bicubic, ML: interval location in x and y 2 x 6, cubic B-spline
+# weights 2 x 12 (done once per node, counted per evaluation as the oracle
+# evaluates them), 4 x 4 contraction 32, clamp 1, S 2, log and n*log 3 = 75;
+# chi2 replaces the log and its FMA by the Pearson term (about 6 more)
+FLOP_PER_EVAL_XY_ML = 75
+FLOP_PER_EVAL_XY_CHI2 = 78
 
 
 def parse():
@@ -64,13 +70,14 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="rz",
-                    choices=["rz", "mixed", "lrf_fit", "simplex", "knn"],
+                    choices=["rz", "mixed", "lrf_fit", "simplex", "knn", "xy"],
                     help="rz: the headline comparison; mixed: 19/61/127-sensor stream in one "
                          "persistent launch; lrf_fit: one step of the iterative LRF "
                          "reconstruction (reconstruct + refit) on the 61-sensor detector; "
                          "simplex: the simplex search against the plain grid on the r-z "
                          "events; knn: k-NN reconstruction of r-z events against a "
-                         "calibration set")
+                         "calibration set; xy: the 8x8 array with per-sensor bicubic "
+                         "LRFs, ML and chi2")
     return ap.parse_args()
 
 
@@ -362,6 +369,45 @@ def knn_step(args):
     print(json.dumps(rec), flush=True)
 
 
+def xy_step(args):
+    """The 8 x 8 square array (pitch 6 mm) with per-sensor bicubic XY LRFs
+    (34 x 34 coefficients each, 296 KB in FP32) and gains U[0.8, 1.2]: 1M
+    flood-field events, 9 x 9 grid x 6 iterations, ML and chi2."""
+    import torch
+    import workloads as W
+    from paper_1602_07247_amd import ants
+    wl = W.workload(1)
+    n = args.events if args.events != 10_000_000 else 1_000_000
+    stream = torch.cuda.current_stream()
+    lrf = ants.LrfSet(wl.lrf)
+    sig, truth = ants.generate(lrf, ants.gen_cfg(wl.events), n, args.seed)
+    evals = int(np.prod(wl.grid.nodes)) * 64 * wl.grid.iterations
+    res = {}
+    for stat, name, fpe in ((0, "ml", FLOP_PER_EVAL_XY_ML), (1, "chi2", FLOP_PER_EVAL_XY_CHI2)):
+        g = ants.grid_cfg(W.GridCfg(**{**wl.grid.__dict__, "stat": stat}))
+        out = ants.alloc_out(n)
+        wall, ev = timed(lambda: ants.reconstruct(lrf, g, sig, out=out, stream=stream),
+                         args.steps, args.warmup, stream)
+        sx = sigma_xy(out, truth)
+        flops = n * evals * fpe
+        ach = flops / (ev * 1e-3) / 1e12
+        res[name] = {"events_per_s": n / wall, "ms_per_step": 1e3 * wall, "sigma_xy_mm": sx[0],
+                     "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                                  "traffic": None, "kernel_ms": ev, "flop_per_launch": flops,
+                                  "flop_per_eval": fpe,
+                                  "kernel": "cg_kernel<XY,%s,NT=2,SL=1>" % name.upper()}}
+    rec = {"metric": "events/s reconstructed, 8x8 array with per-sensor bicubic LRFs, 1 MI355X",
+           "value": res["ml"]["events_per_s"], "unit": "events/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ml"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic (flood-field events drawn on the GPU from the LRF model)",
+           "config": {"workload": "square64 XY LRFs 34x34 per sensor, %d events, 9x9 grid x 6, "
+                                  "step0 1.5 mm" % n, "events": n},
+           "ml": res["ml"], "chi2": res["chi2"], "roofline": res["ml"]["roofline"]}
+    print(json.dumps(rec), flush=True)
+
+
 def copy_probe():
     import torch
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
@@ -549,6 +595,9 @@ def main():
         return
     if args.workload == "knn":
         knn_step(args)
+        return
+    if args.workload == "xy":
+        xy_step(args)
         return
     import torch
     import workloads as W

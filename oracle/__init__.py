@@ -44,7 +44,10 @@ class _Lrf(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_sensors", C.c_int), ("sxy", C.POINTER(C.c_double)),
                 ("gain", C.POINTER(C.c_double)), ("active", C.POINTER(C.c_uint8)),
                 ("shared", C.c_int), ("nb", C.c_int * 2), ("lo", C.c_double * 2),
-                ("hi", C.c_double * 2), ("coef", C.POINTER(C.c_double))]
+                ("hi", C.c_double * 2), ("coef", C.POINTER(C.c_double)),
+                ("xy_nb", C.c_int * 2), ("xy_lo", C.c_double * 2), ("xy_hi", C.c_double * 2),
+                ("xy_coef", C.POINTER(C.c_double)), ("xy_shared", C.c_int),
+                ("n_planes", C.c_int), ("z_lo", C.c_double), ("z_hi", C.c_double)]
 
 
 class _Cfg(C.Structure):
@@ -138,6 +141,18 @@ class Model:
         self.c.hi[0], self.c.hi[1] = lrf.hi
         self.c.coef = _dp(self.coef)
         self.n_sensors = self.sxy.shape[0]
+        # composite: XY residual; sliced: z planes (see workloads.LRFSet)
+        xc = getattr(lrf, "xy_coef", None)
+        if xc is not None:
+            self.xy_coef = np.ascontiguousarray(xc, dtype=np.float64)
+            self.c.xy_coef = _dp(self.xy_coef)
+            self.c.xy_nb[0], self.c.xy_nb[1] = lrf.xy_nb
+            self.c.xy_lo[0], self.c.xy_lo[1] = lrf.xy_lo
+            self.c.xy_hi[0], self.c.xy_hi[1] = lrf.xy_hi
+            self.c.xy_shared = int(lrf.xy_shared)
+        self.c.n_planes = int(getattr(lrf, "n_planes", 0))
+        self.c.z_lo = float(getattr(lrf, "z_lo", 0.0))
+        self.c.z_hi = float(getattr(lrf, "z_hi", 0.0))
 
 
 def _cfg(g):

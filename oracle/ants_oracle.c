@@ -39,6 +39,8 @@
 #define O_AXIAL 1
 #define O_XY 2
 #define O_RZ 3
+#define O_COMPOSITE 4
+#define O_SLICED 5
 
 typedef struct {
   int kind;             /* 1 axial (r), 2 XY (x,y), 3 r-z (r,z)          */
@@ -49,7 +51,18 @@ typedef struct {
   int shared;           /* 1: one coefficient table for all sensors       */
   int nb[2];            /* breakpoints per axis, both ends included       */
   double lo[2], hi[2];  /* spline domain per axis                         */
-  const double* coef;   /* [n_lrf][nb[1]+2][nb[0]+2] (axis 1 unused = 1 row) */
+  const double* coef;   /* [n_lrf][nb[1]+2][nb[0]+2] (axis 1 unused = 1 row);
+                           sliced: [n_lrf][n_planes][nb[1]+2][nb[0]+2]     */
+  /* composite (kind 4, Sec. 6.1.1): the fields above hold the axial part
+   * (one table shared by all sensors), these the XY residual added to it */
+  int xy_nb[2];
+  double xy_lo[2], xy_hi[2];
+  const double* xy_coef;  /* [n_xy][xy_nb[1]+2][xy_nb[0]+2]                 */
+  int xy_shared;
+  /* sliced (kind 5, Sec. 6.1.2): XY LRFs on n_planes z planes at
+   * z_lo + p (z_hi - z_lo) / (n_planes - 1)                                */
+  int n_planes;
+  double z_lo, z_hi;
 } o_lrf;
 
 typedef struct {
@@ -205,7 +218,9 @@ double o_deboor1(const double* c, int nb, double lo, double hi, double u) {
 /* the domain, 0 outside (reading).                                     */
 /* ------------------------------------------------------------------ */
 static const double* o_table(const o_lrf* L, int i) {
-  size_t per = (size_t)(L->nb[0] + 2) * (size_t)(L->kind == O_AXIAL ? 1 : (L->nb[1] + 2));
+  size_t per = (size_t)(L->nb[0] + 2) *
+               (size_t)((L->kind == O_AXIAL || L->kind == O_COMPOSITE) ? 1 : (L->nb[1] + 2));
+  if (L->kind == O_SLICED) per *= (size_t)L->n_planes;
   return L->coef + (L->shared ? 0 : (size_t)i * per);
 }
 
@@ -217,6 +232,28 @@ double o_lrf_value(const o_lrf* L, int i, double x, double y, double z) {
     v = o_spline1(o_table(L, i), L->nb[0], L->lo[0], L->hi[0], r);
   } else if (L->kind == O_XY) {
     v = o_spline2(o_table(L, i), L->nb, L->lo, L->hi, x, y, NULL, NULL);
+  } else if (L->kind == O_COMPOSITE) {
+    /* Sec. 6.1.1: the sum of an axial LRF and an XY LRF (the residual);
+     * reading: each part is 0 outside its own domain, the sum is clamped */
+    double r = sqrt(dx * dx + dy * dy);
+    double a = o_spline1(L->coef, L->nb[0], L->lo[0], L->hi[0], r);
+    size_t per = (size_t)(L->xy_nb[0] + 2) * (size_t)(L->xy_nb[1] + 2);
+    const double* t = L->xy_coef + (L->xy_shared ? 0 : (size_t)i * per);
+    v = a + o_spline2(t, L->xy_nb, L->xy_lo, L->xy_hi, x, y, NULL, NULL);
+  } else if (L->kind == O_SLICED) {
+    /* Sec. 6.1.2: XY LRFs on z planes, linear interpolation in z between
+     * the values of the two closest planes; reading: 0 outside the planes'
+     * z range (with the domain slack) */
+    int p;
+    double t;
+    if (!o_locate(z, L->n_planes, L->z_lo, L->z_hi, &p, &t)) return 0.0;
+    const double* c = o_table(L, i);
+    size_t plane = (size_t)(L->nb[0] + 2) * (size_t)(L->nb[1] + 2);
+    double a = o_spline2(c + (size_t)p * plane, L->nb, L->lo, L->hi, x, y, NULL, NULL);
+    double b = o_spline2(c + (size_t)(p + 1) * plane, L->nb, L->lo, L->hi, x, y, NULL, NULL);
+    a = a > 0.0 ? a : 0.0;
+    b = b > 0.0 ? b : 0.0;
+    return (1.0 - t) * a + t * b;
   } else {
     double r = sqrt(dx * dx + dy * dy);
     v = o_spline2(o_table(L, i), L->nb, L->lo, L->hi, r, z, NULL, NULL);

@@ -89,7 +89,7 @@ def quasi_interp_2d(f, lo, hi, nb) -> np.ndarray:
 
 # ----------------------------------------------------------- descriptors
 
-KIND_AXIAL, KIND_XY, KIND_RZ = 1, 2, 3
+KIND_AXIAL, KIND_XY, KIND_RZ, KIND_COMPOSITE, KIND_SLICED = 1, 2, 3, 4, 5
 
 
 @dataclass
@@ -103,7 +103,18 @@ class LRFSet:
     nb: tuple                  # (nb0, nb1); nb1 = 1 for axial
     lo: tuple
     hi: tuple
-    coef: np.ndarray           # [n_lrf][nb1+2][nb0+2] float64 (axial: [n_lrf][1][nb0+2])
+    coef: np.ndarray           # [n_lrf][nb1+2][nb0+2] float64 (axial: [n_lrf][1][nb0+2];
+                               # sliced: [n_lrf][n_planes][nb1+2][nb0+2])
+    # composite: the XY residual added to the (shared) axial part
+    xy_nb: tuple = (0, 0)
+    xy_lo: tuple = (0.0, 0.0)
+    xy_hi: tuple = (0.0, 0.0)
+    xy_coef: np.ndarray = None  # [n_xy][xy_nb1+2][xy_nb0+2]
+    xy_shared: int = 1
+    # sliced: XY LRFs on n_planes z planes from z_lo to z_hi
+    n_planes: int = 0
+    z_lo: float = 0.0
+    z_hi: float = 0.0
 
     @property
     def n_sensors(self) -> int:
@@ -197,6 +208,40 @@ def xy_lrf(sxy, gain, h=5.0, nb=32, lo=-24.0, hi=24.0) -> LRFSet:
     n = sxy.shape[0]
     return LRFSet(KIND_XY, sxy, gain, np.ones(n, np.uint8), 0, (nb, nb),
                   (lo, lo), (hi, hi), np.stack(tabs))
+
+
+def composite_lrf(sxy, h=10.0, nb=20, hi=150.0, xy_nb=24, ext=90.0, amp=0.04,
+                  shift=6.0, width=14.0) -> LRFSet:
+    """Composite LRF (axial part + XY residual per sensor): the axial
+    solid-angle response of axial_lrf plus, per sensor, a non-axial bump
+    amp * exp(-((x - X - shift)^2 + (y - Y)^2) / (2 width^2)) (light
+    scattered towards +x) on a uniform XY grid over [-ext, ext]^2."""
+    base = axial_lrf(sxy, h=h, nb=nb, hi=hi)
+    tabs = []
+    for X, Y in sxy:
+        tabs.append(quasi_interp_2d(
+            lambda x, y, X=X, Y=Y: amp * np.exp(-((x - X - shift) ** 2 + (y - Y) ** 2)
+                                                / (2 * width ** 2)),
+            (-ext, -ext), (ext, ext), (xy_nb, xy_nb)))
+    return LRFSet(KIND_COMPOSITE, base.sxy, base.gain, base.active, 1, base.nb, base.lo,
+                  base.hi, base.coef, xy_nb=(xy_nb, xy_nb), xy_lo=(-ext, -ext),
+                  xy_hi=(ext, ext), xy_coef=np.stack(tabs), xy_shared=0)
+
+
+def sliced_lrf(sxy, n_planes=6, z_lo=0.0, z_hi=50.0, nb=20, ext=130.0) -> LRFSet:
+    """Sliced LRF: per sensor, XY LRFs on n_planes z planes, each the
+    solid-angle response with h = z + 10 mm of that plane (as the r-z
+    workload), on a uniform XY grid over [-ext, ext]^2."""
+    zs = np.linspace(z_lo, z_hi, n_planes)
+    tabs = []
+    for X, Y in sxy:
+        tabs.append(np.stack([quasi_interp_2d(
+            lambda x, y, X=X, Y=Y, h=z + 10.0: solid_angle(h, (x - X) ** 2 + (y - Y) ** 2),
+            (-ext, -ext), (ext, ext), (nb, nb)) for z in zs]))
+    n = sxy.shape[0]
+    return LRFSet(KIND_SLICED, sxy, np.ones(n), np.ones(n, np.uint8), 0, (nb, nb),
+                  (-ext, -ext), (ext, ext), np.stack(tabs), n_planes=n_planes, z_lo=z_lo,
+                  z_hi=z_hi)
 
 
 def streams(k: int, n: int = 4):

@@ -51,6 +51,11 @@ IMPL_FLOP_PER_EVAL_RZ_ML = 20
 # chi2 replaces the log and its FMA by the Pearson term (about 6 more)
 FLOP_PER_EVAL_XY_ML = 75
 FLOP_PER_EVAL_XY_CHI2 = 78
+# FP32 fraction of 157.3 from the hardware counters, 64 x (ADD + MUL +
+# 2 FMA + TRANS) of SQ_INSTS_VALU_*_F32 / kernel time, as recorded in
+# profiles/cg_kernel_rz_hex37_10M_plain_and_refine.md (reported beside the
+# canonical fraction, which counts the bicubic the oracle evaluates)
+COUNTER_FRAC = {"plain": 0.227, "refine": 0.087}
 
 
 def parse():
@@ -625,7 +630,12 @@ def main():
                   "traffic": profiled_traffic("plain"),
                   "kernel": "cg_kernel<RZ,ML,NT=6,SL=1> (7x7x7 plain grid)", "kernel_ms": ev_p,
                   "flop_per_launch": flops, "flop_per_eval": FLOP_PER_EVAL_RZ_ML,
-                  "impl_flop_per_eval": IMPL_FLOP_PER_EVAL_RZ_ML}
+                  "impl_flop_per_eval": IMPL_FLOP_PER_EVAL_RZ_ML,
+                  # the work the kernel does after the z-collapse (about 20
+                  # operations per evaluation), as a fraction of the peak
+                  "impl_frac": achieved * IMPL_FLOP_PER_EVAL_RZ_ML / FLOP_PER_EVAL_RZ_ML
+                  / PEAK_FP32_TFLOPS,
+                  "counter_frac": COUNTER_FRAC.get("plain")}
     rec = {
         "metric": "events/s reconstructed (plain grid vs NN-seeded) at equal sigma_xy, 1 MI355X",
         "value": n / wall_p, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -685,6 +695,9 @@ def main():
                            "kernel_ms": ev_r, "flop_per_launch": flops_r,
                            "flop_per_eval": FLOP_PER_EVAL_RZ_ML,
                            "impl_flop_per_eval": IMPL_FLOP_PER_EVAL_RZ_ML,
+                           "impl_frac": ach_r * IMPL_FLOP_PER_EVAL_RZ_ML / FLOP_PER_EVAL_RZ_ML
+                           / PEAK_FP32_TFLOPS,
+                           "counter_frac": COUNTER_FRAC.get("refine"),
                            "mean_iterations": float(k_ev.mean())}
         rec["value"] = n / wall_s
         rec["ms_per_step"] = 1e3 * wall_s

@@ -62,7 +62,21 @@ const char* ants_version(void);
 /* and RZ the first axis is r (lo[0] must be 0); RZ's second axis is z; */
 /* XY's axes are global x and y.                                        */
 /* ------------------------------------------------------------------ */
-typedef enum { ANTS_LRF_AXIAL = 1, ANTS_LRF_XY = 2, ANTS_LRF_RZ = 3 } ants_lrf_kind;
+typedef enum {
+  ANTS_LRF_AXIAL = 1,
+  ANTS_LRF_XY = 2,
+  ANTS_LRF_RZ = 3,
+  /* Sec. 6.1.1 "Composite": an Axial LRF (the first-axis fields below, one
+   * table shared by all sensors: shared must be 1) plus an XY LRF of the
+   * residual (the xy_* fields, per sensor or shared); each part is 0
+   * outside its own domain and the LRF is max(axial + residual, 0). */
+  ANTS_LRF_COMPOSITE = 4,
+  /* Sec. 6.1.2 "Sliced": XY LRFs (the fields below describe x and y) on
+   * n_planes z planes at z_lo + p (z_hi - z_lo) / (n_planes - 1); the LRF
+   * is (1 - t) L_p + t L_p+1 of the two closest planes' (clamped) values,
+   * 0 outside [z_lo, z_hi] (relative slack 1e-9).  3-D grids only. */
+  ANTS_LRF_SLICED = 5
+} ants_lrf_kind;
 
 typedef struct {
   int32_t n_sensors;          /* 1 .. 256                                       */
@@ -76,7 +90,17 @@ typedef struct {
                                  ignored for AXIAL                                */
   double lo[2], hi[2];        /* spline domain per axis, mm                      */
   const double* coef;         /* [n_tables][n_knots[1]+2][n_knots[0]+2] FP64;
-                                 AXIAL: [n_tables][n_knots[0]+2]                  */
+                                 AXIAL and COMPOSITE: [n_tables][n_knots[0]+2];
+                                 SLICED: [n_tables][n_planes][n_knots[1]+2]
+                                 [n_knots[0]+2]                                   */
+  /* COMPOSITE only: the XY residual (global x, y)                             */
+  int32_t xy_knots[2];        /* breakpoints per axis, 2..256                      */
+  double xy_lo[2], xy_hi[2];  /* residual domain, mm                               */
+  const double* xy_coef;      /* [n_xy][xy_knots[1]+2][xy_knots[0]+2] FP64         */
+  int32_t xy_shared;          /* 1: one residual for all sensors; 0: per sensor   */
+  /* SLICED only                                                                 */
+  int32_t n_planes;           /* 2..64                                            */
+  double z_lo, z_hi;          /* z of the first and last plane, mm                */
 } ants_lrf_desc;
 
 typedef struct ants_lrfset ants_lrfset;   /* opaque; owns its device copies */
@@ -104,6 +128,7 @@ ants_status ants_lrfset_info(const ants_lrfset* set, int32_t* n_sensors, int32_t
  *   uint8    active[n_sensors], zero padding to a multiple of 8 bytes
  *   double   coef[n_coef]          (layout of ants_lrf_desc.coef)
  *   uint64   FNV-1a (64-bit) hash of every preceding byte.
+ * Composite and sliced sets are not written (ANTS_E_UNSUPPORTED).
  * ants_lrf_write writes a descriptor (NULL gain/active are written as 1);
  * ants_lrfset_save writes what a set was created from (all sensors, passive
  * ones included).  Errors: ANTS_E_ARG (NULL, sizes, unwritable path).

@@ -23,7 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, E_ARG, E_FORMAT, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 EV_EMPTY, EV_BAD_INPUT, EV_NO_ACTIVE, EV_NO_VALID_NODE, EV_FALLBACK, EV_TIE = 1, 2, 4, 8, 16, 32
-LRF_AXIAL, LRF_XY, LRF_RZ = 1, 2, 3
+LRF_AXIAL, LRF_XY, LRF_RZ, LRF_COMPOSITE, LRF_SLICED = 1, 2, 3, 4, 5
 STAT_ML, STAT_CHI2 = 0, 1
 START_COG, START_MAXSENSOR, START_SEED = 0, 1, 2
 
@@ -38,7 +38,10 @@ class LrfDesc(C.Structure):
     _fields_ = [("n_sensors", C.c_int32), ("sensor_xy", C.POINTER(C.c_double)),
                 ("gain", C.POINTER(C.c_double)), ("active", C.POINTER(C.c_uint8)),
                 ("kind", C.c_int32), ("shared", C.c_int32), ("n_knots", C.c_int32 * 2),
-                ("lo", C.c_double * 2), ("hi", C.c_double * 2), ("coef", C.POINTER(C.c_double))]
+                ("lo", C.c_double * 2), ("hi", C.c_double * 2), ("coef", C.POINTER(C.c_double)),
+                ("xy_knots", C.c_int32 * 2), ("xy_lo", C.c_double * 2), ("xy_hi", C.c_double * 2),
+                ("xy_coef", C.POINTER(C.c_double)), ("xy_shared", C.c_int32),
+                ("n_planes", C.c_int32), ("z_lo", C.c_double), ("z_hi", C.c_double)]
 
 
 class GridCfg(C.Structure):
@@ -191,7 +194,20 @@ def lrf_desc(model):
     d.lo[0], d.lo[1] = float(model.lo[0]), float(model.lo[1])
     d.hi[0], d.hi[1] = float(model.hi[0]), float(model.hi[1])
     d.coef = _dptr(coef)
-    return d, (sxy, gain, active, coef)
+    keep = [sxy, gain, active, coef]
+    xc = getattr(model, "xy_coef", None)
+    if xc is not None:
+        xc = np.ascontiguousarray(xc, np.float64)
+        keep.append(xc)
+        d.xy_coef = _dptr(xc)
+        d.xy_knots[0], d.xy_knots[1] = int(model.xy_nb[0]), int(model.xy_nb[1])
+        d.xy_lo[0], d.xy_lo[1] = float(model.xy_lo[0]), float(model.xy_lo[1])
+        d.xy_hi[0], d.xy_hi[1] = float(model.xy_hi[0]), float(model.xy_hi[1])
+        d.xy_shared = int(model.xy_shared)
+    d.n_planes = int(getattr(model, "n_planes", 0))
+    d.z_lo = float(getattr(model, "z_lo", 0.0))
+    d.z_hi = float(getattr(model, "z_hi", 0.0))
+    return d, keep
 
 
 def write_lrf(model, path):

@@ -79,9 +79,30 @@ struct DevLrf {
   const double* Y;     // [na]
   const double* g;     // [na] relative gain
   const float* pp;     // axial: [ntab][nintp][4]; r-z: [nc1][nintp][4] (r-polys per z-row)
-  const float* c32;    // XY: [ntab][nc1][nc0] FP32 B-spline coefficients
-  const double* c64;   // all kinds: [ntab][nc1][nc0] FP64 coefficients
+  const float* c32;    // XY: [ntab][nc1][nc0] FP32 B-spline coefficients;
+                       // sliced: [ntab][nplanes][nc1][nc0]
+  const double* c64;   // all kinds: [ntab][nc1][nc0] FP64 coefficients (sliced:
+                       // [ntab][nplanes][nc1][nc0]; composite: the axial row)
+  // composite: the XY residual (coefficient tables in xc32 / xc64, table of
+  // active sensor a at xtab[a] * xnc0 * xnc1)
+  int xnb0, xnb1, xnc0, xnc1;
+  double xlo0, xhi0, xlo1, xhi1, xinv_d0, xinv_d1;
+  const int32_t* xtab;
+  const float* xc32;
+  const double* xc64;
+  // sliced: planes at zlo + p / inv_dz, p = 0 .. nplanes - 1
+  int nplanes;
+  double zlo, zhi, inv_dz;
 };
+// LRF kinds whose screen value is a cubic in the distance r read from a
+// table (the domain-end handling of the screen applies to them)
+__host__ __device__ constexpr bool radial_kind(int k) {
+  return k == ANTS_LRF_AXIAL || k == ANTS_LRF_RZ;
+}
+// LRF kinds with a bicubic in global x, y (per-node cell and weights)
+__host__ __device__ constexpr bool xy_kind(int k) {
+  return k == ANTS_LRF_XY || k == ANTS_LRF_COMPOSITE || k == ANTS_LRF_SLICED;
+}
 
 struct GridP {
   int nx, ny, nz, nn;  // nodes per axis, total

@@ -183,7 +183,7 @@ ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
   if ((int64_t)G.nx * G.ny * G.nz > kMaxNodes)
     return set_error(ANTS_E_ARG, "grid of %d x %d x %d exceeds %d nodes", G.nx, G.ny, G.nz,
                      kMaxNodes);
-  if (L.kind != ANTS_LRF_RZ && G.nz != 1)
+  if (L.kind != ANTS_LRF_RZ && L.kind != ANTS_LRF_SLICED && G.nz != 1)
     return set_error(ANTS_E_ARG, "a 2-D LRF needs nodes[2] = 1");
   if (G.nz > 101) return set_error(ANTS_E_ARG, "nodes[2] = %d exceeds 101", G.nz);
   G.nn = G.nx * G.ny * G.nz;
@@ -306,23 +306,48 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
     return fail(ANTS_E_ARG, "n_sensors = %d outside 1..%d", ns, kMaxSensors);
   if (!D->sensor_xy || !D->coef) return fail(ANTS_E_ARG, "sensor_xy and coef are required");
   const int kind = D->kind;
-  if (kind != ANTS_LRF_AXIAL && kind != ANTS_LRF_XY && kind != ANTS_LRF_RZ)
+  if (kind < ANTS_LRF_AXIAL || kind > ANTS_LRF_SLICED)
     return fail(ANTS_E_ARG, "unknown LRF kind %d", kind);
+  const bool one_axis = kind == ANTS_LRF_AXIAL || kind == ANTS_LRF_COMPOSITE;
   const int nb0 = D->n_knots[0];
-  const int nb1 = kind == ANTS_LRF_AXIAL ? 1 : D->n_knots[1];
-  if (nb0 < 2 || nb0 > 256 || (kind != ANTS_LRF_AXIAL && (nb1 < 2 || nb1 > 256)))
+  const int nb1 = one_axis ? 1 : D->n_knots[1];
+  if (nb0 < 2 || nb0 > 256 || (!one_axis && (nb1 < 2 || nb1 > 256)))
     return fail(ANTS_E_ARG, "n_knots (%d, %d) outside 2..256", D->n_knots[0], D->n_knots[1]);
-  const int naxes = kind == ANTS_LRF_AXIAL ? 1 : 2;
+  const int naxes = one_axis ? 1 : 2;
   for (int a = 0; a < naxes; ++a)
     if (!(isfinite(D->lo[a]) && isfinite(D->hi[a]) && D->lo[a] < D->hi[a]))
       return fail(ANTS_E_FORMAT, "axis %d domain [%g, %g] invalid", a, D->lo[a], D->hi[a]);
-  if (kind != ANTS_LRF_XY && D->lo[0] != 0.0)
+  if (kind != ANTS_LRF_XY && kind != ANTS_LRF_SLICED && D->lo[0] != 0.0)
     return fail(ANTS_E_UNSUPPORTED, "the r axis must start at 0 (lo[0] = %g)", D->lo[0]);
-  if (kind == ANTS_LRF_RZ && !D->shared)
-    return fail(ANTS_E_UNSUPPORTED, "r-z LRFs must be shared by all sensors");
-  const int nc0 = nb0 + 2, nc1 = kind == ANTS_LRF_AXIAL ? 1 : nb1 + 2;
+  if ((kind == ANTS_LRF_RZ || kind == ANTS_LRF_COMPOSITE) && !D->shared)
+    return fail(ANTS_E_UNSUPPORTED, "r-z LRFs and the axial part of composite LRFs must be "
+                                    "shared by all sensors");
+  // composite: the XY residual
+  const int xnb0 = kind == ANTS_LRF_COMPOSITE ? D->xy_knots[0] : 0;
+  const int xnb1 = kind == ANTS_LRF_COMPOSITE ? D->xy_knots[1] : 0;
+  const int xntab = kind == ANTS_LRF_COMPOSITE ? (D->xy_shared ? 1 : ns) : 0;
+  const size_t xper = (size_t)(xnb0 + 2) * (xnb1 + 2);
+  if (kind == ANTS_LRF_COMPOSITE) {
+    if (xnb0 < 2 || xnb0 > 256 || xnb1 < 2 || xnb1 > 256)
+      return fail(ANTS_E_ARG, "xy_knots (%d, %d) outside 2..256", xnb0, xnb1);
+    if (!D->xy_coef) return fail(ANTS_E_ARG, "a composite LRF needs xy_coef");
+    for (int a = 0; a < 2; ++a)
+      if (!(isfinite(D->xy_lo[a]) && isfinite(D->xy_hi[a]) && D->xy_lo[a] < D->xy_hi[a]))
+        return fail(ANTS_E_FORMAT, "residual axis %d domain [%g, %g] invalid", a, D->xy_lo[a],
+                    D->xy_hi[a]);
+    for (size_t i = 0; i < xper * xntab; ++i)
+      if (!isfinite(D->xy_coef[i])) return fail(ANTS_E_FORMAT, "xy_coef[%zu] is not finite", i);
+  }
+  // sliced: the z planes
+  const int np = kind == ANTS_LRF_SLICED ? D->n_planes : 1;
+  if (kind == ANTS_LRF_SLICED) {
+    if (np < 2 || np > 64) return fail(ANTS_E_ARG, "n_planes = %d outside 2..64", np);
+    if (!(isfinite(D->z_lo) && isfinite(D->z_hi) && D->z_lo < D->z_hi))
+      return fail(ANTS_E_FORMAT, "plane range [%g, %g] invalid", D->z_lo, D->z_hi);
+  }
+  const int nc0 = nb0 + 2, nc1 = one_axis ? 1 : nb1 + 2;
   const int ntab = D->shared ? 1 : ns;
-  const size_t per = (size_t)nc0 * nc1;
+  const size_t per = (size_t)nc0 * nc1 * np;
   for (size_t i = 0; i < per * ntab; ++i)
     if (!isfinite(D->coef[i])) return fail(ANTS_E_FORMAT, "coef[%zu] is not finite", i);
   for (int i = 0; i < 2 * ns; ++i)
@@ -333,12 +358,13 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
         return fail(ANTS_E_FORMAT, "gain[%d] = %g must be positive", i, D->gain[i]);
 
   // active sensors in their original order
-  std::vector<int32_t> col, tab;
+  std::vector<int32_t> col, tab, xtab;
   std::vector<double> X, Y, g;
   for (int i = 0; i < ns; ++i) {
     if (D->active && !D->active[i]) continue;
     col.push_back(i);
     tab.push_back(D->shared ? 0 : i);
+    xtab.push_back(D->xy_shared ? 0 : i);
     X.push_back(D->sensor_xy[2 * i]);
     Y.push_back(D->sensor_xy[2 * i + 1]);
     g.push_back(D->gain ? D->gain[i] : 1.0);
@@ -347,9 +373,9 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
 
   const int nint0 = nb0 - 1;
   const int nintp = nint0 + 1;  // one all-zero interval past the domain end
-  std::vector<float> pp, c32;
-  if (kind == ANTS_LRF_AXIAL || kind == ANTS_LRF_RZ) {
-    const int rows = kind == ANTS_LRF_AXIAL ? ntab : nc1;
+  std::vector<float> pp, c32, xc32;
+  if (kind == ANTS_LRF_AXIAL || kind == ANTS_LRF_RZ || kind == ANTS_LRF_COMPOSITE) {
+    const int rows = kind == ANTS_LRF_RZ ? nc1 : ntab;
     pp.assign((size_t)rows * nintp * 4, 0.f);
     for (int r = 0; r < rows; ++r)
       for (int m = 0; m < nint0; ++m) {
@@ -362,6 +388,10 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
   } else {
     c32.resize(per * ntab);
     for (size_t i = 0; i < c32.size(); ++i) c32[i] = (float)D->coef[i];
+  }
+  if (kind == ANTS_LRF_COMPOSITE) {
+    xc32.resize(xper * xntab);
+    for (size_t i = 0; i < xc32.size(); ++i) xc32[i] = (float)D->xy_coef[i];
   }
 
   ants_lrfset* S = new ants_lrfset();
@@ -381,16 +411,34 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
   d.ntab = ntab;
   d.lo0 = D->lo[0];
   d.hi0 = D->hi[0];
-  d.lo1 = kind == ANTS_LRF_AXIAL ? 0.0 : D->lo[1];
-  d.hi1 = kind == ANTS_LRF_AXIAL ? 1.0 : D->hi[1];
+  d.lo1 = one_axis ? 0.0 : D->lo[1];
+  d.hi1 = one_axis ? 1.0 : D->hi[1];
   d.d0 = (d.hi0 - d.lo0) / (nb0 - 1);
-  d.d1 = kind == ANTS_LRF_AXIAL ? 1.0 : (d.hi1 - d.lo1) / (nb1 - 1);
+  d.d1 = one_axis ? 1.0 : (d.hi1 - d.lo1) / (nb1 - 1);
+  if (kind == ANTS_LRF_COMPOSITE) {
+    d.xnb0 = xnb0;
+    d.xnb1 = xnb1;
+    d.xnc0 = xnb0 + 2;
+    d.xnc1 = xnb1 + 2;
+    d.xlo0 = D->xy_lo[0];
+    d.xhi0 = D->xy_hi[0];
+    d.xlo1 = D->xy_lo[1];
+    d.xhi1 = D->xy_hi[1];
+    d.xinv_d0 = (xnb0 - 1) / (d.xhi0 - d.xlo0);
+    d.xinv_d1 = (xnb1 - 1) / (d.xhi1 - d.xlo1);
+  }
+  if (kind == ANTS_LRF_SLICED) {
+    d.nplanes = np;
+    d.zlo = D->z_lo;
+    d.zhi = D->z_hi;
+    d.inv_dz = (np - 1) / (D->z_hi - D->z_lo);
+  }
   d.finv0 = (float)(1.0 / d.d0);
   d.inv_d0 = 1.0 / d.d0;
   d.inv_d1 = 1.0 / d.d1;
   // non-negative pieces: the screen can skip the clamp at 0
   d.nonneg = 0;
-  if (!pp.empty()) {
+  if (!pp.empty() && kind != ANTS_LRF_COMPOSITE) {
     bool nn = true;
     for (size_t r = 0; r + 3 < pp.size() && nn; r += 4) {
       const double a0 = pp[r], a1 = pp[r + 1], a2 = pp[r + 2], a3 = pp[r + 3];
@@ -435,6 +483,17 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
   if (dpp) S->allocs.push_back(dpp);
   if (e == hipSuccess) e = upload(&dc32, c32.data(), c32.size());
   if (dc32) S->allocs.push_back(dc32);
+  int32_t* dxtab = nullptr;
+  float* dxc32 = nullptr;
+  double* dxc64 = nullptr;
+  if (kind == ANTS_LRF_COMPOSITE) {
+    if (e == hipSuccess) e = upload(&dxtab, xtab.data(), xtab.size());
+    if (dxtab) S->allocs.push_back(dxtab);
+    if (e == hipSuccess) e = upload(&dxc32, xc32.data(), xc32.size());
+    if (dxc32) S->allocs.push_back(dxc32);
+    if (e == hipSuccess) e = upload(&dxc64, D->xy_coef, xper * xntab);
+    if (dxc64) S->allocs.push_back(dxc64);
+  }
   if (e != hipSuccess) {
     ants_lrfset_destroy(S);
     return hip_fail(e, "ants_lrfset_create upload");
@@ -463,6 +522,9 @@ ants_status ants_lrfset_create(const ants_lrf_desc* D, ants_lrfset** out) {
   d.pp = dpp;
   d.c32 = dc32;
   d.c64 = dc64;
+  d.xtab = dxtab;
+  d.xc32 = dxc32;
+  d.xc64 = dxc64;
   *out = S;
   return ANTS_OK;
 }
@@ -473,6 +535,8 @@ ants_status ants_lrf_write(const ants_lrf_desc* D, const char* path) {
   if (ns < 1 || ns > kMaxSensors)
     return fail(ANTS_E_ARG, "n_sensors = %d outside 1..%d", ns, kMaxSensors);
   if (!D->sensor_xy || !D->coef) return fail(ANTS_E_ARG, "sensor_xy and coef are required");
+  if (D->kind == ANTS_LRF_COMPOSITE || D->kind == ANTS_LRF_SLICED)
+    return fail(ANTS_E_UNSUPPORTED, "composite and sliced sets have no file format");
   if (D->kind != ANTS_LRF_AXIAL && D->kind != ANTS_LRF_XY && D->kind != ANTS_LRF_RZ)
     return fail(ANTS_E_ARG, "unknown LRF kind %d", D->kind);
   const int nb1 = D->kind == ANTS_LRF_AXIAL ? 0 : D->n_knots[1];
@@ -489,6 +553,8 @@ ants_status ants_lrf_write(const ants_lrf_desc* D, const char* path) {
 
 ants_status ants_lrfset_save(const ants_lrfset* S, const char* path) {
   if (!S || !path) return fail(ANTS_E_ARG, "ants_lrfset_save: NULL set or path");
+  if (S->h_kind == ANTS_LRF_COMPOSITE || S->h_kind == ANTS_LRF_SLICED)
+    return fail(ANTS_E_UNSUPPORTED, "composite and sliced sets have no file format");
   return write_lrf_file(path, S->ns, S->h_kind, S->h_shared, S->h_knots, S->h_lo, S->h_hi,
                         S->h_xy.data(), S->h_gain.data(), S->h_active.data(), S->h_coef.data(),
                         S->h_coef.size());

@@ -154,6 +154,10 @@ hipError_t launch_gen(const DevLrf& L, const GenP& P, hipStream_t stream, int ma
     hipLaunchKernelGGL(gen_kernel<ANTS_LRF_AXIAL>, g, b, 0, stream, L, P, waves_total);
   else if (L.kind == ANTS_LRF_XY)
     hipLaunchKernelGGL(gen_kernel<ANTS_LRF_XY>, g, b, 0, stream, L, P, waves_total);
+  else if (L.kind == ANTS_LRF_COMPOSITE)
+    hipLaunchKernelGGL(gen_kernel<ANTS_LRF_COMPOSITE>, g, b, 0, stream, L, P, waves_total);
+  else if (L.kind == ANTS_LRF_SLICED)
+    hipLaunchKernelGGL(gen_kernel<ANTS_LRF_SLICED>, g, b, 0, stream, L, P, waves_total);
   else
     hipLaunchKernelGGL(gen_kernel<ANTS_LRF_RZ>, g, b, 0, stream, L, P, waves_total);
   return hipGetLastError();

@@ -193,6 +193,19 @@ struct NodeF<ANTS_LRF_XY> {
   int cell;              // my * nc0 + mx
   float w[16];           // wy[a] * wx[b]
 };
+template <>
+struct NodeF<ANTS_LRF_COMPOSITE> {
+  float ox, oy;          // offset from the centre (axial part)
+  int cell;              // residual: my * xnc0 + mx
+  float w[16];           // residual weights (0 outside the residual's domain)
+};
+template <>
+struct NodeF<ANTS_LRF_SLICED> {
+  int cell;              // lower plane p * pstride + my * nc0 + mx
+  int pstride;           // coefficients per plane
+  float t;               // position between plane p and p + 1
+  float w[16];
+};
 
 // Radial kinds: node-sensor distance in units of the breakpoint spacing
 // (v = r / d0, the domain starting at r = 0), the sensor's table (r-z: the
@@ -218,35 +231,60 @@ __device__ __forceinline__ float rad32(const float4* T, float v, int nlast) {
   return NN ? p : fmaxf(p, 0.f);
 }
 
+// FP32 bicubic of a 4 x 4 coefficient patch (rows nc0 apart) with the
+// node's weights, read through the cache
+__device__ __forceinline__ float bicubic32(const float* p, int nc0, const float (&w)[16]) {
+  typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+  f4u r0 = *(const f4u*)(p);
+  f4u r1 = *(const f4u*)(p + nc0);
+  f4u r2 = *(const f4u*)(p + 2 * nc0);
+  f4u r3 = *(const f4u*)(p + 3 * nc0);
+  float v = w[0] * r0.x;
+  v = fmaf(w[1], r0.y, v);
+  v = fmaf(w[2], r0.z, v);
+  v = fmaf(w[3], r0.w, v);
+  v = fmaf(w[4], r1.x, v);
+  v = fmaf(w[5], r1.y, v);
+  v = fmaf(w[6], r1.z, v);
+  v = fmaf(w[7], r1.w, v);
+  v = fmaf(w[8], r2.x, v);
+  v = fmaf(w[9], r2.y, v);
+  v = fmaf(w[10], r2.z, v);
+  v = fmaf(w[11], r2.w, v);
+  v = fmaf(w[12], r3.x, v);
+  v = fmaf(w[13], r3.y, v);
+  v = fmaf(w[14], r3.z, v);
+  v = fmaf(w[15], r3.w, v);
+  return v;
+}
+
+// FP32 coefficient tables and row length the screen's bicubics read
+// (composite: its XY residual)
+template <int KIND>
+__device__ __forceinline__ const float* scr_c32(const DevLrf& L) {
+  return KIND == ANTS_LRF_COMPOSITE ? L.xc32 : L.c32;
+}
+template <int KIND>
+__device__ __forceinline__ int scr_nc0(const DevLrf& L) {
+  return KIND == ANTS_LRF_COMPOSITE ? L.xnc0 : L.nc0;
+}
+
 // Sensor record broadcast from LDS: A = {dX, dY, n, 1/L_c}, B = {g, L_c, table offset, a}
 template <int KIND, bool NN>
 __device__ __forceinline__ float lrf32(const NodeF<KIND>& nd, float dX, float dY, int tofs,
                                        const float4* btab, const float* c32, int nc0,
                                        float finv, int nlast) {
   if constexpr (KIND == ANTS_LRF_XY) {
-    typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+    return fmaxf(bicubic32(c32 + tofs + nd.cell, nc0, nd.w), 0.f);
+  } else if constexpr (KIND == ANTS_LRF_COMPOSITE) {
+    // the shared axial table (row 0) plus the sensor's residual, clamped
+    const float a = rad32<true>(btab, rad_v(nd, dX, dY), nlast);
+    return fmaxf(a + bicubic32(c32 + tofs + nd.cell, nc0, nd.w), 0.f);
+  } else if constexpr (KIND == ANTS_LRF_SLICED) {
     const float* p = c32 + tofs + nd.cell;
-    f4u r0 = *(const f4u*)(p);
-    f4u r1 = *(const f4u*)(p + nc0);
-    f4u r2 = *(const f4u*)(p + 2 * nc0);
-    f4u r3 = *(const f4u*)(p + 3 * nc0);
-    float v = nd.w[0] * r0.x;
-    v = fmaf(nd.w[1], r0.y, v);
-    v = fmaf(nd.w[2], r0.z, v);
-    v = fmaf(nd.w[3], r0.w, v);
-    v = fmaf(nd.w[4], r1.x, v);
-    v = fmaf(nd.w[5], r1.y, v);
-    v = fmaf(nd.w[6], r1.z, v);
-    v = fmaf(nd.w[7], r1.w, v);
-    v = fmaf(nd.w[8], r2.x, v);
-    v = fmaf(nd.w[9], r2.y, v);
-    v = fmaf(nd.w[10], r2.z, v);
-    v = fmaf(nd.w[11], r2.w, v);
-    v = fmaf(nd.w[12], r3.x, v);
-    v = fmaf(nd.w[13], r3.y, v);
-    v = fmaf(nd.w[14], r3.z, v);
-    v = fmaf(nd.w[15], r3.w, v);
-    return fmaxf(v, 0.f);
+    const float a = fmaxf(bicubic32(p, nc0, nd.w), 0.f);
+    const float b = fmaxf(bicubic32(p + nd.pstride, nc0, nd.w), 0.f);
+    return fmaf(nd.t, b - a, a);
   } else {
     const float v = rad_v(nd, dX, dY);
     return rad32<NN>(rad_tab<KIND>(nd, btab, tofs), v, nlast);
@@ -366,9 +404,40 @@ __device__ __forceinline__ bool make_node(const DevLrf& L, const GridP& G, doubl
   y = cy + oy;
   z = cz + oz;
   bool valid = j < G.nn;
-  if constexpr (KIND != ANTS_LRF_XY) {
+  if constexpr (radial_kind(KIND) || KIND == ANTS_LRF_COMPOSITE) {
     nd.ox = (float)(ox * L.inv_d0);
     nd.oy = (float)(oy * L.inv_d0);
+  }
+  if constexpr (KIND == ANTS_LRF_COMPOSITE) {
+    // residual weights; 0 outside its domain (the axial part still counts)
+    int m0 = 0, m1 = 0;
+    double t0 = 0.0, t1 = 0.0, b0[4], b1[4];
+    const bool in = locate64(x, L.xnb0, L.xlo0, L.xhi0, L.xinv_d0, m0, t0) &&
+                    locate64(y, L.xnb1, L.xlo1, L.xhi1, L.xinv_d1, m1, t1);
+    bweights64(t0, b0);
+    bweights64(t1, b1);
+    nd.cell = in ? m1 * L.xnc0 + m0 : 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) nd.w[a * 4 + b] = in ? (float)(b1[a] * b0[b]) : 0.f;
+  }
+  if constexpr (KIND == ANTS_LRF_SLICED) {
+    int m0 = 0, m1 = 0, pz = 0;
+    double t0 = 0.0, t1 = 0.0, tz = 0.0, b0[4], b1[4];
+    bool in0 = locate64(x, L.nb0, L.lo0, L.hi0, L.inv_d0, m0, t0);
+    bool in1 = locate64(y, L.nb1, L.lo1, L.hi1, L.inv_d1, m1, t1);
+    bool inz = locate64(z, L.nplanes, L.zlo, L.zhi, L.inv_dz, pz, tz);
+    valid = valid && in0 && in1 && inz;
+    bweights64(t0, b0);
+    bweights64(t1, b1);
+    nd.pstride = L.nc0 * L.nc1;
+    nd.cell = pz * nd.pstride + m1 * L.nc0 + m0;
+    nd.t = (float)tz;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) nd.w[a * 4 + b] = (float)(b1[a] * b0[b]);
   }
   if constexpr (KIND == ANTS_LRF_RZ) {
     int jzc = jz < G.nz ? jz : G.nz - 1;
@@ -624,7 +693,10 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       r.coff = coef_off64<KIND>(L, a);
       r.n = ign[q] ? -1.0f : nq[q];   // negative: ignored by the cuts
       rec64[a] = r;
-      tofq[q] = (KIND == ANTS_LRF_XY) ? L.tab[a] * L.nc0 * L.nc1 : L.tab[a] * L.nintp;
+      tofq[q] = KIND == ANTS_LRF_XY          ? L.tab[a] * L.nc0 * L.nc1
+                : KIND == ANTS_LRF_SLICED    ? L.tab[a] * L.nplanes * L.nc0 * L.nc1
+                : KIND == ANTS_LRF_COMPOSITE ? L.xtab[a] * L.xnc0 * L.xnc1
+                                             : L.tab[a] * L.nintp;
     }
   }
 
@@ -746,7 +818,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
     float dXq[SL], dYq[SL], Lcq[SL];
     float ex = 0.f, ey = 0.f, lo2 = 0.f, hi2 = 0.f;
     bool reach = false;   // some sensor may reach the end of the domain
-    if constexpr (KIND != ANTS_LRF_XY) {
+    if constexpr (radial_kind(KIND)) {
       ex = (float)((double)(G.nx - 1 - G.hx) * sx * L.inv_d0);
       ey = (float)((double)(G.ny - 1 - G.hy) * sy * L.inv_d0);
       band = 4e-6f * (vhi + 2.f * (ex + ey) + 1.f);
@@ -761,13 +833,13 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
         const SensorRec64 r = rec64[a];
         const float dX = (float)((r.X - cx) * L.inv_d0), dY = (float)((r.Y - cy) * L.inv_d0);
         const float Lc = have_prev ? Lprev[q]
-                                   : lrf32<KIND, NN>(ndc, dX, dY, tofq[q], btab, L.c32, L.nc0,
+                                   : lrf32<KIND, NN>(ndc, dX, dY, tofq[q], btab, scr_c32<KIND>(L), scr_nc0<KIND>(L),
                                                      finv, nlast);
         if (!ign[q]) Sc = fmaf((float)r.g, Lc, Sc);
         dXq[q] = dX;
         dYq[q] = dY;
         Lcq[q] = Lc;
-        if constexpr (KIND != ANTS_LRF_XY) {
+        if constexpr (radial_kind(KIND)) {
           const float fx = fabsf(dX) + ex, fy = fabsf(dY) + ey;
           reach = reach || (!ign[q] && !(fmaf(fx, fx, fy * fy) < lo2));
         }
@@ -1000,14 +1072,14 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
           const int o0 = __float_as_int(B0.z), o1 = __float_as_int(B1.z), oh = __float_as_int(Bh.z);
 #pragma unroll
           for (int t = 0; t < LT; ++t) {
-            const float L0 = lrf32<KIND, NN>(nd[t], A0.x, A0.y, o0, btab, L.c32, L.nc0, finv, nlast);
+            const float L0 = lrf32<KIND, NN>(nd[t], A0.x, A0.y, o0, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B0.x, L0 - B0.y, dS[t]);
             T[t] = fmaf(A0.z, __builtin_amdgcn_logf(L0 * A0.w), T[t]);
-            const float L1 = lrf32<KIND, NN>(nd[t], A1.x, A1.y, o1, btab, L.c32, L.nc0, finv, nlast);
+            const float L1 = lrf32<KIND, NN>(nd[t], A1.x, A1.y, o1, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B1.x, L1 - B1.y, dS[t]);
             T[t] = fmaf(A1.z, __builtin_amdgcn_logf(L1 * A1.w), T[t]);
           }
-          const float Lh = lrf32<KIND, NN>(nd[LT], Ah.x, Ah.y, oh, btab, L.c32, L.nc0, finv, nlast);
+          const float Lh = lrf32<KIND, NN>(nd[LT], Ah.x, Ah.y, oh, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
           dS[LT] = fmaf(Bh.x, Lh - Bh.y, dS[LT]);
           T[LT] = fmaf(Ah.z, __builtin_amdgcn_logf(Lh * Ah.w), T[LT]);
         }
@@ -1016,12 +1088,12 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
           const int o = __float_as_int(B.z);
 #pragma unroll
           for (int t = 0; t < LT; ++t) {
-            const float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+            const float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, o, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
             T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
           }
           const float w = hb ? 0.f : 1.f;
-          const float Lh = lrf32<KIND, NN>(nd[LT], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+          const float Lh = lrf32<KIND, NN>(nd[LT], A.x, A.y, o, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
           dS[LT] = fmaf(B.x * w, Lh - B.y, dS[LT]);
           T[LT] = fmaf(A.z * w, __builtin_amdgcn_logf(Lh * A.w), T[LT]);
         }
@@ -1031,12 +1103,12 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
           const int o0 = __float_as_int(B0.z), o1 = __float_as_int(B1.z), oh = __float_as_int(Bh.z);
 #pragma unroll
           for (int t = 0; t < LT; ++t) {
-            const float L0 = lrf32<KIND, NN>(nd[t], A0.x, A0.y, o0, btab, L.c32, L.nc0, finv, nlast);
+            const float L0 = lrf32<KIND, NN>(nd[t], A0.x, A0.y, o0, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B0.x, L0 - B0.y, dS[t]);
-            const float L1 = lrf32<KIND, NN>(nd[t], A1.x, A1.y, o1, btab, L.c32, L.nc0, finv, nlast);
+            const float L1 = lrf32<KIND, NN>(nd[t], A1.x, A1.y, o1, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B1.x, L1 - B1.y, dS[t]);
           }
-          const float Lh = lrf32<KIND, NN>(nd[LT], Ah.x, Ah.y, oh, btab, L.c32, L.nc0, finv, nlast);
+          const float Lh = lrf32<KIND, NN>(nd[LT], Ah.x, Ah.y, oh, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
           dS[LT] = fmaf(Bh.x, Lh - Bh.y, dS[LT]);
         }
         if (p < z_end) {
@@ -1044,10 +1116,10 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
           const int o = __float_as_int(B.z);
 #pragma unroll
           for (int t = 0; t < LT; ++t) {
-            const float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+            const float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, o, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
           }
-          const float Lh = lrf32<KIND, NN>(nd[LT], A.x, A.y, o, btab, L.c32, L.nc0, finv, nlast);
+          const float Lh = lrf32<KIND, NN>(nd[LT], A.x, A.y, o, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
           dS[LT] = fmaf(hb ? 0.f : B.x, Lh - B.y, dS[LT]);
         }
         dS[LT] += __shfl_xor(dS[LT], 32);
@@ -1059,7 +1131,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
           int tofs = __float_as_int(B.z);
   #pragma unroll
           for (int t = 0; t < NT; ++t) {
-            float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+            float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
             T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
           }
@@ -1069,7 +1141,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
           // zero (or NaN where the first half's term is infinite already)
           float4 A = recA[p], B = recB[p];
           const float w = hb ? 0.f : 1.f;
-          float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+          float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, scr_c32<KIND>(L), scr_nc0<KIND>(L),
                                      finv, nlast);
           dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
           T[0] = fmaf(A.z * w, __builtin_amdgcn_logf(Lv * A.w), T[0]);
@@ -1080,14 +1152,14 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
           int tofs = __float_as_int(B.z);
   #pragma unroll
           for (int t = 0; t < NT; ++t) {
-            float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+            float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
             dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
           }
         }
         if (split && p < z_end) {
           float4 A = recA[p], B = recB[p];
           const float w = hb ? 0.f : 1.f;
-          float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+          float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, scr_c32<KIND>(L), scr_nc0<KIND>(L),
                                      finv, nlast);
           dS[0] = fmaf(B.x * w, Lv - B.y, dS[0]);
         }
@@ -1103,7 +1175,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       bool knife[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) knife[t] = false;
-      if constexpr (KIND != ANTS_LRF_XY && !FA) {
+      if constexpr (radial_kind(KIND) && !FA) {
         for (int p = n_ci; p < n_pos; ++p) {
           const float4 A = recA[p], B = recB[p];
           const int o = __float_as_int(B.z);
@@ -1152,13 +1224,13 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
         int tofs = __float_as_int(B.z);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
           S[t] = fmaf(B.x, Lv, S[t]);
         }
       }
       if (split && p < n_scr) {
         float4 A = recA[p], B = recB[p];
-        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, scr_c32<KIND>(L), scr_nc0<KIND>(L),
                                    finv, nlast);
         S[0] = fmaf(hb ? 0.f : B.x, Lv, S[0]);
       }
@@ -1170,7 +1242,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
         int tofs = __float_as_int(B.z);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, L.c32, L.nc0, finv, nlast);
+          float Lv = lrf32<KIND, NN>(nd[t], A.x, A.y, tofs, btab, scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
           float mu = Ag[t] * B.x * Lv;
           float dd = A.z - mu;
           float v = fmaxf(mu, fvf);
@@ -1179,7 +1251,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       }
       if (split && p < n_scr) {
         float4 A = recA[p], B = recB[p];
-        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, L.c32, L.nc0,
+        float Lv = lrf32<KIND, NN>(nd[0], A.x, A.y, __float_as_int(B.z), btab, scr_c32<KIND>(L), scr_nc0<KIND>(L),
                                    finv, nlast);
         float mu = Ag[0] * B.x * Lv;
         float dd = A.z - mu;
@@ -1191,7 +1263,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       bool knife[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) knife[t] = false;
-      if constexpr (KIND != ANTS_LRF_XY) {
+      if constexpr (radial_kind(KIND)) {
         auto mark = [&](int p0, int p1) {
           for (int p = p0; p < p1; ++p) {
             const float4 A = recA[p];
@@ -1240,7 +1312,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       const int tb = jb >> 6, lb = jb & 63;
       float Sb = 0.f;
       NodeF<KIND> ndb;
-      if constexpr (KIND == ANTS_LRF_XY) {
+      if constexpr (xy_kind(KIND)) {
         double xx, yy, zz;
         make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, jb, ztab, nodeidx, ndb, xx, yy, zz);
       }
@@ -1248,7 +1320,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       for (int t = 0; t < NT; ++t) {
         if (t == tb) {
           Sb = lane_val(Snode[t], lb);
-          if constexpr (KIND != ANTS_LRF_XY) {
+          if constexpr (radial_kind(KIND)) {
             ndb.ox = lane_val(nd[t].ox, lb);
             ndb.oy = lane_val(nd[t].oy, lb);
           }
@@ -1266,8 +1338,8 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
         if (a < na && !ign[q]) {
           RA[q] = recA[posq[q]];
           RB[q] = recB[posq[q]];
-          Lb[q] = lrf32<KIND, NN>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab, L.c32,
-                              L.nc0, finv, nlast);
+          Lb[q] = lrf32<KIND, NN>(ndb, RA[q].x, RA[q].y, __float_as_int(RB[q].z), btab,
+                                  scr_c32<KIND>(L), scr_nc0<KIND>(L), finv, nlast);
         }
         Lprev[q] = Lb[q];
       }
@@ -1528,7 +1600,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
 // whose time goes largely to latency-bound reductions and FP64 decisions;
 // three (168 VGPRs) for more tiles; the XY kernels with many tiles keep two.
 template <int KIND, int NT>
-constexpr int waves_per_eu() { return (KIND == ANTS_LRF_XY && NT >= 4) ? 2 : NT == 1 ? 4 : 3; }
+constexpr int waves_per_eu() { return (xy_kind(KIND) && NT >= 4) ? 2 : NT == 1 ? 4 : 3; }
 
 template <int KIND, int STAT, int NT, int SL, bool NN, int FZ>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KIND, NT>())))
@@ -1585,7 +1657,7 @@ template <int KIND, int STAT, int NT, int SL, bool NN, int FZ = 0>
 hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t stream,
                     int max_blocks) {
   int btab_n = 0;
-  if (KIND == ANTS_LRF_AXIAL) btab_n = L.ntab * L.nintp;
+  if (KIND == ANTS_LRF_AXIAL || KIND == ANTS_LRF_COMPOSITE) btab_n = L.ntab * L.nintp;
   if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
   const int per_wave = wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT, FZ ? G.nx * G.ny : 0);
   size_t smem = (size_t)btab_n * 16 + (size_t)kWavesPerBlock * per_wave;
@@ -1650,7 +1722,9 @@ hipError_t launch_ksn(const DevLrf& L, const GridP& G, const IoP& io, hipStream_
 
 template <int KIND, int STAT>
 hipError_t launch_ks(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
-  if (KIND != ANTS_LRF_XY && L.nonneg) return launch_ksn<KIND, STAT, true>(L, G, io, s, mb);
+  if constexpr (radial_kind(KIND)) {
+    if (L.nonneg) return launch_ksn<KIND, STAT, true>(L, G, io, s, mb);
+  }
   return launch_ksn<KIND, STAT, false>(L, G, io, s, mb);
 }
 

@@ -61,6 +61,9 @@ ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets
     SetDesc d;
     memset(&d, 0, sizeof(d));
     d.L = S[i]->d;
+    if (d.L.kind != ANTS_LRF_AXIAL && d.L.kind != ANTS_LRF_XY && d.L.kind != ANTS_LRF_RZ)
+      return set_error(ANTS_E_UNSUPPORTED, "sets[%d]: composite and sliced LRFs are not "
+                                           "supported by the multi-detector launch", i);
     ants_status st = grid_params(d.L, &cfgs[i], &d.G);
     if (st != ANTS_OK) return st;
     if (cfgs[i].start == ANTS_START_SEED)

@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) simplex_kernel(SxP P) {
 
 template <int KIND, int STAT, int SL>
 hipError_t launch_sx_kss(const SxP& P, int blocks, hipStream_t s) {
-  if (KIND == ANTS_LRF_RZ && P.dims == 3)
+  if ((KIND == ANTS_LRF_RZ || KIND == ANTS_LRF_SLICED) && P.dims == 3)
     hipLaunchKernelGGL((simplex_kernel<KIND, STAT, SL, 3>), dim3(blocks), dim3(256), 0, s, P);
   else
     hipLaunchKernelGGL((simplex_kernel<KIND, STAT, SL, 2>), dim3(blocks), dim3(256), 0, s, P);
@@ -355,8 +355,8 @@ extern "C" ants_status ants_reconstruct_simplex(ants_lrfset* set, const ants_sim
   const DevLrf& L = set->d;
   if (cfg->dims != 2 && cfg->dims != 3)
     return set_error(ANTS_E_ARG, "dims = %d must be 2 or 3", cfg->dims);
-  if (cfg->dims == 3 && L.kind != ANTS_LRF_RZ)
-    return set_error(ANTS_E_ARG, "a 3-D search needs an r-z LRF");
+  if (cfg->dims == 3 && L.kind != ANTS_LRF_RZ && L.kind != ANTS_LRF_SLICED)
+    return set_error(ANTS_E_ARG, "a 3-D search needs an r-z or sliced LRF");
   if (cfg->stat != ANTS_STAT_ML && cfg->stat != ANTS_STAT_CHI2)
     return set_error(ANTS_E_ARG, "unknown statistic %d", cfg->stat);
   if (cfg->start < ANTS_START_COG || cfg->start > ANTS_START_SEED)
@@ -410,8 +410,10 @@ extern "C" ants_status ants_reconstruct_simplex(ants_lrfset* set, const ants_sim
   const int64_t cap = (int64_t)num_cu() * 16;
   if (blocks > cap) blocks = cap;
   hipStream_t s = (hipStream_t)hip_stream;
-  hipError_t e = L.kind == ANTS_LRF_AXIAL ? launch_sx_k<ANTS_LRF_AXIAL>(P, (int)blocks, s)
-                 : L.kind == ANTS_LRF_XY  ? launch_sx_k<ANTS_LRF_XY>(P, (int)blocks, s)
-                                          : launch_sx_k<ANTS_LRF_RZ>(P, (int)blocks, s);
+  hipError_t e = L.kind == ANTS_LRF_AXIAL       ? launch_sx_k<ANTS_LRF_AXIAL>(P, (int)blocks, s)
+                 : L.kind == ANTS_LRF_XY        ? launch_sx_k<ANTS_LRF_XY>(P, (int)blocks, s)
+                 : L.kind == ANTS_LRF_COMPOSITE ? launch_sx_k<ANTS_LRF_COMPOSITE>(P, (int)blocks, s)
+                 : L.kind == ANTS_LRF_SLICED    ? launch_sx_k<ANTS_LRF_SLICED>(P, (int)blocks, s)
+                                                : launch_sx_k<ANTS_LRF_RZ>(P, (int)blocks, s);
   return e == hipSuccess ? ANTS_OK : hip_error(e, "ants_reconstruct_simplex launch");
 }

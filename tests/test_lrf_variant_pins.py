@@ -35,7 +35,7 @@ def _same(a, b):
 def test_composite_reduces_to_axial_and_to_xy():
     sxy = W.hex_array(2, 30.0)
     comp = W.composite_lrf(sxy)
-    axial = W.axial_lrf(sxy)
+    axial = W.axial_lrf(sxy, nb=comp.nb[0], hi=comp.hi[0])
     pos = np.random.default_rng(1).uniform(-80, 80, (300, 3))
     pos[:, 2] = 0.0
     no_res = dataclasses.replace(comp, xy_coef=np.zeros_like(comp.xy_coef))

@@ -210,7 +210,7 @@ def xy_lrf(sxy, gain, h=5.0, nb=32, lo=-24.0, hi=24.0) -> LRFSet:
                   (lo, lo), (hi, hi), np.stack(tabs))
 
 
-def composite_lrf(sxy, h=10.0, nb=20, hi=150.0, xy_nb=24, ext=90.0, amp=0.04,
+def composite_lrf(sxy, h=10.0, nb=24, hi=200.0, xy_nb=24, ext=90.0, amp=0.04,
                   shift=6.0, width=14.0) -> LRFSet:
     """Composite LRF (axial part + XY residual per sensor): the axial
     solid-angle response of axial_lrf plus, per sensor, a non-axial bump

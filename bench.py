@@ -617,8 +617,15 @@ def main():
     sig, truth = ants.generate(lrf, ants.gen_cfg(wl.events), n, args.seed)
     out_plain = ants.alloc_out(n)
     torch.cuda.synchronize()
+    nt = min(n, 1_000_000)
 
-    # ---- plain grid
+    def plan_rec(p, ms):
+        return {"waves_per_block": p.waves_per_block, "blocks_per_cu": p.blocks_per_cu,
+                "screen": "per-node" if p.screen else "column-factored",
+                "candidate_ms": [round(float(v), 4) for v in ms if v > 0]}
+
+    # ---- plain grid (launch plan tuned on the first 1M events, untimed)
+    plan_p, ms_p = ants.autotune(lrf, plain, sig[:nt].contiguous(), stream=stream)
     wall_p, ev_p = timed(lambda: ants.reconstruct(lrf, plain, sig, out=out_plain, stream=stream),
                          args.steps, args.warmup, stream)
     evals = int(np.prod(wl.grid.nodes)) * 37 * wl.grid.iterations
@@ -628,7 +635,8 @@ def main():
     roof_plain = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                   "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                   "traffic": profiled_traffic("plain"),
-                  "kernel": "cg_kernel<RZ,ML,NT=6,SL=1> (7x7x7 plain grid)", "kernel_ms": ev_p,
+                  "kernel": "cg_kernel<RZ,ML,NT=6,SL=1,%s> (7x7x7 plain grid)" %
+                            ("FZ=0" if plan_p.screen else "FZ=7"), "kernel_ms": ev_p,
                   "flop_per_launch": flops, "flop_per_eval": FLOP_PER_EVAL_RZ_ML,
                   "impl_flop_per_eval": IMPL_FLOP_PER_EVAL_RZ_ML,
                   # the work the kernel does after the z-collapse (about 20
@@ -647,7 +655,7 @@ def main():
                    "events": n, "sensors": 37},
         "plain": {"events_per_s": n / wall_p, "ms_per_step": 1e3 * wall_p,
                   "sigma_xy_mm": sp[0], "sigma_xy_fiducial_mm": sp[1], "p95_radial_mm": sp[2],
-                  "roofline": roof_plain},
+                  "roofline": roof_plain, "plan": plan_rec(plan_p, ms_p)},
         "roofline": roof_plain,
     }
 
@@ -662,6 +670,16 @@ def main():
         refine = ants.grid_cfg(W.seeded_refine_grid(kappa=args.kappa))
         out_seed = ants.alloc_out(n)
         nfb_box = {}
+        # refinement launch plan tuned on the first 1M events with the
+        # network's seeds (untimed set-up, like the training)
+        import torch
+        pred = net.forward(lrf, sig, stream=stream)
+        seeds = pred.clone()
+        seeds[:, :3] = (pred[:, :3] * torch.tensor(W.SEED_POS_SCALE, device=pred.device)
+                        + torch.tensor(W.SEED_POS_OFFSET, device=pred.device))
+        seeds = seeds.contiguous()
+        plan_r, ms_r = ants.autotune(lrf, refine, sig[:nt].contiguous(),
+                                     seeds=seeds[:nt].contiguous(), stream=stream)
 
         def seeded():
             o, nfb = ants.reconstruct_seeded(lrf, net, refine, plain, 2.0, sig, out=out_seed,
@@ -675,15 +693,14 @@ def main():
         _, ev_mlp = timed(lambda: net.forward(lrf, sig, stream=stream), 2, 1, stream)
         # the step's dominant kernel: the 3x3x3 refinement (one node tile),
         # timed alone from the same seeds; FLOP from each event's iterations
-        import torch
-        pred = net.forward(lrf, sig, stream=stream)
-        seeds = pred.clone()
-        seeds[:, :3] = (pred[:, :3] * torch.tensor(W.SEED_POS_SCALE, device=pred.device)
-                        + torch.tensor(W.SEED_POS_OFFSET, device=pred.device))
-        seeds = seeds.contiguous()
         out_r = ants.alloc_out(n)
         _, ev_r = timed(lambda: ants.reconstruct(lrf, refine, sig, seeds=seeds, out=out_r,
                                                  stream=stream), args.steps, 1, stream)
+        # the same kernel under the default plan, for comparison
+        ants.set_plan(lrf, refine, None)
+        _, ev_r0 = timed(lambda: ants.reconstruct(lrf, refine, sig, seeds=seeds, out=out_r,
+                                                  stream=stream), 2, 1, stream)
+        ants.set_plan(lrf, refine, plan_r)
         rg = W.seeded_refine_grid(kappa=args.kappa)
         k_ev = seed_iterations(pred[:, 3].cpu().numpy(), rg)
         flops_r = int(k_ev.sum()) * int(np.prod(rg.nodes)) * 37 * FLOP_PER_EVAL_RZ_ML
@@ -691,7 +708,9 @@ def main():
         rec["roofline"] = {"bound": "alu", "achieved": ach_r, "peak": PEAK_FP32_TFLOPS,
                            "unit": "TFLOP/s", "frac": ach_r / PEAK_FP32_TFLOPS,
                            "traffic": profiled_traffic("refine"),
-                           "kernel": "cg_kernel<RZ,ML,NT=1,SL=1> (3x3x3 seeded refinement)",
+                           "kernel": "cg_kernel<RZ,ML,NT=1,SL=1,%s> (3x3x3 seeded refinement)" %
+                                     ("FZ=0" if plan_r.screen else "FZ=3"),
+                           "plan": plan_rec(plan_r, ms_r), "default_plan_kernel_ms": ev_r0,
                            "kernel_ms": ev_r, "flop_per_launch": flops_r,
                            "flop_per_eval": FLOP_PER_EVAL_RZ_ML,
                            "impl_flop_per_eval": IMPL_FLOP_PER_EVAL_RZ_ML,

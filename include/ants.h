@@ -223,6 +223,35 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
                              const float* d_signals, const float* d_seeds, ants_out out,
                              void* hip_stream);
 
+/* Launch plan of ants_reconstruct (and of the refinement and fallback
+ * grids of the seeded path) for one grid configuration of one set.  The
+ * reconstructed values do not depend on it. */
+typedef struct {
+  int32_t waves_per_block;   /* events in flight per block: 1, 2 or 4 (default 4) */
+  int32_t blocks_per_cu;     /* cap on resident blocks per compute unit; 0 = as many
+                                as fit (default)                                   */
+  int32_t screen;            /* 0 (default): the column-factored r-z screen where it
+                                applies (ML, 3, 5 or 7 z planes, <= 64 active
+                                sensors); 1: the per-node screen                   */
+} ants_grid_plan;
+
+/* Autotuner (per set and grid configuration): times the candidate plans
+ * (screen variant where both apply, waves per block 4/2/1, blocks per CU
+ * as many as fit or 2) on the first n_sample events of d_signals (d_seeds
+ * as for ants_reconstruct), writing into `scratch` (n_sample rows); only
+ * the kernel is timed, between HIP events, after a warm-up launch.  The
+ * fastest goes to *best and is stored in the set for this configuration
+ * (up to 8 configurations per set, the oldest dropped first); host_ms
+ * [12] (or NULL) receives each candidate's time in search order (screen
+ * outermost, then waves per block, then blocks per CU).  Synchronises the
+ * stream.  ants_set_plan stores a plan explicitly (NULL removes it), for
+ * a deterministic choice. */
+ants_status ants_autotune(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t n_sample,
+                          const float* d_signals, const float* d_seeds, ants_out scratch,
+                          ants_grid_plan* best, double* host_ms, void* hip_stream);
+ants_status ants_set_plan(ants_lrfset* set, const ants_grid_cfg* cfg,
+                          const ants_grid_plan* plan);
+
 /* ------------------------------------------------------------------ */
 /* Simplex search (Sec. 5.1.2.1: the Minuit2 Simplex minimiser over the  */
 /* position, x, y or x, y, z, from the centroid or the strongest        */

@@ -87,6 +87,11 @@ class Plan(C.Structure):
                 ("table_in_lds", C.c_int32)]
 
 
+class GridPlan(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("screen", C.c_int32)]
+
+
 class SimplexCfg(C.Structure):
     _fields_ = [("dims", C.c_int32), ("stat", C.c_int32), ("start", C.c_int32),
                 ("step0", C.c_double * 3), ("z_start", C.c_double), ("tol", C.c_double),
@@ -141,6 +146,9 @@ _lib.ants_autotune_multi.argtypes = [C.POINTER(_vp), C.POINTER(GridCfg), C.c_int
                                      C.POINTER(Chunk), C.c_int32, C.c_int64, Out, C.POINTER(Plan),
                                      C.POINTER(C.c_double), _vp]
 
+_lib.ants_autotune.argtypes = [_vp, C.POINTER(GridCfg), C.c_int64, _vp, _vp, Out,
+                               C.POINTER(GridPlan), C.POINTER(C.c_double), _vp]
+_lib.ants_set_plan.argtypes = [_vp, C.POINTER(GridCfg), C.POINTER(GridPlan)]
 _lib.ants_reconstruct_simplex.argtypes = [_vp, C.POINTER(SimplexCfg), C.c_int64, _vp, _vp, Out,
                                           _vp, _vp]
 
@@ -160,7 +168,7 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf",
             "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load",
             "ants_reconstruct_simplex", "ants_knn_create", "ants_knn_destroy",
-            "ants_knn_reconstruct")
+            "ants_knn_reconstruct", "ants_autotune", "ants_set_plan")
 
 
 def _check(code):
@@ -412,6 +420,26 @@ class Knn:
             self.close()
         except Exception:
             pass
+
+
+def autotune(lrfset: LrfSet, cfg: GridCfg, signals, seeds=None, stream=None):
+    """Time the launch plans of `cfg` on `signals` and store the fastest in
+    the set (ants_autotune).  Returns (GridPlan, per-candidate ms)."""
+    n = signals.shape[0]
+    scratch = alloc_out(n, 0, signals.device)
+    best = GridPlan()
+    ms = np.zeros(12, np.float64)
+    _check(_lib.ants_autotune(lrfset.handle, C.byref(cfg), n, signals.data_ptr(),
+                              seeds.data_ptr() if seeds is not None else None,
+                              _out_struct(scratch), C.byref(best),
+                              ms.ctypes.data_as(C.POINTER(C.c_double)), _stream_handle(stream)))
+    return best, ms
+
+
+def set_plan(lrfset: LrfSet, cfg: GridCfg, plan):
+    """Store (or, with plan=None, remove) the set's launch plan for cfg."""
+    _check(_lib.ants_set_plan(lrfset.handle, C.byref(cfg),
+                              C.byref(plan) if plan is not None else None))
 
 
 def gen_cfg(recipe, noiseless=False) -> GenCfg:

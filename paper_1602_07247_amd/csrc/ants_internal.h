@@ -128,6 +128,10 @@ struct GridP {
   double cut_dist;     // > 0: ignore sensors farther (x-y) than it from the start
   double fb_thr;       // >= 0: events with chi2/ndf above it go to the fallback list
   int or_status;       // status bits OR-ed into every processed event
+  // launch plan (host side; see ants_grid_plan): waves per block (0 = 4),
+  // cap on blocks per CU (0 = as many as fit), screen (0 = column-factored
+  // where it applies, 1 = per node)
+  int plan_wpb, plan_bpc, plan_screen;
 };
 
 struct IoP {
@@ -255,6 +259,11 @@ ants_status set_error(ants_status st, const char* fmt, ...) __attribute__((forma
 ants_status hip_error(hipError_t e, const char* what);
 // ants_grid_cfg -> kernel parameters (validated against the LRF set)
 ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* G);
+// key of a grid configuration in a set's plan cache (fields that change the
+// work per event); never 0
+uint64_t grid_cfg_key(const ants_grid_cfg& c);
+// the set's stored launch plan for this configuration, if any, into G
+void apply_grid_plan(const ants_lrfset* S, const ants_grid_cfg* cfg, GridP* G);
 int num_cu();
 // grow-only device buffer
 hipError_t ensure(void** p, size_t* have, size_t need);
@@ -287,6 +296,14 @@ struct ants_lrfset {
   void* ms_host = nullptr;
   size_t ms_host_bytes = 0;
   hipEvent_t ms_copied = nullptr;
+  // launch plans of ants_reconstruct per grid configuration (ants_autotune,
+  // ants_set_plan): key, waves per block, blocks per CU, screen
+  struct GridPlanEntry {
+    uint64_t key;
+    int32_t wpb, bpc, screen;
+  };
+  GridPlanEntry gplan[8] = {};
+  int n_gplan = 0;
   // this set's part of a multi-detector plan (from ants_autotune_multi),
   // valid for the grid configuration whose hash is mplan_key
   uint64_t mplan_key = 0;

@@ -170,6 +170,37 @@ hipError_t launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
+uint64_t grid_cfg_key(const ants_grid_cfg& c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(c.nodes, sizeof(c.nodes));
+  mix(&c.iterations, sizeof(c.iterations));
+  mix(&c.stat, sizeof(c.stat));
+  mix(&c.start, sizeof(c.start));
+  mix(&c.screen_scale, sizeof(c.screen_scale));
+  mix(&c.seed_steps, sizeof(c.seed_steps));
+  mix(&c.cut_signal, sizeof(c.cut_signal));
+  mix(&c.cut_distance, sizeof(c.cut_distance));
+  return h | 1;
+}
+
+void apply_grid_plan(const ants_lrfset* S, const ants_grid_cfg* cfg, GridP* G) {
+  const uint64_t k = grid_cfg_key(*cfg);
+  for (int i = 0; i < S->n_gplan; ++i)
+    if (S->gplan[i].key == k) {
+      G->plan_wpb = S->gplan[i].wpb;
+      G->plan_bpc = S->gplan[i].bpc;
+      G->plan_screen = S->gplan[i].screen;
+      return;
+    }
+}
+
 ants_status grid_params(const DevLrf& L, const ants_grid_cfg* cfg, GridP* Gp) {
   GridP& G = *Gp;
   memset(&G, 0, sizeof(G));
@@ -644,6 +675,7 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
   GridP G;
   ants_status st = ants::grid_params(L, cfg, &G);
   if (st != ANTS_OK) return st;
+  ants::apply_grid_plan(set, cfg, &G);
   if (cfg->start == ANTS_START_SEED && !d_seeds)
     return fail(ANTS_E_ARG, "start = SEED needs d_seeds");
   if (n_events == 0) return ANTS_OK;
@@ -676,6 +708,110 @@ ants_status ants_reconstruct(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t
   hipError_t e = ants::launch_grid(L, G, io, (hipStream_t)hip_stream, ants::num_cu() * 8);
   if (e != hipSuccess) return hip_fail(e, "ants_reconstruct launch");
   return ANTS_OK;
+}
+
+ants_status ants_set_plan(ants_lrfset* set, const ants_grid_cfg* cfg,
+                          const ants_grid_plan* plan) {
+  if (!set || !cfg) return fail(ANTS_E_ARG, "ants_set_plan: NULL set or cfg");
+  const uint64_t k = ants::grid_cfg_key(*cfg);
+  int slot = -1;
+  for (int i = 0; i < set->n_gplan; ++i)
+    if (set->gplan[i].key == k) slot = i;
+  if (!plan) {   // remove
+    if (slot >= 0) {
+      for (int i = slot + 1; i < set->n_gplan; ++i) set->gplan[i - 1] = set->gplan[i];
+      --set->n_gplan;
+    }
+    return ANTS_OK;
+  }
+  if (plan->waves_per_block != 1 && plan->waves_per_block != 2 && plan->waves_per_block != 4)
+    return fail(ANTS_E_ARG, "waves_per_block = %d must be 1, 2 or 4", plan->waves_per_block);
+  if (plan->blocks_per_cu < 0 || plan->blocks_per_cu > 32)
+    return fail(ANTS_E_ARG, "blocks_per_cu = %d outside 0..32", plan->blocks_per_cu);
+  if (plan->screen != 0 && plan->screen != 1)
+    return fail(ANTS_E_ARG, "screen = %d must be 0 or 1", plan->screen);
+  if (slot < 0) {
+    if (set->n_gplan == 8) {   // full: drop the oldest
+      for (int i = 1; i < 8; ++i) set->gplan[i - 1] = set->gplan[i];
+      set->n_gplan = 7;
+    }
+    slot = set->n_gplan++;
+  }
+  set->gplan[slot] = {k, plan->waves_per_block, plan->blocks_per_cu, plan->screen};
+  return ANTS_OK;
+}
+
+ants_status ants_autotune(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t n_sample,
+                          const float* d_signals, const float* d_seeds, ants_out scratch,
+                          ants_grid_plan* best, double* host_ms, void* hip_stream) {
+  if (!set || !cfg || !best) return fail(ANTS_E_ARG, "ants_autotune: NULL set, cfg or best");
+  if (n_sample < 1 || n_sample > ((int64_t)1 << 31) - 1)
+    return fail(ANTS_E_ARG, "n_sample = %lld out of range", (long long)n_sample);
+  GridP G;
+  ants_status st = ants::grid_params(set->d, cfg, &G);
+  if (st != ANTS_OK) return st;
+  if (cfg->start == ANTS_START_SEED && !d_seeds)
+    return fail(ANTS_E_ARG, "start = SEED needs d_seeds");
+  if (!d_signals || !scratch.x || !scratch.y || !scratch.z || !scratch.E || !scratch.lnl ||
+      !scratch.chi2 || !scratch.ndf || !scratch.status)
+    return fail(ANTS_E_ARG, "NULL signals or scratch output");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev != set->device) return fail(ANTS_E_ARG, "LRF set lives on another device");
+  IoP io;
+  memset(&io, 0, sizeof(io));
+  io.sig = d_signals;
+  io.ld = set->ns;
+  io.seeds = d_seeds;
+  io.x = scratch.x;
+  io.y = scratch.y;
+  io.z = scratch.z;
+  io.E = scratch.E;
+  io.lnl = scratch.lnl;
+  io.chi2 = scratch.chi2;
+  io.ndf = scratch.ndf;
+  io.status = scratch.status;
+  io.n = n_sample;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return fail(ANTS_E_DEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(ANTS_E_DEVICE, "hipEventCreate failed");
+  }
+  // candidates: screen variant (where the column-factored one applies),
+  // waves per block, cap on blocks per CU; the kernel alone is timed
+  const bool fact = set->d.kind == ANTS_LRF_RZ && cfg->stat == ANTS_STAT_ML &&
+                    set->d.na <= 64 && (G.nz == 3 || G.nz == 5 || G.nz == 7);
+  const int W[3] = {4, 2, 1}, B[2] = {0, 2};
+  float best_ms = HUGE_VALF;
+  int k = 0;
+  hipError_t e = hipSuccess;
+  for (int sc = 0; sc <= (fact ? 1 : 0) && e == hipSuccess; ++sc)
+    for (int wi = 0; wi < 3 && e == hipSuccess; ++wi)
+      for (int bi = 0; bi < 2 && e == hipSuccess; ++bi) {
+        G.plan_screen = sc;
+        G.plan_wpb = W[wi];
+        G.plan_bpc = B[bi];
+        e = ants::launch_grid(set->d, G, io, s, ants::num_cu() * 8);   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = ants::launch_grid(set->d, G, io, s, ants::num_cu() * 8);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) break;
+        if (host_ms) host_ms[k] = ms;
+        ++k;
+        if (ms < best_ms) {
+          best_ms = ms;
+          *best = ants_grid_plan{W[wi], B[bi], sc};
+        }
+      }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(e, "ants_autotune");
+  return ants_set_plan(set, cfg, best);
 }
 
 ants_status ants_generate(ants_lrfset* set, const ants_gen_cfg* cfg, int64_t n_events,

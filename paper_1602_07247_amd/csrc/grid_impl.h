@@ -1660,9 +1660,14 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   if (KIND == ANTS_LRF_AXIAL || KIND == ANTS_LRF_COMPOSITE) btab_n = L.ntab * L.nintp;
   if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
   const int per_wave = wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT, FZ ? G.nx * G.ny : 0);
-  size_t smem = (size_t)btab_n * 16 + (size_t)kWavesPerBlock * per_wave;
+  // waves (events in flight) per block and a cap on resident blocks per
+  // CU from the set's launch plan
+  const int wpb = (G.plan_wpb >= 1 && G.plan_wpb <= kWavesPerBlock) ? G.plan_wpb : kWavesPerBlock;
+  if (G.plan_bpc > 0 && (int64_t)G.plan_bpc * num_cu() < max_blocks)
+    max_blocks = G.plan_bpc * num_cu();
+  size_t smem = (size_t)btab_n * 16 + (size_t)wpb * per_wave;
   int64_t nwork = io.n;
-  int64_t blocks = (nwork + kWavesPerBlock - 1) / kWavesPerBlock;
+  int64_t blocks = (nwork + wpb - 1) / wpb;
   auto kern = cg_kernel<KIND, STAT, NT, SL, NN, FZ>;
   if (smem > 65536) {
     hipError_t st = hipFuncSetAttribute((const void*)kern,
@@ -1672,16 +1677,16 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   // waves stride over the events: launch no more blocks than are resident
   // at once, so that no block starts after the others have finished
   int resident = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, 64 * kWavesPerBlock, smem) ==
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, 64 * wpb, smem) ==
           hipSuccess &&
       resident > 0 && (int64_t)resident * num_cu() < max_blocks)
     max_blocks = resident * num_cu();
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
   if (blocks > 8) blocks = blocks / 8 * 8;   // XCD-aware work order (see cg_kernel)
-  int64_t waves_total = blocks * kWavesPerBlock;
+  int64_t waves_total = blocks * wpb;
   KArgs A{L, G, io, waves_total, per_wave, btab_n};
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), smem, stream, A);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * wpb), smem, stream, A);
   return hipGetLastError();
 }
 
@@ -1699,10 +1704,14 @@ hipError_t launch_fz(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t
 
 template <int KIND, int STAT, int SL, bool NN>
 hipError_t launch_kss(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
+  // r-z, ML: the column-factored screen for 3, 5 or 7 z planes, unless
+  // the launch plan asks for the per-node screen
   if constexpr (KIND == ANTS_LRF_RZ && STAT == ANTS_STAT_ML && SL == 1) {
-    if (G.nz == 3) return launch_fz<KIND, STAT, SL, NN, 3>(L, G, io, s, mb);
-    if (G.nz == 5) return launch_fz<KIND, STAT, SL, NN, 5>(L, G, io, s, mb);
-    if (G.nz == 7) return launch_fz<KIND, STAT, SL, NN, 7>(L, G, io, s, mb);
+    if (G.plan_screen != 1) {
+      if (G.nz == 3) return launch_fz<KIND, STAT, SL, NN, 3>(L, G, io, s, mb);
+      if (G.nz == 5) return launch_fz<KIND, STAT, SL, NN, 5>(L, G, io, s, mb);
+      if (G.nz == 7) return launch_fz<KIND, STAT, SL, NN, 7>(L, G, io, s, mb);
+    }
   }
   switch (node_tiles(G.nn)) {
     case 1: return launch_t<KIND, STAT, 1, SL, NN>(L, G, io, s, mb);

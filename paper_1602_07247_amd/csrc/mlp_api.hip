@@ -538,6 +538,8 @@ ants_status seeded_check(ants_lrfset* S, ants_mlp* M, const ants_grid_cfg* refin
   if (st != ANTS_OK) return st;
   st = grid_params(S->d, fallback, Gf);
   if (st != ANTS_OK) return st;
+  apply_grid_plan(S, refine, Gr);
+  apply_grid_plan(S, fallback, Gf);
   if (n == 0) return ANTS_OK;
   if (!d_signals || !out.x || !out.y || !out.z || !out.E || !out.lnl || !out.chi2 || !out.ndf ||
       !out.status)

@@ -25,27 +25,6 @@ struct MPlan {
   std::vector<int> T, lds;
 };
 
-// Key of a grid configuration in a set's plan (the fields that change the
-// work per event).
-uint64_t cfg_key(const ants_grid_cfg& c) {
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&](const void* p, size_t n) {
-    const unsigned char* b = (const unsigned char*)p;
-    for (size_t i = 0; i < n; ++i) {
-      h ^= b[i];
-      h *= 1099511628211ull;
-    }
-  };
-  mix(c.nodes, sizeof(c.nodes));
-  mix(&c.iterations, sizeof(c.iterations));
-  mix(&c.stat, sizeof(c.stat));
-  mix(&c.start, sizeof(c.start));
-  mix(&c.screen_scale, sizeof(c.screen_scale));
-  mix(&c.cut_signal, sizeof(c.cut_signal));
-  mix(&c.cut_distance, sizeof(c.cut_distance));
-  return h | 1;   // never 0 (0 = no plan)
-}
-
 ants_status prepare(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n_sets,
                     const ants_chunk* ch, int n_chunks, Prepared* P) {
   if (!S || !cfgs || !ch) return set_error(ANTS_E_ARG, "NULL sets, configurations or chunks");
@@ -214,11 +193,11 @@ MPlan stored_plan(ants_lrfset* const* S, const ants_grid_cfg* cfgs, int n) {
   pl.T.assign(n, 32);
   pl.lds.assign(n, 1);
   for (int i = 0; i < n; ++i)
-    if (S[i]->mplan_key == cfg_key(cfgs[i]) && S[i]->mplan_T > 0) {
+    if (S[i]->mplan_key == grid_cfg_key(cfgs[i]) && S[i]->mplan_T > 0) {
       pl.T[i] = S[i]->mplan_T;
       pl.lds[i] = S[i]->mplan_lds;
     }
-  if (S[0]->mplan_key == cfg_key(cfgs[0]) && S[0]->mplan_bpc > 0) pl.bpc = S[0]->mplan_bpc;
+  if (S[0]->mplan_key == grid_cfg_key(cfgs[0]) && S[0]->mplan_bpc > 0) pl.bpc = S[0]->mplan_bpc;
   return pl;
 }
 
@@ -347,7 +326,7 @@ ants_status ants_autotune_multi(ants_lrfset* const* sets, const ants_grid_cfg* c
   hipEventDestroy(b);
   if (st != ANTS_OK) return st;
   for (int i = 0; i < n_sets; ++i) {
-    sets[i]->mplan_key = cfg_key(cfgs[i]);
+    sets[i]->mplan_key = grid_cfg_key(cfgs[i]);
     sets[i]->mplan_T = cur.T[i];
     sets[i]->mplan_lds = cur.lds[i];
     sets[i]->mplan_bpc = cur.bpc;

@@ -388,20 +388,41 @@ def xy_step(args):
     sig, truth = ants.generate(lrf, ants.gen_cfg(wl.events), n, args.seed)
     evals = int(np.prod(wl.grid.nodes)) * 64 * wl.grid.iterations
     res = {}
+    nt = min(n, 250_000)
     for stat, name, fpe in ((0, "ml", FLOP_PER_EVAL_XY_ML), (1, "chi2", FLOP_PER_EVAL_XY_CHI2)):
         g = ants.grid_cfg(W.GridCfg(**{**wl.grid.__dict__, "stat": stat}))
+        # the per-node screen reading the coefficients through the cache,
+        # for comparison with the LDS-staged factored screen
+        ants.set_plan(lrf, g, ants.GridPlan(4, 0, 1))
+        out_c = ants.alloc_out(n)
+        wall_c, ev_c = timed(lambda: ants.reconstruct(lrf, g, sig, out=out_c, stream=stream),
+                             max(2, args.steps // 2), 1, stream)
+        ants.set_plan(lrf, g, None)
+        plan, cand_ms = ants.autotune(lrf, g, sig[:nt].contiguous(), stream=stream)
         out = ants.alloc_out(n)
         wall, ev = timed(lambda: ants.reconstruct(lrf, g, sig, out=out, stream=stream),
                          args.steps, args.warmup, stream)
+        same = all(bool(torch.equal(out[k], out_c[k]))
+                   for k in ("x", "y", "E", "status"))
         sx = sigma_xy(out, truth)
         flops = n * evals * fpe
         ach = flops / (ev * 1e-3) / 1e12
+        ach_c = flops / (ev_c * 1e-3) / 1e12
         res[name] = {"events_per_s": n / wall, "ms_per_step": 1e3 * wall, "sigma_xy_mm": sx[0],
+                     "plan": {"waves_per_block": plan.waves_per_block,
+                              "blocks_per_cu": plan.blocks_per_cu,
+                              "screen": "per-node (cache)" if plan.screen else
+                                        "factored (LDS-staged rows)",
+                              "candidate_ms": [round(float(v), 4) for v in cand_ms if v > 0]},
+                     "cache_variant": {"events_per_s": n / wall_c, "kernel_ms": ev_c,
+                                       "frac": ach_c / PEAK_FP32_TFLOPS,
+                                       "identical_outputs": same},
                      "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                                   "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
                                   "traffic": None, "kernel_ms": ev, "flop_per_launch": flops,
                                   "flop_per_eval": fpe,
-                                  "kernel": "cg_kernel<XY,%s,NT=2,SL=1>" % name.upper()}}
+                                  "kernel": "cg_kernel<XY,%s,NT=2,SL=1,%s>" %
+                                            (name.upper(), "FZ=0" if plan.screen else "FZ=1")}}
     rec = {"metric": "events/s reconstructed, 8x8 array with per-sensor bicubic LRFs, 1 MI355X",
            "value": res["ml"]["events_per_s"], "unit": "events/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ml"]["ms_per_step"],

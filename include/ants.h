@@ -230,9 +230,14 @@ typedef struct {
   int32_t waves_per_block;   /* events in flight per block: 1, 2 or 4 (default 4) */
   int32_t blocks_per_cu;     /* cap on resident blocks per compute unit; 0 = as many
                                 as fit (default)                                   */
-  int32_t screen;            /* 0 (default): the column-factored r-z screen where it
-                                applies (ML, 3, 5 or 7 z planes, <= 64 active
-                                sensors); 1: the per-node screen                   */
+  int32_t screen;            /* 0 (default): a factored screen where one applies:
+                                r-z column-factored (ML, 3, 5 or 7 z planes, <= 64
+                                active sensors), or XY with each sensor's
+                                coefficients collapsed along y for the grid's node
+                                rows and staged in LDS (one z plane, <= 64 node
+                                columns and rows, rows x nc0 <= 1536); 1: the
+                                per-node screen (XY: coefficients read through the
+                                cache)                                             */
 } ants_grid_plan;
 
 /* Autotuner (per set and grid configuration): times the candidate plans

@@ -44,8 +44,8 @@ __host__ __device__ inline int cval_place(int na, int nz, int nt, int fact_nxy) 
   if (fact_nxy > 0 && 8 * nz * (fact_nxy > 64 ? fact_nxy : 64) >= need) return 2;
   return 0;
 }
-inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt,
-                          int fact_nxy = 0) {
+__host__ __device__ inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt,
+                                              int fact_nxy = 0) {
   int b = 64 * na + 256 * nt + 24 * kMaxSeedSteps;
   if (cval_place(na, nz, nt, fact_nxy) == 0) b += 512 * nt;
   if (fact_nxy > 0) b += 8 * nz * (fact_nxy > 64 ? fact_nxy : 64) + 128;
@@ -55,6 +55,12 @@ inline int wave_lds_bytes(int kind, int na, int nz, int nintp, int nc0, int nt,
   }
   return (b + 15) & ~15;
 }
+
+// XY factored screen: per wave, the y-collapsed coefficient rows of a chunk
+// of sensors (kXfFloats floats), and the y-weights and first coefficient
+// row of up to 64 node rows.
+constexpr int kXfFloats = 1536;
+constexpr int kXfBytes = 4 * kXfFloats + 64 * 16 + 64 * 4;
 
 // Device-resident view of an LRF set.  Sensors are the active ones only,
 // in their original order ("compact index" a = 0..na-1).
@@ -129,10 +135,18 @@ struct GridP {
   double fb_thr;       // >= 0: events with chi2/ndf above it go to the fallback list
   int or_status;       // status bits OR-ed into every processed event
   // launch plan (host side; see ants_grid_plan): waves per block (0 = 4),
-  // cap on blocks per CU (0 = as many as fit), screen (0 = column-factored
-  // where it applies, 1 = per node)
+  // cap on blocks per CU (0 = as many as fit), screen (0 = factored where it
+  // applies: r-z columns, or XY rows staged in LDS; 1 = per node)
   int plan_wpb, plan_bpc, plan_screen;
 };
+
+// The XY factored screen applies to single-plane grids of at most 64 node
+// columns and rows whose y-collapsed rows of one sensor fit the staging area
+// (at most nc0 coefficients per row).
+inline bool xf_applies(const DevLrf& L, const GridP& G) {
+  return L.kind == ANTS_LRF_XY && G.nz == 1 && G.nx <= 64 && G.ny <= 64 &&
+         G.ny * L.nc0 <= kXfFloats;
+}
 
 struct IoP {
   const float* sig;    // [n][ns]

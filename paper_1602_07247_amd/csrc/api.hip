@@ -781,8 +781,9 @@ ants_status ants_autotune(ants_lrfset* set, const ants_grid_cfg* cfg, int64_t n_
   }
   // candidates: screen variant (where the column-factored one applies),
   // waves per block, cap on blocks per CU; the kernel alone is timed
-  const bool fact = set->d.kind == ANTS_LRF_RZ && cfg->stat == ANTS_STAT_ML &&
-                    set->d.na <= 64 && (G.nz == 3 || G.nz == 5 || G.nz == 7);
+  const bool fact = (set->d.kind == ANTS_LRF_RZ && cfg->stat == ANTS_STAT_ML &&
+                     set->d.na <= 64 && (G.nz == 3 || G.nz == 5 || G.nz == 7)) ||
+                    ants::xf_applies(set->d, G);
   const int W[3] = {4, 2, 1}, B[2] = {0, 2};
   float best_ms = HUGE_VALF;
   int k = 0;

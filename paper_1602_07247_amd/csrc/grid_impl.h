@@ -331,8 +331,11 @@ struct WaveLds {
                        // overlaying storage that is dead during the decisions
   float* fscr;         // factored r-z screen: partial sums [group][column][plane][2]
   uint16_t* lanecg;    // factored r-z screen: column | group << 8 per lane
+  float* xf;           // XY factored screen: y-collapsed rows [sensor][node row][column]
+  float4* xroww;       // XY factored screen: y-weights of each node row
+  int* xrowm;          // XY factored screen: first coefficient row of each node row
 };
-template <int KIND, int NT, bool FA = false>
+template <int KIND, int NT, bool FA = false, bool FX = false>
 __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& L,
                                             const GridP& G) {
   WaveLds w;
@@ -361,16 +364,25 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* wbase, const DevLrf& 
   w.cand = (uint16_t*)(w.pm + nzp);
   w.nodeidx = w.cand + 64 * NT;
   w.lanecg = w.nodeidx + 64 * NT;
+  w.xf = nullptr;
+  w.xroww = nullptr;
+  w.xrowm = nullptr;
+  if constexpr (FX) {
+    // after everything else (that size is a multiple of 16 bytes)
+    w.xf = (float*)(wbase + wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT, 0));
+    w.xroww = (float4*)(w.xf + kXfFloats);
+    w.xrowm = (int*)(w.xroww + 64);
+  }
   return w;
 }
 
 // Per-wave set-up: node index table and, for seeded refinement, the final
 // step divided by the shrink factor k times (iterated quotients), k <
 // kMaxSeedSteps, per axis.
-template <int KIND, int NT, bool FA = false>
+template <int KIND, int NT, bool FA = false, bool FX = false>
 __device__ __forceinline__ void wave_setup(unsigned char* wbase, const DevLrf& L, const GridP& G,
                                            int lane) {
-  const WaveLds w = wave_lds<KIND, NT, FA>(wbase, L, G);
+  const WaveLds w = wave_lds<KIND, NT, FA, FX>(wbase, L, G);
   fill_nodeidx(G, w.nodeidx, 64 * NT, lane);
   if constexpr (FA) {
     // factored screen: lane -> (column of the x-y lattice, sensor group);
@@ -516,12 +528,15 @@ template <int KIND, int STAT, int NT, int SL, bool NN, int FZ, class Src>
 __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
                                               const float4* btab, unsigned char* wbase,
                                               const int lane) {
-  constexpr bool FA = FZ > 0;
+  // FZ > 0: r-z, the column-factored screen over FZ z-planes; XY, the
+  // screen from y-collapsed coefficient rows staged in LDS
+  constexpr bool FA = FZ > 0 && KIND == ANTS_LRF_RZ;
+  constexpr bool FX = FZ > 0 && KIND == ANTS_LRF_XY;
   const ParView V0 = src.view();
   const DevLrf& L = V0.L;
   const GridP& G = V0.G;
   const IoP& io = V0.io;
-  const WaveLds W = wave_lds<KIND, NT, FA>(wbase, L, G);
+  const WaveLds W = wave_lds<KIND, NT, FA, FX>(wbase, L, G);
   float4* recA = W.recA;
   float4* recB = W.recB;
   SensorRec64* rec64 = W.rec64;
@@ -918,10 +933,11 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
     // grids of at most 32 nodes split the sensors between the two halves of
     // the wave: lanes l and l + 32 both hold node l, each sums over every
     // other sensor, and the halves add their sums
-    const bool split = !FA && NT == 1 && G.nn <= 32;
+    const bool split = !FA && !FX && NT == 1 && G.nn <= 32;
     // with several tiles and at most 32 nodes in the last one (ML screen),
     // only the last tile is split that way
-    const bool lsplit = !FA && STAT == ANTS_STAT_ML && NT >= 2 && G.nn - 64 * (NT - 1) <= 32;
+    const bool lsplit =
+        !FA && !FX && STAT == ANTS_STAT_ML && NT >= 2 && G.nn - 64 * (NT - 1) <= 32;
     const int hb = (split || lsplit) ? (lk >> 5) : 0;
     const int pstep = split ? 2 : 1;
     NodeF<KIND> nd[NT];
@@ -934,6 +950,103 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       valid[t] = make_node<KIND>(L, G, cx, cy, cz, sx, sy, sz, j, ztab, nodeidx, nd[t], xx, yy, zz);
       if (half) valid[t] = valid[t] && lk < 32;
     }
+    // XY factored screen.  Every sensor's bicubic is on the same knot grid,
+    // so a node's x-weights and first coefficient column depend on its
+    // column only and its y-weights and first row on its row only.  Each
+    // sensor's coefficients are collapsed along y once per node row (over
+    // the columns the grid touches) and staged in LDS; a node then reads 4
+    // values and applies its 4 x-weights.  Here: the x-weights and offset of
+    // each node, and the y-weights and first row of each node row.
+    float4 xw[NT];
+    int xoff[NT];
+    int xm0 = 0, xwc = 4;
+    if constexpr (FX) {
+      int m0t[NT], jyt[NT];
+      int mlo = 1 << 30, mhi = -1;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int j = t * 64 + lk;
+        const int pk = nodeidx[j];
+        const int jx = pk & G.mskx, jy = (pk >> G.shy) & G.msky;
+        const double x = cx + (double)(jx - G.hx) * sx;
+        const double y = cy + (double)(jy - G.hy) * sy;
+        int m0 = 0, m1 = 0;
+        double t0 = 0.0, t1 = 0.0, b0[4];
+        const bool inx = locate64(x, L.nb0, L.lo0, L.hi0, L.inv_d0, m0, t0);
+        const bool iny = locate64(y, L.nb1, L.lo1, L.hi1, L.inv_d1, m1, t1);
+        bweights64(t0, b0);
+        xw[t] = make_float4((float)b0[0], (float)b0[1], (float)b0[2], (float)b0[3]);
+        m0t[t] = inx ? m0 : -1;
+        jyt[t] = jy;
+        if (j < G.nn && inx) {
+          mlo = m0 < mlo ? m0 : mlo;
+          mhi = m0 > mhi ? m0 : mhi;
+        }
+        if (j < G.nn && jx == 0) {
+          double b1[4];
+          bweights64(t1, b1);
+          W.xroww[jy] = make_float4((float)b1[0], (float)b1[1], (float)b1[2], (float)b1[3]);
+          W.xrowm[jy] = iny ? m1 : 0;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const int a = __shfl_xor(mlo, o), b = __shfl_xor(mhi, o);
+        mlo = a < mlo ? a : mlo;
+        mhi = b > mhi ? b : mhi;
+      }
+      mlo = uni(mlo);
+      mhi = uni(mhi);
+      if (mhi < 0) mlo = mhi = 0;   // no node column inside the domain
+      xm0 = mlo;
+      xwc = mhi - mlo + 4;
+      // columns outside the domain (invalid nodes) read the first column
+#pragma unroll
+      for (int t = 0; t < NT; ++t) xoff[t] = jyt[t] * xwc + (m0t[t] >= 0 ? m0t[t] - xm0 : 0);
+      wave_sync_lds();
+    }
+    const int xstride = G.ny * xwc;   // floats per staged sensor
+    const int xcap = FX ? uni(kXfFloats / xstride) : 1;   // sensors per chunk (>= 1)
+    const float xinv_wc = FX ? 1.0f / (float)xwc : 1.0f;
+    // stage records [p0, p0 + cnt): row jy of sensor p at p * xstride + jy *
+    // xwc; lanes take (sensor, column), node rows go in threes with their
+    // 12 loads issued together
+    auto xf_stage = [&](int p0, int cnt) {
+      if constexpr (FX) {
+        const int total = cnt * xwc;
+        const int nc0 = L.nc0, ny = G.ny;
+        for (int i = lk; i < total; i += 64) {
+          const int pp = (int)(((float)i + 0.5f) * xinv_wc);
+          const int col = i - pp * xwc;
+          const float* src = L.c32 + __float_as_int(recB[p0 + pp].z) + xm0 + col;
+          float* dst = W.xf + pp * xstride + col;
+          for (int jy0 = 0; jy0 < ny; jy0 += 3) {
+            float4 w[3];
+            float c[3][4];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+              const int jy = jy0 + u < ny ? jy0 + u : ny - 1;   // in bounds; not stored
+              w[u] = W.xroww[jy];
+              const float* q = src + W.xrowm[jy] * nc0;
+#pragma unroll
+              for (int a = 0; a < 4; ++a) c[u][a] = q[a * nc0];
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+              if (jy0 + u < ny)
+                dst[(jy0 + u) * xwc] =
+                    fmaf(w[u].w, c[u][3], fmaf(w[u].z, c[u][2], fmaf(w[u].y, c[u][1], w[u].x * c[u][0])));
+          }
+        }
+        wave_sync_lds();
+      }
+    };
+    // LRF of node tile t from sensor p's staged rows (base at chunk record p0)
+    auto xf_lrf = [&](const float* rows, int t) -> float {
+      const float* r = rows + xoff[t];
+      return fmaxf(fmaf(xw[t].w, r[3], fmaf(xw[t].z, r[2], fmaf(xw[t].y, r[1], xw[t].x * r[0]))),
+                   0.f);
+    };
 
     // ---- FP32 screen
     float D[NT], Snode[NT];
@@ -941,7 +1054,34 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       float dS[NT], T[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) { dS[t] = 0.f; T[t] = 0.f; }
-      if constexpr (FA) {
+      if constexpr (FX) {
+        // chunks of staged sensors; XY has no edge classes: counted sensors
+        // are [0, n_ci), zero-signal ones [n_pos, z_end)
+        for (int p0 = 0; p0 < z_end; p0 += xcap) {
+          const int p1 = p0 + xcap < z_end ? p0 + xcap : z_end;
+          xf_stage(p0, p1 - p0);
+          const int pc = p1 < n_ci ? p1 : n_ci;
+#pragma unroll 2
+          for (int p = p0; p < pc; ++p) {
+            const float4 A = recA[p], B = recB[p];
+            const float* rows = W.xf + (p - p0) * xstride;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              const float Lv = xf_lrf(rows, t);
+              dS[t] = fmaf(B.x, Lv - B.y, dS[t]);
+              T[t] = fmaf(A.z, __builtin_amdgcn_logf(Lv * A.w), T[t]);
+            }
+          }
+#pragma unroll 2
+          for (int p = p0 > n_pos ? p0 : n_pos; p < p1; ++p) {
+            const float4 B = recB[p];
+            const float* rows = W.xf + (p - p0) * xstride;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) dS[t] = fmaf(B.x, xf_lrf(rows, t) - B.y, dS[t]);
+          }
+          wave_sync_lds();
+        }
+      } else if constexpr (FA) {
         // r-z, 2 to 8 z-planes: the distance from a sensor depends on the
         // node's x-y column only, so lanes take (column, sensor group) and
         // evaluate every plane from one distance; the groups' partial sums
@@ -1218,6 +1358,40 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
       float S[NT], Q[NT], Ag[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) { S[t] = 0.f; Q[t] = 0.f; }
+      if constexpr (FX) {
+        // sums, then Pearson terms, over chunks of staged sensors (staged
+        // once when every screened sensor fits one chunk)
+        const bool one = n_scr <= xcap;
+        for (int p0 = 0; p0 < n_scr; p0 += xcap) {
+          const int p1 = p0 + xcap < n_scr ? p0 + xcap : n_scr;
+          xf_stage(p0, p1 - p0);
+          for (int p = p0; p < p1; ++p) {
+            const float4 B = recB[p];
+            const float* rows = W.xf + (p - p0) * xstride;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) S[t] = fmaf(B.x, xf_lrf(rows, t), S[t]);
+          }
+          if (!one) wave_sync_lds();
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Ag[t] = S[t] > 0.f ? N32 / S[t] : 0.f;
+        for (int p0 = 0; p0 < n_scr; p0 += xcap) {
+          const int p1 = p0 + xcap < n_scr ? p0 + xcap : n_scr;
+          if (!one) xf_stage(p0, p1 - p0);
+          for (int p = p0; p < p1; ++p) {
+            const float4 A = recA[p], B = recB[p];
+            const float* rows = W.xf + (p - p0) * xstride;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              const float mu = Ag[t] * B.x * xf_lrf(rows, t);
+              const float dd = A.z - mu;
+              const float v = fmaxf(mu, fvf);
+              Q[t] = fmaf(dd * dd, __builtin_amdgcn_rcpf(v), Q[t]);
+            }
+          }
+          wave_sync_lds();
+        }
+      } else {
       int p = 0;
       for (; p + pstep <= n_scr; p += pstep) {
         float4 A = recA[p + hb], B = recB[p + hb];
@@ -1259,6 +1433,7 @@ __device__ __forceinline__ void process_event(const Src& src, const int64_t e,
         Q[0] = fmaf(hb ? 0.f : dd * dd, __builtin_amdgcn_rcpf(v), Q[0]);
       }
       if (split) Q[0] += __shfl_xor(Q[0], 32);
+      }
       // nodes at the domain end of an edge sensor go to FP64 (untrusted)
       bool knife[NT];
 #pragma unroll
@@ -1620,7 +1795,8 @@ cg_kernel(KArgs A) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwb = blockDim.x >> 6;
   unsigned char* wbase = (unsigned char*)(smem4 + btab_n) + (size_t)wv * per_wave_bytes;
-  wave_setup<KIND, NT, (FZ > 0)>(wbase, L, G, lane0);
+  wave_setup<KIND, NT, (FZ > 0 && KIND == ANTS_LRF_RZ), (FZ > 0 && KIND == ANTS_LRF_XY)>(
+      wbase, L, G, lane0);
   int64_t nwork = io.list ? (int64_t)(*io.list_n) : io.n;
   // one node tile (small grids, the seeded refinement): parameters re-read
   // per event and stage (measured 3.5% faster); more tiles: held in
@@ -1659,7 +1835,9 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   int btab_n = 0;
   if (KIND == ANTS_LRF_AXIAL || KIND == ANTS_LRF_COMPOSITE) btab_n = L.ntab * L.nintp;
   if (KIND == ANTS_LRF_RZ) btab_n = L.nc1 * L.nintp;
-  const int per_wave = wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT, FZ ? G.nx * G.ny : 0);
+  constexpr bool fa = FZ > 0 && KIND == ANTS_LRF_RZ, fx = FZ > 0 && KIND == ANTS_LRF_XY;
+  const int per_wave = wave_lds_bytes(KIND, L.na, G.nz, L.nintp, L.nc0, NT, fa ? G.nx * G.ny : 0) +
+                       (fx ? kXfBytes : 0);
   // waves (events in flight) per block and a cap on resident blocks per
   // CU from the set's launch plan
   const int wpb = (G.plan_wpb >= 1 && G.plan_wpb <= kWavesPerBlock) ? G.plan_wpb : kWavesPerBlock;
@@ -1690,7 +1868,8 @@ hipError_t launch_t(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t 
   return hipGetLastError();
 }
 
-// column-factored r-z screen for FZ z-planes
+// factored screens: r-z column-factored for FZ z-planes; XY (FZ = 1) from
+// y-collapsed rows staged in LDS
 template <int KIND, int STAT, int SL, bool NN, int FZ>
 hipError_t launch_fz(const DevLrf& L, const GridP& G, const IoP& io, hipStream_t s, int mb) {
   switch (node_tiles(G.nn)) {
@@ -1712,6 +1891,9 @@ hipError_t launch_kss(const DevLrf& L, const GridP& G, const IoP& io, hipStream_
       if (G.nz == 5) return launch_fz<KIND, STAT, SL, NN, 5>(L, G, io, s, mb);
       if (G.nz == 7) return launch_fz<KIND, STAT, SL, NN, 7>(L, G, io, s, mb);
     }
+  }
+  if constexpr (KIND == ANTS_LRF_XY) {
+    if (G.plan_screen != 1 && xf_applies(L, G)) return launch_fz<KIND, STAT, SL, NN, 1>(L, G, io, s, mb);
   }
   switch (node_tiles(G.nn)) {
     case 1: return launch_t<KIND, STAT, 1, SL, NN>(L, G, io, s, mb);

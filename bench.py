@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="rz",
-                    choices=["rz", "mixed", "lrf_fit", "simplex", "knn", "xy"],
+                    choices=["rz", "mixed", "lrf_fit", "simplex", "knn", "xy", "train"],
                     help="rz: the headline comparison; mixed: 19/61/127-sensor stream in one "
                          "persistent launch; lrf_fit: one step of the iterative LRF "
                          "reconstruction (reconstruct + refit) on the 61-sensor detector; "
@@ -434,6 +434,45 @@ def xy_step(args):
     print(json.dumps(rec), flush=True)
 
 
+def train_step(args):
+    """Training of the seed network as in the headline benchmark (37 inputs
+    padded to 64, three hidden layers of 256, BF16 products on the matrix
+    cores, Adam, batch 4096) on events drawn on the GPU from the r-z LRFs."""
+    import torch
+    import workloads as W
+    from paper_1602_07247_amd import ants
+    wl = W.workload(2)
+    lrf = ants.LrfSet(wl.lrf)
+    batch = 4096
+    net = ants.Mlp(37, 256, 3, seed=2024, pos_scale=W.SEED_POS_SCALE,
+                   pos_offset=W.SEED_POS_OFFSET)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(lrf, wl.events, args.train_events, args.val_events, batch=batch,
+                       epochs=args.epochs, lr=2e-3, lr_decay=0.85, seed=args.seed + 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps = (args.train_events // batch) * args.epochs
+    # matrix-core work per training event: forward and weight gradients of
+    # every layer, input gradients of the hidden layers after the first
+    dims = [(64, 256), (256, 256), (256, 256), (256, 4)]
+    flop_ev = 2 * (2 * sum(a * b for a, b in dims) + sum(a * b for a, b in dims[1:3]))
+    tflops = flop_ev * batch * steps / wall / 1e12
+    rec = {"metric": "training event-epochs/s (seed network, batch 4096), 1 MI355X",
+           "value": args.train_events * args.epochs / wall, "unit": "event-epochs/s",
+           "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": 1e3 * wall / steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic (events drawn on the GPU from the r-z LRF model), includes "
+                   "event generation and validation passes",
+           "config": {"workload": "37-256x3-4 network, %d training + %d validation events, "
+                                  "%d epochs" % (args.train_events, args.val_events,
+                                                 args.epochs)},
+           "mfma": {"flop_per_event": flop_ev, "achieved_tflops": tflops,
+                    "peak_tflops": 2500.0, "frac": tflops / 2500.0},
+           "final_val_loss": float(losses[-1][1])}
+    print(json.dumps(rec), flush=True)
+
+
 def copy_probe():
     import torch
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
@@ -624,6 +663,9 @@ def main():
         return
     if args.workload == "xy":
         xy_step(args)
+        return
+    if args.workload == "train":
+        train_step(args)
         return
     import torch
     import workloads as W

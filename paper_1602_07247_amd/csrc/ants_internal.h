@@ -220,7 +220,22 @@ struct GemmP {
   int64_t ldcf;
   __bf16* Cb;          // BF16 result or NULL
   int64_t ldcb;
+  // optional FP32 workspace for split-K partial products (ws_n floats);
+  // NULL: no split
+  float* ws;
+  int64_t ws_n;
 };
+// Split of the k range for a GEMM whose output has few 64 x 64 tiles and a
+// long k (weight gradients, k = batch): enough splits to give about 256
+// blocks, each at least 64 deep.
+inline int gemm_splits(int M, int N, int K) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles >= 128 || K < 128) return 1;
+  int s = (256 + tiles - 1) / tiles;
+  if (s > K / 64) s = K / 64;
+  if (s > 64) s = 64;
+  return s < 1 ? 1 : s;
+}
 struct HeadP {
   float scale[3], inv_scale[3], offset[3];
   float inv_batch;

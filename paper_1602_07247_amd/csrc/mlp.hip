@@ -25,7 +25,61 @@ constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;   // LDS row pitch (bf16 
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }   // round to nearest even
 
-__global__ void __launch_bounds__(256) gemm_kernel(GemmP P) {
+// Operand tile staging: a 64 x 32 tile X(r0 + i, k0 + j) into S[i][j] (LDS
+// row pitch LDK), in two halves (global -> registers, registers -> LDS) so
+// the next tile's loads are in flight during the current tile's products.
+// Mode 0: k contiguous (X = base[r * s_r + k]), each thread loads 8
+// consecutive k of one row; mode 1: rows contiguous (base[k * s_k + r], the
+// batch-major operands of the weight gradients), each thread loads 8
+// consecutive rows of one k and writes them down the tile's column; mode 2:
+// any strides, element by element.  Elements past R or K are zero.
+__device__ __forceinline__ bf16x8 load_tile(const __bf16* X, int64_t s_r, int64_t s_k, int R,
+                                            int K, int r0, int k0, int mode, int tid) {
+  bf16x8 v;
+  if (mode == 1) {
+    const int r = r0 + (tid & 7) * 8, k = k0 + (tid >> 3);
+    if (k < K && r + 7 < R) {
+      v = *(const bf16x8*)(X + (int64_t)k * s_k + r);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        v[e] = (k < K && r + e < R) ? X[(int64_t)k * s_k + r + e] : (__bf16)0.f;
+    }
+  } else {
+    const int r = r0 + (tid >> 2), k = k0 + (tid & 3) * 8;
+    if (mode == 0 && r < R && k + 7 < K) {
+      v = *(const bf16x8*)(X + (int64_t)r * s_r + k);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        v[e] = (r < R && k + e < K) ? X[(int64_t)r * s_r + (int64_t)(k + e) * s_k] : (__bf16)0.f;
+    }
+  }
+  return v;
+}
+__device__ __forceinline__ void store_tile(bf16x8 v, int mode, __bf16* S, int tid) {
+  if (mode == 1) {
+    const int lk = tid >> 3, lr = (tid & 7) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) S[(lr + e) * LDK + lk] = v[e];
+  } else {
+    *(bf16x8*)(S + (tid >> 2) * LDK + (tid & 3) * 8) = v;
+  }
+}
+
+__device__ __forceinline__ void gemm_store(const GemmP& P, int m, int n, float v) {
+  if (P.bias) v += P.bias[n];
+  if (P.relu) v = fmaxf(v, 0.f);
+  if (P.mask && !((float)P.mask[(int64_t)m * P.ldmask + n] > 0.f)) v = 0.f;
+  if (P.Cf) P.Cf[(int64_t)m * P.ldcf + n] = v;
+  if (P.Cb) P.Cb[(int64_t)m * P.ldcb + n] = to_bf16(v);
+}
+
+// Block (x, y, z): output tile (n0, m0) over the z-th of gridDim.z equal
+// slices of k (whole BK steps).  One slice: the epilogue is applied here;
+// several: the raw FP32 partial goes to ws[z][m][n] and gemm_reduce_kernel
+// adds the slices in order (deterministic) and applies it.
+__global__ void __launch_bounds__(256) gemm_kernel(GemmP P, int amode, int bmode, int kslice) {
   __shared__ __align__(16) __bf16 As[BM * LDK];
   __shared__ __align__(16) __bf16 Bs[BN * LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -37,38 +91,21 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmP P) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  // each thread stages 8 consecutive k of one row of A and of B
-  const int lr = tid >> 2, lk = (tid & 3) * 8;
-  const bool a_vec = P.sa_k == 1 && (P.sa_m % 8) == 0 && (P.K % 8) == 0;
-  const bool b_vec = P.sb_k == 1 && (P.sb_n % 8) == 0 && (P.K % 8) == 0;
-  for (int k0 = 0; k0 < P.K; k0 += BK) {
-    {
-      const int m = m0 + lr, k = k0 + lk;
-      bf16x8 v;
-      if (a_vec && m < P.M && k + 7 < P.K) {
-        v = *(const bf16x8*)(P.A + (int64_t)m * P.sa_m + k);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          v[e] = (m < P.M && k + e < P.K) ? P.A[(int64_t)m * P.sa_m + (int64_t)(k + e) * P.sa_k]
-                                          : (__bf16)0.f;
-      }
-      *(bf16x8*)(As + lr * LDK + lk) = v;
-    }
-    {
-      const int n = n0 + lr, k = k0 + lk;
-      bf16x8 v;
-      if (b_vec && n < P.N && k + 7 < P.K) {
-        v = *(const bf16x8*)(P.B + (int64_t)n * P.sb_n + k);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          v[e] = (n < P.N && k + e < P.K) ? P.B[(int64_t)n * P.sb_n + (int64_t)(k + e) * P.sb_k]
-                                          : (__bf16)0.f;
-      }
-      *(bf16x8*)(Bs + lr * LDK + lk) = v;
-    }
+  const int kb = blockIdx.z * kslice;
+  const int ke = kb + kslice < P.K ? kb + kslice : P.K;
+  bf16x8 va, vb;
+  if (kb < ke) {
+    va = load_tile(P.A, P.sa_m, P.sa_k, P.M, ke, m0, kb, amode, tid);
+    vb = load_tile(P.B, P.sb_n, P.sb_k, P.N, ke, n0, kb, bmode, tid);
+  }
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    store_tile(va, amode, As, tid);
+    store_tile(vb, bmode, Bs, tid);
     __syncthreads();
+    if (k0 + BK < ke) {
+      va = load_tile(P.A, P.sa_m, P.sa_k, P.M, ke, m0, k0 + BK, amode, tid);
+      vb = load_tile(P.B, P.sb_n, P.sb_k, P.N, ke, n0, k0 + BK, bmode, tid);
+    }
     // operand fragments: lane l holds row (l % 16) and k = 8*(l / 16) .. +7,
     // the same k assignment for A and B
     const int fr = lane & 15, fk = (lane >> 4) * 8;
@@ -85,6 +122,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmP P) {
     __syncthreads();
   }
   // result layout: lane l holds C[4*(l/16) + r][l % 16], r = 0..3
+  float* part = gridDim.z > 1 ? P.ws + (int64_t)blockIdx.z * P.M * P.N : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -94,14 +132,28 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmP P) {
         const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + r;
         const int n = n0 + wc + j * 16 + (lane & 15);
         if (m < P.M && n < P.N) {
-          float v = acc[i][j][r];
-          if (P.bias) v += P.bias[n];
-          if (P.relu) v = fmaxf(v, 0.f);
-          if (P.mask && !((float)P.mask[(int64_t)m * P.ldmask + n] > 0.f)) v = 0.f;
-          if (P.Cf) P.Cf[(int64_t)m * P.ldcf + n] = v;
-          if (P.Cb) P.Cb[(int64_t)m * P.ldcb + n] = to_bf16(v);
+          if (part) part[(int64_t)m * P.N + n] = acc[i][j][r];
+          else gemm_store(P, m, n, acc[i][j][r]);
         }
       }
+}
+
+__global__ void gemm_reduce_kernel(GemmP P, int splits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mn = (int64_t)P.M * P.N;
+  if (i >= mn) return;
+  // slices added in order; loads issued eight at a time
+  float v = 0.f;
+  int z = 0;
+  for (; z + 8 <= splits; z += 8) {
+    float t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = P.ws[(z + u) * mn + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; z < splits; ++z) v += P.ws[z * mn + i];
+  gemm_store(P, (int)(i / P.N), (int)(i % P.N), v);
 }
 
 // ---------------------------------------------------------------------------
@@ -257,23 +309,45 @@ mlp_fwd_kernel(FwdP P) {
   }
 }
 
-// x_hat = bf16(n_a * (n_active / N)) for the active sensors, zero padding
-__global__ void normalize_kernel(const float* sig, int64_t ld, const int32_t* col, int na,
-                                 int64_t n, int kin, __bf16* X) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const float* row = sig + e * ld;
-  float N = 0.f;
-  bool ok = true;
-  for (int a = 0; a < na; ++a) {
-    float v = row[col[a]];
-    if (!(v >= 0.f) || !(v < __builtin_huge_valf())) ok = false;
-    N += v;
+// x_hat = bf16(n_a * (n_active / N)) for the active sensors, zero padding.
+// A block takes 64 events: their signals are staged in LDS by all threads,
+// each event's sum runs in sensor order (as in the fused inference), and
+// the rows are written by all threads.
+constexpr int NR = 64;
+__global__ void __launch_bounds__(256) normalize_kernel(const float* sig, int64_t ld,
+                                                        const int32_t* col, int na, int64_t n,
+                                                        int kin, __bf16* X) {
+  __shared__ float stage[NR * 64];
+  __shared__ float scl[NR];
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * NR;
+  for (int i = tid; i < NR * na; i += 256) {
+    const int r = i / na, a = i - r * na;
+    const int64_t e = e0 + r;
+    stage[i] = e < n ? sig[e * ld + col[a]] : 0.f;
   }
-  ok = ok && N > 0.f;
-  const float s = ok ? (float)na / N : 0.f;
-  __bf16* out = X + e * kin;
-  for (int a = 0; a < kin; ++a) out[a] = (ok && a < na) ? to_bf16(row[col[a]] * s) : (__bf16)0.f;
+  __syncthreads();
+  if (tid < NR) {
+    const float* row = stage + tid * na;
+    float N = 0.f;
+    bool ok = e0 + tid < n;
+    for (int a = 0; a < na; ++a) {
+      const float v = row[a];
+      if (!(v >= 0.f) || !(v < __builtin_huge_valf())) ok = false;
+      N += v;
+    }
+    ok = ok && N > 0.f;
+    scl[tid] = ok ? (float)na / N : 0.f;
+  }
+  __syncthreads();
+  for (int i = tid; i < NR * kin; i += 256) {
+    const int r = i / kin, a = i - r * kin;
+    const int64_t e = e0 + r;
+    if (e >= n) continue;
+    __bf16 v = (__bf16)0.f;
+    if (a < na && scl[r] > 0.f) v = to_bf16(stage[r * na + a] * scl[r]);
+    X[e * kin + a] = v;
+  }
 }
 
 // Gaussian negative log-likelihood with one log-variance s per event:
@@ -384,11 +458,34 @@ inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t);
 
 }  // namespace
 
+// staging mode of an operand (see stage_tile): vector loads need 16-byte
+// aligned rows (or columns) and a unit stride along the loaded direction
+static int stage_mode(const __bf16* X, int64_t s_r, int64_t s_k) {
+  const bool al = ((uintptr_t)X & 15) == 0;
+  if (al && s_k == 1 && s_r % 8 == 0) return 0;
+  if (al && s_r == 1 && s_k % 8 == 0) return 1;
+  return 2;
+}
+
 hipError_t launch_gemm(const GemmP& P, hipStream_t s) {
   if (P.M <= 0 || P.N <= 0) return hipSuccess;
-  dim3 g((unsigned)((P.N + BN - 1) / BN), (unsigned)((P.M + BM - 1) / BM));
-  hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, P);
-  return hipGetLastError();
+  int splits = P.ws ? gemm_splits(P.M, P.N, P.K) : 1;
+  if ((int64_t)splits * P.M * P.N > P.ws_n) splits = 1;
+  // whole BK steps per slice
+  const int steps = P.K > 0 ? (P.K + BK - 1) / BK : 0;
+  const int per = steps > 0 ? (steps + splits - 1) / splits : 1;
+  splits = steps > 0 ? (steps + per - 1) / per : 1;
+  const int kslice = per * BK;
+  dim3 g((unsigned)((P.N + BN - 1) / BN), (unsigned)((P.M + BM - 1) / BM), (unsigned)splits);
+  hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, P, stage_mode(P.A, P.sa_m, P.sa_k),
+                     stage_mode(P.B, P.sb_n, P.sb_k), kslice);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && splits > 1) {
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3(nb((int64_t)P.M * P.N)), dim3(256), 0, s, P,
+                       splits);
+    e = hipGetLastError();
+  }
+  return e;
 }
 hipError_t launch_mlp_fwd(const FwdP& P, hipStream_t s) {
   if (P.n <= 0) return hipSuccess;
@@ -405,7 +502,9 @@ hipError_t launch_mlp_fwd(const FwdP& P, hipStream_t s) {
 hipError_t launch_normalize(const float* sig, int64_t ld, const int32_t* col, int na, int64_t n,
                             int kin, __bf16* X, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(normalize_kernel, dim3(nb(n)), dim3(256), 0, s, sig, ld, col, na, n, kin, X);
+  if (na > 64 || na > kin) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(normalize_kernel, dim3(nb(n, NR)), dim3(256), 0, s, sig, ld, col, na, n, kin,
+                     X);
   return hipGetLastError();
 }
 hipError_t launch_head_loss(const float* Y, const float* target, int64_t ldt, int64_t n,

@@ -48,6 +48,8 @@ struct ants_mlp {
   std::vector<__bf16*> H;
   float *Y = nullptr, *dY = nullptr, *loss_ev = nullptr, *loss = nullptr;
   __bf16 *dYb = nullptr, *dHa = nullptr, *dHb = nullptr;
+  float* gws = nullptr;   // split-K partial products of the weight gradients
+  int64_t gws_n = 0;
   Dev mem;      // parameter-sized buffers
   Dev work;     // activation buffers (reallocated when rows grow)
 };
@@ -69,6 +71,16 @@ ants_status mlp_workspace(ants_mlp* M, int64_t rows) {
   if (e == hipSuccess) e = M->work.alloc(&M->dHb, (size_t)rows * M->hidden);
   if (e == hipSuccess) e = M->work.alloc(&M->loss_ev, (size_t)rows);
   if (e == hipSuccess) e = M->work.alloc(&M->loss, 4);
+  // the weight gradients' split-K partials at this many rows (the split
+  // only grows with the row count)
+  int64_t ws = (int64_t)gemm_splits(4, M->hidden, (int)rows) * 4 * M->hidden;
+  for (int l = 0; l < M->layers; ++l) {
+    const int64_t w = (int64_t)gemm_splits(M->hidden, (int)M->din[l], (int)rows) * M->hidden *
+                      M->din[l];
+    ws = w > ws ? w : ws;
+  }
+  M->gws_n = ws;
+  if (e == hipSuccess) e = M->work.alloc(&M->gws, (size_t)ws);
   if (e != hipSuccess) {
     M->rows = 0;
     return hip_error(e, "network workspace");
@@ -154,6 +166,8 @@ hipError_t backward_rows(ants_mlp* M, const float* target, int64_t ldt, int64_t 
   if (e == hipSuccess) {
     // dW_out[o][j] = sum_b dY[b][o] H[L-1][b][j]
     GemmP P = gemm(4, M->hidden, (int)n, M->dYb, 1, 4, M->H[L - 1], 1, M->hidden);
+    P.ws = M->gws;
+    P.ws_n = M->gws_n;
     P.Cf = M->g + M->offW[L];
     P.ldcf = M->hidden;
     e = launch_gemm(P, s);
@@ -169,6 +183,8 @@ hipError_t backward_rows(ants_mlp* M, const float* target, int64_t ldt, int64_t 
     if (e == hipSuccess) {
       // dW_l[j][i] = sum_b dH[b][j] in[b][i]
       GemmP P = gemm(M->hidden, (int)di, (int)n, dH, 1, M->hidden, in, 1, di);
+      P.ws = M->gws;
+      P.ws_n = M->gws_n;
       P.Cf = M->g + M->offW[l];
       P.ldcf = di;
       e = launch_gemm(P, s);

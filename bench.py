@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=48_000,
                     help="events for the oracle CPU baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=160207247)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch plans (profiling runs: every dispatch of a "
+                         "kernel then covers the full batch)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="rz",
@@ -398,7 +401,10 @@ def xy_step(args):
         wall_c, ev_c = timed(lambda: ants.reconstruct(lrf, g, sig, out=out_c, stream=stream),
                              max(2, args.steps // 2), 1, stream)
         ants.set_plan(lrf, g, None)
-        plan, cand_ms = ants.autotune(lrf, g, sig[:nt].contiguous(), stream=stream)
+        if args.no_tune:
+            plan, cand_ms = ants.GridPlan(4, 0, 0), []
+        else:
+            plan, cand_ms = ants.autotune(lrf, g, sig[:nt].contiguous(), stream=stream)
         out = ants.alloc_out(n)
         wall, ev = timed(lambda: ants.reconstruct(lrf, g, sig, out=out, stream=stream),
                          args.steps, args.warmup, stream)
@@ -688,7 +694,10 @@ def main():
                 "candidate_ms": [round(float(v), 4) for v in ms if v > 0]}
 
     # ---- plain grid (launch plan tuned on the first 1M events, untimed)
-    plan_p, ms_p = ants.autotune(lrf, plain, sig[:nt].contiguous(), stream=stream)
+    if args.no_tune:
+        plan_p, ms_p = ants.GridPlan(4, 0, 0), []
+    else:
+        plan_p, ms_p = ants.autotune(lrf, plain, sig[:nt].contiguous(), stream=stream)
     wall_p, ev_p = timed(lambda: ants.reconstruct(lrf, plain, sig, out=out_plain, stream=stream),
                          args.steps, args.warmup, stream)
     evals = int(np.prod(wl.grid.nodes)) * 37 * wl.grid.iterations
@@ -741,8 +750,11 @@ def main():
         seeds[:, :3] = (pred[:, :3] * torch.tensor(W.SEED_POS_SCALE, device=pred.device)
                         + torch.tensor(W.SEED_POS_OFFSET, device=pred.device))
         seeds = seeds.contiguous()
-        plan_r, ms_r = ants.autotune(lrf, refine, sig[:nt].contiguous(),
-                                     seeds=seeds[:nt].contiguous(), stream=stream)
+        if args.no_tune:
+            plan_r, ms_r = ants.GridPlan(4, 0, 0), []
+        else:
+            plan_r, ms_r = ants.autotune(lrf, refine, sig[:nt].contiguous(),
+                                         seeds=seeds[:nt].contiguous(), stream=stream)
 
         def seeded():
             o, nfb = ants.reconstruct_seeded(lrf, net, refine, plain, 2.0, sig, out=out_seed,

@@ -3,10 +3,14 @@
 TEST INFRASTRUCTURE ONLY: nothing in the library imports or runs this.
 
 The LRF module computes LRFs from signals and event positions (Sec. 6),
-here for the axial parameterisation (Sec. 6.1.1) with one LRF shared by all
-sensors and per-sensor relative gains (Sec. 6.2, "one group for all
-sensors").  The iterative procedure of Sec. 8 alternates it with the
-position reconstruction, keeping only events that pass a filter.
+here for the axial parameterisation (Sec. 6.1.1) with per-sensor relative
+gains and the sensors in groups that share one LRF (Sec. 6.2: one group
+for all sensors, groups by distance from the array centre or by symmetry,
+or every sensor its own); the relative gains can be re-calculated within
+fixed groups without changing the LRF profiles (Sec. 6.3).  The iterative
+procedure of Sec. 8 alternates the fit with the position reconstruction,
+keeping only events that pass a filter, optionally with a small random
+shift of the reconstructed positions (its draws are inputs here).
 
 Readings (the paper prints no fit formula):
   * model: signal n_ie = E_e * g_i * L(r_ie), L a uniform cubic B-spline
@@ -19,7 +23,14 @@ Readings (the paper prints no fit formula):
   * a ridge of `ridge` times the mean diagonal of the normal matrix keeps
     coefficients without data defined (they go to zero);
   * events enter when their reconstruction status is 0, E > 0 and finite,
-    and chi2/ndf <= chi2ndf_max (when given).
+    and chi2/ndf <= chi2ndf_max (when given);
+  * groups: one table per group, fitted to the pairs of its member sensors
+    only; a group without pairs has no solution (NaN);
+  * shift: the fit reads (x + dx, y + dy) for each event, the shift drawn
+    by the caller;
+  * gains within groups: the least-squares scale of n_ie / E_e against the
+    group's fixed L(r_ie) over the sensor's pairs in the domain,
+    g_i = sum (n/E) L / sum L^2.
 """
 from __future__ import annotations
 
@@ -51,20 +62,34 @@ def event_mask(E, status=None, chi2=None, ndf=None, chi2ndf_max=None):
     return use
 
 
-def normal_equations(sxy, gain, active, signals, x, y, E, use, nb, lo, hi):
+def _positions(x, y, use, shift):
+    xe = np.asarray(x, np.float64)
+    ye = np.asarray(y, np.float64)
+    if shift is not None:
+        sh = np.asarray(shift, np.float64)
+        xe = xe + sh[:, 0]
+        ye = ye + sh[:, 1]
+    return xe[use], ye[use]
+
+
+def normal_equations(sxy, gain, active, signals, x, y, E, use, nb, lo, hi, members=None,
+                     shift=None):
     """Normal matrix M [(nb+2)^2] and right-hand side v [nb+2] of the
-    least-squares fit, and the number of (event, sensor) pairs in it."""
+    least-squares fit over the pairs of the sensors in `members` (default:
+    every active sensor), and the number of (event, sensor) pairs in it.
+    `shift` [n][2]: added to the event positions."""
     nc = nb + 2
     d = (hi - lo) / (nb - 1)
     tol = 1e-9 * (hi - lo)
     M = np.zeros((nc, nc))
     v = np.zeros(nc)
     sig = np.asarray(signals, np.float64)[use]
-    xe = np.asarray(x, np.float64)[use]
-    ye = np.asarray(y, np.float64)[use]
+    xe, ye = _positions(x, y, use, shift)
     Ee = np.asarray(E, np.float64)[use]
     npairs = 0
-    for i in range(len(sxy)):
+    if members is None:
+        members = range(len(sxy))
+    for i in members:
         if not active[i]:
             continue
         r = np.sqrt((xe - sxy[i][0]) ** 2 + (ye - sxy[i][1]) ** 2)
@@ -88,3 +113,74 @@ def fit_axial_shared(sxy, gain, active, signals, x, y, E, use, nb, lo, hi, ridge
     M, v, _ = normal_equations(sxy, gain, active, signals, x, y, E, use, nb, lo, hi)
     lam = ridge * float(np.mean(np.diag(M)))
     return np.linalg.solve(M + lam * np.eye(len(v)), v)
+
+
+def _solve(M, v, ridge):
+    lam = ridge * float(np.mean(np.diag(M)))
+    try:
+        return np.linalg.solve(M + lam * np.eye(len(v)), v)
+    except np.linalg.LinAlgError:
+        return np.full(len(v), np.nan)
+
+
+def fit_axial_grouped(sxy, gain, active, signals, x, y, E, use, nb, lo, hi, groups,
+                      ridge=1e-9, shift=None):
+    """One axial table per sensor group (Sec. 6.2).  `groups` [n_sensors]:
+    the group of each sensor (0..G-1), -1 for sensors not fitted.  Returns
+    the coefficients [G][nb+2] (NaN rows for groups without pairs) and the
+    pair count of each group [G]."""
+    groups = np.asarray(groups, np.int64)
+    G = int(groups.max()) + 1 if len(groups) and groups.max() >= 0 else 0
+    coef = np.full((G, nb + 2), np.nan)
+    pairs = np.zeros(G, np.int64)
+    for g in range(G):
+        members = [i for i in range(len(sxy)) if groups[i] == g and active[i]]
+        M, v, npairs = normal_equations(sxy, gain, active, signals, x, y, E, use, nb, lo, hi,
+                                        members, shift)
+        pairs[g] = npairs
+        if npairs > 0:
+            coef[g] = _solve(M, v, ridge)
+    return coef, pairs
+
+
+def axial_value(coef, nb, lo, hi, r):
+    """The reconstruction's axial LRF at distances r: max(spline, 0) inside
+    [lo, hi] (relative slack 1e-9), 0 outside."""
+    r = np.asarray(r, np.float64)
+    d = (hi - lo) / (nb - 1)
+    tol = 1e-9 * (hi - lo)
+    inside = (r >= lo - tol) & (r <= hi + tol)
+    u = (np.clip(r, lo, hi) - lo) / d
+    m = np.clip(np.floor(u).astype(np.int64), 0, nb - 2)
+    b = bspline_weights(u - m)
+    c = np.asarray(coef, np.float64)
+    val = sum(b[..., k] * c[m + k] for k in range(4))
+    return np.where(inside, np.maximum(val, 0.0), 0.0)
+
+
+def fit_gains(sxy, active, signals, x, y, E, use, nb, lo, hi, tables, table_of, shift=None):
+    """Relative gains re-calculated within fixed groups (Sec. 6.3): for each
+    active sensor i with a table (table_of[i] >= 0), the least-squares
+    scale g_i of n_ie / E_e against L_{table_of[i]}(r_ie) over its pairs in
+    the domain.  Returns gains [n_sensors] (NaN where there is no pair or
+    sum L^2 = 0) and the pair counts."""
+    d = (hi - lo) / (nb - 1)
+    tol = 1e-9 * (hi - lo)
+    sig = np.asarray(signals, np.float64)[use]
+    xe, ye = _positions(x, y, use, shift)
+    Ee = np.asarray(E, np.float64)[use]
+    n = len(sxy)
+    gains = np.full(n, np.nan)
+    pairs = np.zeros(n, np.int64)
+    for i in range(n):
+        if not active[i] or table_of[i] < 0:
+            continue
+        r = np.sqrt((xe - sxy[i][0]) ** 2 + (ye - sxy[i][1]) ** 2)
+        inside = (r >= lo - tol) & (r <= hi + tol)
+        L = axial_value(tables[table_of[i]], nb, lo, hi, r[inside])
+        t = sig[inside, i] / Ee[inside]
+        pairs[i] = int(inside.sum())
+        den = float(np.sum(L * L))
+        if pairs[i] > 0 and den > 0.0:
+            gains[i] = float(np.sum(t * L)) / den
+    return gains, pairs

@@ -124,3 +124,126 @@ def test_iterations_converge_from_a_wrong_lrf():
     assert all(b < a for a, b in zip(pos, pos[1:])), pos
     assert pos[-1] < 0.8 * pos[0], pos
     assert all(b < a for a, b in zip(shape, shape[1:])), shape
+
+
+# ---- groups (Sec. 6.2), shifts (Sec. 8), gains within groups (Sec. 6.3)
+
+def _hex61_per_sensor_model(group_of=None, gain_seed=4):
+    """The 61-sensor hexagonal detector with a distinct positive spline per
+    group of sensors (every sensor its own unless group_of is given)."""
+    lrf, rec = W.mixed_geometries()[1]
+    n = lrf.n_sensors
+    g = np.arange(n) if group_of is None else np.asarray(group_of)
+    base = np.asarray(lrf.coef, np.float64).reshape(-1)
+    j = np.arange(base.size)
+    rng = np.random.default_rng(gain_seed)
+    a = rng.uniform(0.3, 1.7, g.max() + 1)
+    s = rng.uniform(0.8, 1.2, g.max() + 1)
+    tabs = np.stack([base * s[k] * (1.0 + 0.15 * np.cos(j * a[k])) for k in range(g.max() + 1)])
+    coef = tabs[g].reshape(n, 1, -1)
+    model = W.LRFSet(lrf.kind, lrf.sxy, np.asarray(lrf.gain, np.float64),
+                     np.asarray(lrf.active, np.uint8), 0, lrf.nb, lrf.lo, lrf.hi, coef)
+    # events out to 175 mm: every sensor sees distances over the whole
+    # domain [0, 150], so every table is determined without a ridge
+    rec = W.EventRecipe("disc", 175.0, rec.e_lo, rec.e_hi)
+    return model, rec, tabs, g
+
+
+def _noiseless(model, rec, n, seed):
+    sig, truth = _events(model, rec, n, seed, noiseless=True)
+    S = oracle.lrf_values(model, truth[:, :3]) @ np.asarray(model.gain, np.float64)
+    return sig, truth, truth[:, 3] / S
+
+
+def test_axial_value_equals_c_oracle_lrf():
+    model, rec, tabs, g = _hex61_per_sensor_model()
+    rng = np.random.default_rng(8)
+    pos = np.zeros((300, 3))
+    pos[:, :2] = rng.uniform(-160, 160, (300, 2))
+    ref = oracle.lrf_values(model, pos)
+    for i in (0, 7, 33, 60):
+        r = np.hypot(pos[:, 0] - model.sxy[i, 0], pos[:, 1] - model.sxy[i, 1])
+        got = F.axial_value(tabs[g[i]], model.nb[0], model.lo[0], model.hi[0], r)
+        np.testing.assert_allclose(got, ref[:, i], rtol=1e-13, atol=1e-15)
+
+
+def test_per_sensor_groups_recover_every_sensors_spline():
+    model, rec, tabs, g = _hex61_per_sensor_model()
+    sig, truth, E = _noiseless(model, rec, 6000, 31)
+    use = np.ones(len(sig), bool)
+    args = (model.sxy, model.gain, model.active, sig, truth[:, 0], truth[:, 1], E, use,
+            model.nb[0], model.lo[0], model.hi[0])
+    coef, pairs = F.fit_axial_grouped(*args, np.arange(model.n_sensors), ridge=0.0)
+    err = np.max(np.abs(coef - tabs), axis=1) / np.max(np.abs(tabs), axis=1)
+    assert err.max() < 1e-8, err.max()
+    assert pairs.sum() == F.normal_equations(*args)[2]
+    # one shared table cannot describe them
+    shared = F.fit_axial_shared(*args, ridge=0.0)
+    assert np.max(np.abs(shared - tabs[0])) > 1e-3 * np.max(np.abs(tabs[0]))
+
+
+def test_distance_groups_recover_each_rings_spline():
+    lrf, rec = W.mixed_geometries()[1]
+    d = np.hypot(lrf.sxy[:, 0], lrf.sxy[:, 1])
+    _, ring = np.unique(np.round(d, 6), return_inverse=True)
+    model, rec, tabs, g = _hex61_per_sensor_model(ring)
+    sig, truth, E = _noiseless(model, rec, 5000, 32)
+    coef, pairs = F.fit_axial_grouped(model.sxy, model.gain, model.active, sig, truth[:, 0],
+                                      truth[:, 1], E, np.ones(len(sig), bool), model.nb[0],
+                                      model.lo[0], model.hi[0], ring, ridge=0.0)
+    assert coef.shape == tabs.shape and ring.max() >= 5
+    assert np.max(np.abs(coef - tabs)) < 1e-8 * np.max(np.abs(tabs))
+
+
+def test_excluded_sensors_and_empty_groups():
+    lrf, rec = W.mixed_geometries()[0]
+    sig, truth = _events(lrf, rec, 1500, 33, noiseless=False)
+    use = np.ones(len(sig), bool)
+    n = lrf.n_sensors
+    args = (sig, truth[:, 0], truth[:, 1], truth[:, 3], use, lrf.nb[0], lrf.lo[0], lrf.hi[0])
+    groups = np.zeros(n, np.int64)
+    groups[[2, 9]] = -1
+    groups[5] = 2                                   # group 1 has no member
+    coef, pairs = F.fit_axial_grouped(lrf.sxy, lrf.gain, lrf.active, *args, groups)
+    act = np.asarray(lrf.active, np.uint8).copy()
+    act[[2, 9, 5]] = 0
+    ref = F.fit_axial_shared(lrf.sxy, lrf.gain, act, *args)
+    np.testing.assert_allclose(coef[0], ref, rtol=1e-12, atol=1e-15)
+    assert np.isnan(coef[1]).all() and pairs[1] == 0 and pairs[2] > 0
+
+
+def test_shift_equals_shifted_positions():
+    lrf, rec = W.mixed_geometries()[1]
+    sig, truth = _events(lrf, rec, 2000, 34, noiseless=False)
+    use = np.ones(len(sig), bool)
+    sh = np.random.default_rng(9).normal(0.0, 2.0, (len(sig), 2))
+    groups = np.arange(lrf.n_sensors) % 3
+    a = F.fit_axial_grouped(lrf.sxy, lrf.gain, lrf.active, sig, truth[:, 0], truth[:, 1],
+                            truth[:, 3], use, lrf.nb[0], lrf.lo[0], lrf.hi[0], groups, shift=sh)
+    b = F.fit_axial_grouped(lrf.sxy, lrf.gain, lrf.active, sig, truth[:, 0] + sh[:, 0],
+                            truth[:, 1] + sh[:, 1], truth[:, 3], use, lrf.nb[0], lrf.lo[0],
+                            lrf.hi[0], groups)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    c = F.fit_axial_grouped(lrf.sxy, lrf.gain, lrf.active, sig, truth[:, 0], truth[:, 1],
+                            truth[:, 3], use, lrf.nb[0], lrf.lo[0], lrf.hi[0], groups)
+    assert np.max(np.abs(a[0] - c[0])) > 0.0
+
+
+def test_gains_within_groups_recover_true_gains():
+    lrf, rec = W.mixed_geometries()[1]
+    d = np.hypot(lrf.sxy[:, 0], lrf.sxy[:, 1])
+    _, ring = np.unique(np.round(d, 6), return_inverse=True)
+    model, rec, tabs, g = _hex61_per_sensor_model(ring)
+    sig, truth, E = _noiseless(model, rec, 3000, 35)
+    gains, pairs = F.fit_gains(model.sxy, model.active, sig, truth[:, 0], truth[:, 1], E,
+                               np.ones(len(sig), bool), model.nb[0], model.lo[0], model.hi[0],
+                               tabs, ring)
+    act = np.asarray(model.active, bool)
+    np.testing.assert_allclose(gains[act], np.asarray(model.gain)[act], rtol=1e-11)
+    assert (pairs[act] > 0).all()
+    # a table scaled by k gives gains scaled by 1 / k
+    g2, _ = F.fit_gains(model.sxy, model.active, sig, truth[:, 0], truth[:, 1], E,
+                        np.ones(len(sig), bool), model.nb[0], model.lo[0], model.hi[0],
+                        2.0 * tabs, ring)
+    np.testing.assert_allclose(g2[act], 0.5 * gains[act], rtol=1e-13)

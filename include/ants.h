@@ -548,6 +548,43 @@ ants_status ants_fit_axial_lrf(ants_lrfset* set, const ants_fit_cfg* cfg, int64_
                                const float* d_signals, int64_t ld, ants_out rec, double* d_coef,
                                int64_t* d_counts, void* hip_stream);
 
+/* Grouped fit (Sec. 6.2: sensors in groups that share one LRF, each with
+ * its relative gain; one group for all, groups by distance from the array
+ * centre or by symmetry, or every sensor its own).  d_group [n_sensors]
+ * int32, device memory, caller-owned: the group of each sensor (by sensor
+ * index), 0..n_groups-1; other values (e.g. -1) leave the sensor out of
+ * every fit; passive sensors are always out.  Each group's table is fitted
+ * as ants_fit_axial_lrf fits the shared one, from its members' pairs only.
+ * d_shift [n_events][2] FP32 or NULL: added to each event's (x, y) before
+ * the fit (Sec. 8: a small random shift of the reconstructed positions
+ * helps the first iterations; the caller draws it).  Writes d_coef
+ * [n_groups][nb + 2] FP64 (NaN rows for groups without pairs and ridge 0,
+ * or without any pair) and, when not NULL, d_counts [n_groups][2] int64 =
+ * (events used, pairs of the group).  n_groups 1..4096.  Same determinism,
+ * workspace rule and stream behaviour as ants_fit_axial_lrf (workspace:
+ * 8 (5 (nb + 2) + 2) bytes per wave of each group). */
+ants_status ants_fit_axial_lrf_grouped(ants_lrfset* set, const ants_fit_cfg* cfg,
+                                       int32_t n_groups, const int32_t* d_group,
+                                       int64_t n_events, const float* d_signals, int64_t ld,
+                                       ants_out rec, const float* d_shift, double* d_coef,
+                                       int64_t* d_counts, void* hip_stream);
+
+/* Relative gains re-calculated within fixed groups (Sec. 6.3), the LRF
+ * profiles unchanged: for each active sensor i with d_table_of[i] in
+ * 0..n_tables-1, the least-squares scale g_i = sum (n/E) L / sum L^2 of
+ * its estimates n_ie / E_e against the reconstruction's LRF of its table,
+ * L(r) = max(spline, 0) (d_tables [n_tables][nb + 2] FP64 on cfg's nb, lo,
+ * hi), over its pairs inside the domain and the events cfg's filter keeps
+ * (cfg->ridge is not used).  Writes d_gains[i] (NaN without pairs or with
+ * sum L^2 = 0) and, when not NULL, d_pairs[i] int64, for those sensors
+ * only (by sensor index; other entries untouched).  d_shift as in the
+ * grouped fit.  All arrays are device memory, caller-owned. */
+ants_status ants_fit_axial_gains(ants_lrfset* set, const ants_fit_cfg* cfg, int32_t n_tables,
+                                 const double* d_tables, const int32_t* d_table_of,
+                                 int64_t n_events, const float* d_signals, int64_t ld,
+                                 ants_out rec, const float* d_shift, double* d_gains,
+                                 int64_t* d_pairs, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -158,6 +158,10 @@ _lib.ants_knn_reconstruct.argtypes = [_vp, C.c_int32, C.c_int64, _vp, _vp, _vp, 
 
 _lib.ants_fit_axial_lrf.argtypes = [_vp, C.POINTER(FitCfg), C.c_int64, _vp, C.c_int64, Out, _vp,
                                     _vp, _vp]
+_lib.ants_fit_axial_lrf_grouped.argtypes = [_vp, C.POINTER(FitCfg), C.c_int32, _vp, C.c_int64,
+                                            _vp, C.c_int64, Out, _vp, _vp, _vp, _vp]
+_lib.ants_fit_axial_gains.argtypes = [_vp, C.POINTER(FitCfg), C.c_int32, _vp, _vp, C.c_int64,
+                                      _vp, C.c_int64, Out, _vp, _vp, _vp, _vp]
 
 EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfset_destroy",
             "ants_lrfset_info", "ants_reconstruct", "ants_generate", "ants_mlp_create",
@@ -168,7 +172,8 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_reconstruct_multi", "ants_autotune_multi", "ants_fit_axial_lrf",
             "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load",
             "ants_reconstruct_simplex", "ants_knn_create", "ants_knn_destroy",
-            "ants_knn_reconstruct", "ants_autotune", "ants_set_plan")
+            "ants_knn_reconstruct", "ants_autotune", "ants_set_plan",
+            "ants_fit_axial_lrf_grouped", "ants_fit_axial_gains")
 
 
 def _check(code):
@@ -654,38 +659,228 @@ def fit_axial_lrf(lrfset: LrfSet, cfg: FitCfg, signals, rec, stream=None):
     return coef, counts
 
 
-class AxialModel:
-    """Detector model with a shared axial LRF (the fields LrfSet reads)."""
+def _dev_i32(a, device):
+    import torch
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, np.int32), device=device)
 
-    def __init__(self, sxy, gain, active, nb, lo, hi, coef):
-        self.kind, self.shared = 1, 1
+
+def _shift_arg(shift, n):
+    import torch
+    if shift is None:
+        return None
+    assert shift.dtype == torch.float32 and shift.is_cuda and tuple(shift.shape) == (n, 2)
+    return shift.contiguous()
+
+
+def fit_axial_lrf_grouped(lrfset: LrfSet, cfg: FitCfg, groups, signals, rec, shift=None,
+                          stream=None):
+    """One axial table per sensor group (Sec. 6.2).  `groups`: the group of
+    each sensor ([n_sensors], 0..G-1; -1 leaves a sensor out); `shift`
+    ([n][2] float32, GPU, or None) is added to the reconstructed positions
+    (Sec. 8).  Returns (coefficients [G][nb+2] float64, counts [G][2] int64
+    = events, pairs), device tensors (asynchronous)."""
+    import torch
+    assert signals.dtype == torch.float32 and signals.is_cuda and signals.dim() == 2
+    assert signals.stride(1) == 1 and signals.shape[1] == lrfset.n_sensors
+    n = signals.shape[0]
+    g = _dev_i32(groups, signals.device)
+    assert g.numel() == lrfset.n_sensors
+    G = int(g.max().item()) + 1
+    assert G >= 1
+    sh = _shift_arg(shift, n)
+    coef = torch.empty((G, cfg.nb + 2), dtype=torch.float64, device=signals.device)
+    counts = torch.empty((G, 2), dtype=torch.int64, device=signals.device)
+    _check(_lib.ants_fit_axial_lrf_grouped(
+        lrfset.handle, C.byref(cfg), G, g.data_ptr(), n, signals.data_ptr(), signals.stride(0),
+        _out_struct(rec), sh.data_ptr() if sh is not None else None, coef.data_ptr(),
+        counts.data_ptr(), _stream_handle(stream)))
+    return coef, counts
+
+
+def fit_axial_gains(lrfset: LrfSet, cfg: FitCfg, tables, table_of, signals, rec, shift=None,
+                    stream=None):
+    """Relative gains re-calculated within fixed groups (Sec. 6.3): `tables`
+    [T][nb+2] float64 (the groups' LRFs), `table_of` [n_sensors] (the table
+    of each sensor, -1: none).  Returns (gains [n_sensors] float64, NaN
+    where not fitted; pairs [n_sensors] int64, 0 where not fitted)."""
+    import torch
+    assert signals.dtype == torch.float32 and signals.is_cuda and signals.dim() == 2
+    assert signals.stride(1) == 1 and signals.shape[1] == lrfset.n_sensors
+    n = signals.shape[0]
+    t = torch.as_tensor(np.ascontiguousarray(tables, np.float64), device=signals.device) \
+        if not isinstance(tables, torch.Tensor) else tables.to(signals.device, torch.float64)
+    t = t.reshape(-1, cfg.nb + 2).contiguous()
+    tof = _dev_i32(table_of, signals.device)
+    assert tof.numel() == lrfset.n_sensors
+    sh = _shift_arg(shift, n)
+    gains = torch.full((lrfset.n_sensors,), float("nan"), dtype=torch.float64,
+                       device=signals.device)
+    pairs = torch.zeros(lrfset.n_sensors, dtype=torch.int64, device=signals.device)
+    _check(_lib.ants_fit_axial_gains(
+        lrfset.handle, C.byref(cfg), t.shape[0], t.data_ptr(), tof.data_ptr(), n,
+        signals.data_ptr(), signals.stride(0), _out_struct(rec),
+        sh.data_ptr() if sh is not None else None, gains.data_ptr(), pairs.data_ptr(),
+        _stream_handle(stream)))
+    return gains, pairs
+
+
+# ---- sensor grouping options (Sec. 6.2), host side
+def groups_all(n_sensors):
+    """One group for all sensors."""
+    return np.zeros(n_sensors, np.int32)
+
+
+def groups_individual(n_sensors):
+    """Every sensor its own group (grouping disabled)."""
+    return np.arange(n_sensors, dtype=np.int32)
+
+
+def groups_by_distance(sxy, tol=1e-3):
+    """Groups of sensors at the same distance (within tol mm) from the
+    array centre (the mean sensor position), numbered outwards."""
+    sxy = np.asarray(sxy, np.float64)
+    d = np.hypot(*(sxy - sxy.mean(0)).T)
+    order = np.argsort(d, kind="stable")
+    g = np.empty(len(d), np.int32)
+    k, last = -1, None
+    for i in order:
+        if last is None or d[i] - last > tol:
+            k += 1
+            last = d[i]
+        g[i] = k
+    return g
+
+
+def groups_by_symmetry(sxy, order, reflect=True, tol=1e-3):
+    """Orbits of the sensors under rotations by 2 pi / order about the array
+    centre (and the reflection x -> -x when `reflect`): order 6 for
+    hexagonal, 4 for square, 2 for rectangular arrays.  Groups are numbered
+    by the orbit's smallest sensor index."""
+    sxy = np.asarray(sxy, np.float64)
+    c = sxy - sxy.mean(0)
+    n = len(c)
+    maps = []
+    for k in range(order):
+        a = 2.0 * np.pi * k / order
+        R = np.array([[np.cos(a), -np.sin(a)], [np.sin(a), np.cos(a)]])
+        maps.append(R)
+        if reflect:
+            maps.append(R @ np.diag([-1.0, 1.0]))
+    g = np.full(n, -1, np.int32)
+    k = 0
+    for i in range(n):
+        if g[i] >= 0:
+            continue
+        for M in maps:
+            p = M @ c[i]
+            j = np.where(np.hypot(*(c - p).T) <= tol)[0]
+            for jj in j:
+                if g[jj] < 0:
+                    g[jj] = k
+        g[i] = k
+        k += 1
+    return g
+
+
+class AxialModel:
+    """Detector model with axial LRFs: `tables` [T][nb+2] and the table of
+    each sensor (`table_of`, default: one shared table); the fields LrfSet
+    reads (per-sensor rows when there are several tables)."""
+
+    def __init__(self, sxy, gain, active, nb, lo, hi, coef, table_of=None):
+        self.kind = 1
         self.sxy = np.ascontiguousarray(sxy, np.float64)
         self.gain = np.ascontiguousarray(gain, np.float64)
         self.active = np.ascontiguousarray(active, np.uint8)
         self.nb, self.lo, self.hi = (int(nb), 1), (float(lo), 0.0), (float(hi), 0.0)
-        self.coef = np.ascontiguousarray(coef, np.float64).reshape(1, 1, int(nb) + 2)
+        self.tables = np.ascontiguousarray(coef, np.float64).reshape(-1, int(nb) + 2)
+        n = len(self.sxy)
+        self.table_of = (np.zeros(n, np.int32) if table_of is None
+                         else np.ascontiguousarray(table_of, np.int32))
+        if len(self.tables) == 1 and (self.table_of == 0).all():
+            self.shared = 1
+            self.coef = self.tables.reshape(1, 1, -1)
+        else:
+            self.shared = 0
+            self.coef = self.tables[np.maximum(self.table_of, 0)].reshape(n, 1, -1)
+
+    def with_active(self, active):
+        return AxialModel(self.sxy, self.gain, active, self.nb[0], self.lo[0], self.hi[0],
+                          self.tables, self.table_of)
 
 
 def iterate_axial_lrf(model, grid: GridCfg, signals, iterations, ridge=1e-9, chi2ndf_max=0.0,
-                      stream=None):
+                      stream=None, groups=None, shift_sigma=0.0, shift_iterations=0,
+                      shift_seed=0, disable=None, refit_gains=False):
     """Iterative LRF reconstruction (Sec. 8): reconstruct every event with the
-    current LRF, keep the events that pass the filter, fit the LRF to their
+    current LRFs, keep the events that pass the filter, fit the LRFs to their
     signals, reconstructed positions and energies, repeat.  `model` is the
-    initial guess (an axial model with one shared table).  Returns the list
-    of models, the initial one first, and the last reconstruction."""
+    initial guess (an AxialModel).
+
+    groups: None (one shared table), a per-sensor group array, or a function
+      k -> group array for fit k (e.g. one common LRF for the first fits,
+      then individual ones: Sec. 8);
+    shift_sigma, shift_iterations, shift_seed: the first shift_iterations
+      fits read the positions shifted by N(0, shift_sigma^2) per axis (drawn
+      with torch's generator from shift_seed + k);
+    disable: {k: [sensor indices]} sensors left out of the reconstruction of
+      iteration k (their LRFs are still fitted; Sec. 8);
+    refit_gains: after each fit, re-calculate the relative gains within the
+      new groups (Sec. 6.3).
+    Sensors of a group without pairs keep their previous LRF.  Returns the
+    list of models, the initial one first, and the last reconstruction."""
     import torch
     st = stream if stream is not None else torch.cuda.current_stream()
     models = [model]
+    n = signals.shape[0]
     for k in range(iterations + 1):
         cur = models[-1]
-        ls = LrfSet(cur)
+        act = np.asarray(cur.active, np.uint8).copy()
+        if disable and k in disable:
+            act[np.asarray(disable[k], np.int64)] = 0
+        ls = LrfSet(cur.with_active(act))
         rec = reconstruct(ls, grid, signals, stream=st)
-        if k < iterations:
-            coef, _ = fit_axial_lrf(ls, fit_cfg(cur.nb[0], cur.lo[0], cur.hi[0], ridge,
-                                                chi2ndf_max), signals, rec, st)
+        if k == iterations:
+            st.synchronize()
+            ls.close()
+            break
+        fs = LrfSet(cur) if disable and k in disable else ls
+        g = groups(k) if callable(groups) else groups
+        g = groups_all(len(cur.sxy)) if g is None else np.asarray(g, np.int32)
+        shift = None
+        if shift_sigma > 0.0 and k < shift_iterations:
+            gen = torch.Generator(device=signals.device).manual_seed(int(shift_seed) + k)
+            shift = torch.randn((n, 2), generator=gen, device=signals.device,
+                                dtype=torch.float32) * float(shift_sigma)
+        cfg = fit_cfg(cur.nb[0], cur.lo[0], cur.hi[0], ridge, chi2ndf_max)
+        coef, counts = fit_axial_lrf_grouped(fs, cfg, g, signals, rec, shift, st)
+        gains = None
+        if refit_gains:
+            gains, _ = fit_axial_gains(fs, cfg, coef, g, signals, rec, shift, st)
         st.synchronize()
+        coef = coef.cpu().numpy()
+        # groups without a solution keep the previous tables of their sensors
+        ns = len(cur.sxy)
+        new = cur.tables[np.maximum(cur.table_of, 0)].copy()
+        for i in range(ns):
+            if 0 <= g[i] < len(coef) and np.isfinite(coef[g[i]]).all():
+                new[i] = coef[g[i]]
+        gain = cur.gain.copy()
+        if gains is not None:
+            gh = gains.cpu().numpy()
+            ok = np.isfinite(gh)
+            gain[ok] = gh[ok]
+        if fs is not ls:
+            fs.close()
         ls.close()
-        if k < iterations:
-            models.append(AxialModel(cur.sxy, cur.gain, cur.active, cur.nb[0], cur.lo[0],
-                                     cur.hi[0], coef.cpu().numpy()))
+        if (g == 0).all() and np.isfinite(coef[0]).all():
+            nxt = AxialModel(cur.sxy, gain, cur.active, cur.nb[0], cur.lo[0], cur.hi[0], coef[0])
+        else:
+            nxt = AxialModel(cur.sxy, gain, cur.active, cur.nb[0], cur.lo[0], cur.hi[0], new,
+                             np.arange(ns))
+        models.append(nxt)
     return models, rec
+
+

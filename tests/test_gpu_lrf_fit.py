@@ -123,3 +123,124 @@ def test_iterative_procedure_converges_from_wrong_lrf(ants):
     # resolution with the true LRF
     assert all(b < a for a, b in zip(errs, errs[1:])), errs
     assert errs[-1] - best < 0.67 * (errs[0] - best), (errs, best)
+
+
+# ---- groups (Sec. 6.2), shifts (Sec. 8), gains within groups (Sec. 6.3)
+
+def _ring_groups(sxy):
+    d = np.hypot(*(np.asarray(sxy) - np.asarray(sxy).mean(0)).T)
+    _, ring = np.unique(np.round(d, 6), return_inverse=True)
+    return ring.astype(np.int32)
+
+
+@pytest.mark.parametrize("g,kind,shift", [(1, "individual", False), (1, "ring", True),
+                                          (2, "ring", False), (0, "mixed", True)])
+def test_grouped_fit_matches_oracle(ants, g, kind, shift):
+    lrf, sig, r = _inputs(g, 20_000, 60 + g)
+    n, ns = len(sig), lrf.sxy.shape[0]
+    print(f"[gpu] grouped LRF fit, {ns} sensors, {kind}, shift {shift}", flush=True)
+    if kind == "individual":
+        groups = np.arange(ns, dtype=np.int32)
+    elif kind == "ring":
+        groups = _ring_groups(lrf.sxy)
+    else:
+        groups = (np.arange(ns) % 3).astype(np.int32)
+        groups[[1, 4]] = -1                              # left out
+        groups[7] = 5                                    # groups 3 and 4 empty
+    sh = np.random.default_rng(g).normal(0.0, 1.5, (n, 2)).astype(np.float32) if shift else None
+    L = ants.LrfSet(lrf)
+    nb, lo, hi = lrf.nb[0], lrf.lo[0], lrf.hi[0]
+    cfg = ants.fit_cfg(nb, lo, hi, 1e-9, 0.0)
+    d_sh = torch.from_numpy(sh).cuda() if shift else None
+    coef, counts = ants.fit_axial_lrf_grouped(L, cfg, groups, torch.from_numpy(sig).cuda(),
+                                              _dev(ants, r), d_sh)
+    torch.cuda.synchronize()
+    use = F.event_mask(r["E"], r["status"])
+    x64 = {k: r[k].astype(np.float64) for k in ("x", "y", "E")}
+    ref, pairs = F.fit_axial_grouped(lrf.sxy, lrf.gain, lrf.active, sig.astype(np.float64),
+                                     x64["x"], x64["y"], x64["E"], use, nb, lo, hi, groups,
+                                     ridge=1e-9,
+                                     shift=sh.astype(np.float64) if shift else None)
+    got = coef.cpu().numpy()
+    c = counts.cpu().numpy()
+    assert got.shape == ref.shape
+    for k in range(len(ref)):
+        if pairs[k] == 0:
+            assert np.isnan(got[k]).all() and c[k, 1] == 0, k
+            continue
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-9 * np.max(np.abs(ref[k])), k
+        assert c[k, 1] == pairs[k] and c[k, 0] == int(use.sum()), k
+    again, _ = ants.fit_axial_lrf_grouped(L, cfg, groups, torch.from_numpy(sig).cuda(),
+                                          _dev(ants, r), d_sh)
+    np.testing.assert_array_equal(again.cpu().numpy(), got)
+
+
+def test_one_group_equals_the_shared_fit(ants):
+    lrf, sig, r = _inputs(1, 8_000, 71)
+    L = ants.LrfSet(lrf)
+    cfg = ants.fit_cfg(lrf.nb[0], lrf.lo[0], lrf.hi[0], 1e-9, 0.0)
+    a, ca = ants.fit_axial_lrf(L, cfg, torch.from_numpy(sig).cuda(), _dev(ants, r))
+    b, cb = ants.fit_axial_lrf_grouped(L, cfg, np.zeros(lrf.sxy.shape[0], np.int32),
+                                       torch.from_numpy(sig).cuda(), _dev(ants, r))
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy()[0])
+    np.testing.assert_array_equal(ca.cpu().numpy(), cb.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("g", [1, 2])
+def test_gains_within_groups_match_oracle(ants, g):
+    lrf, sig, r = _inputs(g, 20_000, 80 + g)
+    ns = lrf.sxy.shape[0]
+    print(f"[gpu] gains within groups, {ns} sensors", flush=True)
+    ring = _ring_groups(lrf.sxy)
+    ring[3] = -1
+    base = np.asarray(lrf.coef, np.float64).reshape(-1)
+    tables = np.stack([base * (1.0 + 0.05 * k) for k in range(ring.max() + 1)])
+    L = ants.LrfSet(lrf)
+    nb, lo, hi = lrf.nb[0], lrf.lo[0], lrf.hi[0]
+    gains, pairs = ants.fit_axial_gains(L, ants.fit_cfg(nb, lo, hi), tables, ring,
+                                        torch.from_numpy(sig).cuda(), _dev(ants, r))
+    torch.cuda.synchronize()
+    use = F.event_mask(r["E"], r["status"])
+    x64 = {k: r[k].astype(np.float64) for k in ("x", "y", "E")}
+    ref, rp = F.fit_gains(lrf.sxy, lrf.active, sig.astype(np.float64), x64["x"], x64["y"],
+                          x64["E"], use, nb, lo, hi, tables, ring)
+    got = gains.cpu().numpy()
+    fitted = np.isfinite(ref)
+    assert np.isnan(got[3]) and pairs.cpu().numpy()[3] == 0
+    np.testing.assert_allclose(got[fitted], ref[fitted], rtol=1e-10)
+    np.testing.assert_array_equal(np.isfinite(got), fitted)
+    np.testing.assert_array_equal(pairs.cpu().numpy(), rp)
+
+
+def test_iteration_with_groups_shift_and_a_disabled_sensor(ants):
+    # Sec. 8 options: one common LRF first, then per-ring LRFs; a random
+    # shift in the first fit; sensor 30 left out of the second
+    # reconstruction.  Each step equals the entry points called by hand.
+    true_lrf, rec = W.mixed_geometries()[1]
+    Lt = ants.LrfSet(true_lrf)
+    sig, truth = ants.generate(Lt, ants.gen_cfg(rec), 50_000, 6)
+    grid = ants.grid_cfg(W.workload(3).grid)
+    wrong = W.axial_lrf(true_lrf.sxy, h=12.0)
+    start = ants.AxialModel(wrong.sxy, wrong.gain, wrong.active, wrong.nb[0], wrong.lo[0],
+                            wrong.hi[0], np.asarray(wrong.coef).reshape(-1))
+    ns = true_lrf.sxy.shape[0]
+    rings = ants.groups_by_distance(true_lrf.sxy)
+    sched = lambda k: ants.groups_all(ns) if k == 0 else rings
+    models, last = ants.iterate_axial_lrf(start, grid, sig, 2, groups=sched, shift_sigma=1.0,
+                                          shift_iterations=1, shift_seed=11, disable={1: [30]})
+    assert len(models) == 3 and models[1].shared == 1 and models[2].shared == 0
+    # by hand: the second step
+    m1 = models[1]
+    act = np.asarray(m1.active, np.uint8).copy()
+    act[30] = 0
+    Lr = ants.LrfSet(m1.with_active(act))
+    o = ants.reconstruct(Lr, grid, sig)
+    Lf = ants.LrfSet(m1)
+    cfg = ants.fit_cfg(m1.nb[0], m1.lo[0], m1.hi[0])
+    coef, _ = ants.fit_axial_lrf_grouped(Lf, cfg, rings, sig, o)
+    torch.cuda.synchronize()
+    c = coef.cpu().numpy()
+    np.testing.assert_array_equal(models[2].coef.reshape(ns, -1), c[rings])
+    assert int(o["status"].cpu().numpy()[0] >= 0)
+    # the disabled sensor's LRF is still fitted (its ring's table)
+    assert np.isfinite(models[2].coef.reshape(ns, -1)[30]).all()

@@ -55,7 +55,7 @@ FLOP_PER_EVAL_XY_CHI2 = 78
 # 2 FMA + TRANS) of SQ_INSTS_VALU_*_F32 / kernel time, as recorded in
 # profiles/cg_kernel_rz_hex37_10M_plain_and_refine.md (reported beside the
 # canonical fraction, which counts the bicubic the oracle evaluates)
-COUNTER_FRAC = {"plain": 0.227, "refine": 0.087}
+COUNTER_FRAC = {"plain": 0.221, "refine": 0.092}
 
 
 def parse():
@@ -72,6 +72,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=48_000,
                     help="events for the oracle CPU baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=160207247)
+    ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
+                                                        "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the HBM traffic record of the plain and refinement kernels "
+                         "from rocprofv3 --pmc counter CSVs of a benchmark run (FETCH_SIZE, "
+                         "then WRITE_SIZE) and of --copy-probe runs; no GPU use")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch plans (profiling runs: every dispatch of a "
                          "kernel then covers the full batch)")
@@ -580,6 +585,49 @@ def timed(fn, steps, warmup, stream):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_kernel_rz_hex37_10M_traffic.json")
 
 
+def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """HBM bytes per launch of the headline's two kernels from rocprofv3
+    counter summaries (KiB per dispatch), each counter scaled so that a
+    1 GiB device copy reads as 1 GiB; the plain grid's full-batch launches
+    are told from its fallback launches (same kernel) by their size."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return rows
+
+    def copy_kib(path, counter):
+        vals = [v for k, vs in per_kernel(path, counter).items() for v in vs]
+        return max(vals)
+
+    gib_kib = float(1 << 20)
+    fscale = gib_kib / copy_kib(copy_fetch_csv, "FETCH_SIZE")
+    wscale = gib_kib / copy_kib(copy_write_csv, "WRITE_SIZE")
+    kernels = {}
+    for tag, key in (("plain", "<3, 0, 6, 1, true, 7>"), ("refine", "<3, 0, 1, 1, true, 3>")):
+        out = {}
+        for name, path, counter, scale in (("read_bytes", fetch_csv, "FETCH_SIZE", fscale),
+                                           ("write_bytes", write_csv, "WRITE_SIZE", wscale)):
+            vals = [v for k, vs in per_kernel(path, counter).items() if key in k for v in vs]
+            big = [v for v in vals if v > 0.1 * max(vals)]
+            out[name] = 1024.0 * scale * float(np.mean(big))
+        out["traffic"] = out["read_bytes"] + out["write_bytes"]
+        kernels[tag] = out
+    rec = {"source_sha256": kernel_source_hash(),
+           "note": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB), scaled "
+                   "by the readings of a 1 GiB device copy; valid only for kernels built from "
+                   "sources with this hash",
+           "fetch_scale": fscale, "write_scale": wscale, "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def kernel_source_hash():
     import glob
     import hashlib
@@ -652,6 +700,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.traffic_json:
+        write_traffic(*args.traffic_json)
+        return
     if args.copy_probe:
         copy_probe()
         return

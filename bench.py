@@ -77,6 +77,9 @@ def parse():
                     help="write the HBM traffic record of the plain and refinement kernels "
                          "from rocprofv3 --pmc counter CSVs of a benchmark run (FETCH_SIZE, "
                          "then WRITE_SIZE) and of --copy-probe runs; no GPU use")
+    ap.add_argument("--mixed-geometry", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="mixed workload: run only the chunks of one detector (0: 19, 1: 61, "
+                         "2: 127 sensors), e.g. for per-geometry counters")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch plans (profiling runs: every dispatch of a "
                          "kernel then covers the full batch)")
@@ -121,8 +124,21 @@ def mixed_stream(args):
         chunks.append((g, bufs[g][used[g]:used[g] + n], off))
         used[g] += n
         off += n
+    if args.mixed_geometry >= 0:
+        # one detector's chunks only, packed into consecutive output rows
+        sel, off = [], 0
+        for g, buf, _ in chunks:
+            if g == args.mixed_geometry:
+                sel.append((g, buf, off))
+                off += buf.shape[0]
+        chunks, total = sel, off
+        keep = geoms == args.mixed_geometry
+        sizes, geoms = sizes[keep], geoms[keep]
     torch.cuda.synchronize()
-    best, ms = ants.autotune_multi(sets, cfgs, chunks, min(total, 1_000_000))
+    if args.no_tune:
+        best, ms = None, []
+    else:
+        best, ms = ants.autotune_multi(sets, cfgs, chunks, min(total, 1_000_000))
     out = ants.alloc_out(total)
     wall, ev = timed(lambda: ants.reconstruct_multi(sets, cfgs, chunks, total, plan=best, out=out,
                                                     stream=stream), args.steps, args.warmup,
@@ -133,6 +149,24 @@ def mixed_stream(args):
                 for g, s in enumerate(sets))
     flops = evals * FLOP_PER_EVAL_AXIAL_ML
     achieved = flops / (ev * 1e-3) / 1e12
+    # each detector's chunks alone through the same launch and plan
+    per_geom = {}
+    if args.mixed_geometry < 0:
+        for g in range(3):
+            sel, o = [], 0
+            for gg, buf, _ in chunks:
+                if gg == g:
+                    sel.append((gg, buf, o))
+                    o += buf.shape[0]
+            og = ants.alloc_out(o)
+            wg, eg = timed(lambda: ants.reconstruct_multi(sets, cfgs, sel, o, plan=best, out=og,
+                                                          stream=stream), 2, 1, stream)
+            fg = int(np.prod(grid.nodes)) * grid.iterations * sets[g].n_active * o * \
+                FLOP_PER_EVAL_AXIAL_ML
+            per_geom["hex%d" % sets[g].n_active] = {
+                "events": o, "events_per_s": o / wg, "kernel_ms": eg,
+                "canonical_tflops": fg / (eg * 1e-3) / 1e12,
+                "frac": fg / (eg * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
     rec = {"metric": "events/s reconstructed, mixed 19/61/127-sensor stream, one persistent launch",
            "value": total / wall, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * wall, "higher_is_better": True,
@@ -140,8 +174,10 @@ def mixed_stream(args):
            "data": "synthetic (flood-field events drawn on the GPU from the LRF model)",
            "config": {"workload": "hex19/61/127 axial LRFs, 20M events in %d lognormal chunks, "
                                   "9x9 grid x 6 iterations" % len(sizes), "events": total},
-           "plan": {"events_per_item": best.events_per_item, "blocks_per_cu": best.blocks_per_cu,
-                    "table_in_lds": best.table_in_lds},
+           "plan": ({"events_per_item": best.events_per_item,
+                     "blocks_per_cu": best.blocks_per_cu, "table_in_lds": best.table_in_lds}
+                    if best is not None else "default"),
+           "per_geometry": per_geom,
            "default_plan_events_per_s": total / wall_d,
            "autotune_ms": [float(v) for v in ms],
            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,

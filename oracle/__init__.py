@@ -65,6 +65,13 @@ class _SCfg(C.Structure):
                 ("max_iter", C.c_int), ("l_floor", C.c_double), ("v_floor", C.c_double)]
 
 
+class _VCfg(C.Structure):
+    _fields_ = [("dims", C.c_int), ("stat", C.c_int), ("start", C.c_int),
+                ("step0", C.c_double * 3), ("z_start", C.c_double), ("h", C.c_double),
+                ("edm_tol", C.c_double), ("max_iter", C.c_int), ("l_floor", C.c_double),
+                ("v_floor", C.c_double)]
+
+
 _lib = None
 
 
@@ -98,6 +105,9 @@ def lib():
                                            C.c_int, i64, P(d), P(d), P(C.c_int), P(i64),
                                            P(C.c_float), C.c_int]
         _lib.o_reconstruct_simplex.argtypes = [P(_Lrf), P(_SCfg), i64, P(d), P(d), P(d),
+                                               P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int),
+                                               C.c_int]
+        _lib.o_reconstruct_migrad.argtypes = [P(_Lrf), P(_VCfg), i64, P(d), P(d), P(d),
                                                P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int),
                                                C.c_int]
         u32 = C.c_uint32
@@ -362,6 +372,43 @@ def _scfg(g):
     c.z_start, c.tol, c.max_iter = float(g.z_start), float(g.tol), int(g.max_iter)
     c.l_floor, c.v_floor = float(g.l_floor), float(g.v_floor)
     return c
+
+
+def _vcfg(g):
+    c = _VCfg()
+    c.dims, c.stat, c.start = int(g.dims), int(g.stat), int(g.start)
+    for k in range(3):
+        c.step0[k] = float(g.step0[k])
+    c.z_start, c.h, c.edm_tol = float(g.z_start), float(g.h), float(g.edm_tol)
+    c.max_iter = int(g.max_iter)
+    c.l_floor, c.v_floor = float(g.l_floor), float(g.v_floor)
+    return c
+
+
+def reconstruct_migrad(lrf, vcfg, signals, seeds=None, threads=None):
+    """Variable-metric (Migrad-style) search per event (FP64).  Returns a
+    dict: x, y, z, E, lnl, chi2, ndf, status, iters (accepted steps) and
+    evals (statistic evaluations)."""
+    m = lrf if isinstance(lrf, Model) else Model(lrf)
+    sig = np.ascontiguousarray(signals, dtype=np.float64)
+    n = sig.shape[0]
+    assert sig.shape[1] == m.n_sensors
+    out6 = np.empty((n, 6), np.float64)
+    ndf = np.empty(n, np.int32)
+    status = np.empty(n, np.int32)
+    iters = np.empty(n, np.int32)
+    evals = np.empty(n, np.int32)
+    sd = None
+    if seeds is not None:
+        sd = np.ascontiguousarray(seeds, dtype=np.float64)
+        assert sd.shape == (n, 4)
+    c = _vcfg(vcfg)
+    lib().o_reconstruct_migrad(C.byref(m.c), C.byref(c), n, _dp(sig),
+                               _dp(sd) if sd is not None else None, _dp(out6), _ip(ndf),
+                               _ip(status), _ip(iters), _ip(evals), _threads(threads))
+    return {"x": out6[:, 0], "y": out6[:, 1], "z": out6[:, 2], "E": out6[:, 3],
+            "lnl": out6[:, 4], "chi2": out6[:, 5], "ndf": ndf, "status": status,
+            "iters": iters, "evals": evals}
 
 
 def reconstruct_simplex(lrf, scfg, signals, seeds=None, threads=None):

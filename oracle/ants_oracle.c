@@ -899,6 +899,186 @@ void o_reconstruct_simplex(const o_lrf* L, const o_scfg* S, int64_t n_ev, const 
 }
 
 /* ------------------------------------------------------------------ */
+/* Variable-metric search per event (Sec. 5.1.2.1: the Minuit2 Migrad    */
+/* minimiser, a variable-metric method with numerical derivatives, over  */
+/* x, y or x, y, z from the centroid, the strongest sensor or a seed).   */
+/* The statistic is the grid's node statistic (ML or chi2, energy from   */
+/* the ratio of the sums).  Readings (the paper names the library, not   */
+/* its steps; written from the textbook quasi-Newton method):            */
+/*  - gradient g by central differences with step h (mm) per searched    */
+/*    axis: g_a = (F(p + h e_a) - F(p - h e_a)) / (2 h);                  */
+/*  - initial inverse curvature V diagonal: V_aa = 1 / d2_a with          */
+/*    d2_a = (F(p + h e_a) - 2 F(p) + F(p - h e_a)) / h^2 from the same    */
+/*    points, or step0_a^2 where d2_a is not positive and finite;        */
+/*  - estimated distance to the minimum EDM = g^T V g / 2; stop when      */
+/*    EDM < edm_tol, or after max_iter iterations;                        */
+/*  - direction d = -V g; if g^T d >= 0, V is reset to diag(step0^2);     */
+/*    if still g^T d >= 0, stop;                                          */
+/*  - line search: alpha = 1, halved (at most 20 times) until            */
+/*    F(p + alpha d) <= F(p) + 1e-4 alpha g^T d; no such alpha: stop;     */
+/*  - BFGS update of V with s = p' - p, y = g' - g when s^T y > 0:       */
+/*    V' = V + (s^T y + y^T V y) / (s^T y)^2 s s^T                        */
+/*           - (V y s^T + s y^T V) / (s^T y);                             */
+/*  - a start where F is not finite gives NO_VALID_NODE (the start is    */
+/*    reported); a non-finite gradient ends the search at the current    */
+/*    point (at the start, before any step).                              */
+/* An iteration is one accepted step.  Arithmetic as written (no fused   */
+/* multiply-add), sums in axis order.                                    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int dims;             /* 2: x, y;  3: x, y, z                          */
+  int stat;             /* 0 ML, 1 chi2                                  */
+  int start;            /* 0 CoG, 1 strongest sensor, 2 seed             */
+  double step0[3];      /* scale per axis (mm): fallback curvature        */
+  double z_start;
+  double h;             /* central-difference step (mm)                   */
+  double edm_tol;       /* stop when EDM < edm_tol                        */
+  int max_iter;
+  double l_floor, v_floor;
+} o_vcfg;
+
+static double o_vm_f(const o_lrf* L, const o_cfg* C, const double* n, double N, const double p[3],
+                     int* nev) {
+  ++*nev;
+  double f = o_node_eval(L, C, n, N, p[0], p[1], p[2]).stat;
+  return isfinite(f) ? f : INFINITY;
+}
+
+/* central-difference gradient and curvature estimates at p (F(p) = f);
+ * returns 0 when a value is not finite */
+static int o_vm_grad(const o_lrf* L, const o_cfg* C, const double* n, double N, const double p[3],
+                     double f, int d, double h, double g[3], double d2[3], int* nev) {
+  for (int a = 0; a < 3; ++a) { g[a] = 0.0; d2[a] = 0.0; }
+  for (int a = 0; a < d; ++a) {
+    double q[3] = {p[0], p[1], p[2]};
+    q[a] = p[a] + h;
+    const double fp = o_vm_f(L, C, n, N, q, nev);
+    q[a] = p[a] - h;
+    const double fm = o_vm_f(L, C, n, N, q, nev);
+    if (!isfinite(fp) || !isfinite(fm)) return 0;
+    g[a] = (fp - fm) / (2.0 * h);
+    d2[a] = ((fp - 2.0 * f) + fm) / (h * h);
+  }
+  return 1;
+}
+
+void o_migrad_event(const o_lrf* L, const o_vcfg* S, const double* n, const double* seed,
+                    double out[6], int* ndf, int* status, int* iters, int* evals) {
+  int ns = L->n_sensors, na = 0, bad = 0, d = S->dims;
+  double N = 0.0;
+  *status = 0;
+  *iters = 0;
+  *evals = 0;
+  for (int i = 0; i < ns; ++i) {
+    if (!L->active[i]) continue;
+    ++na;
+    if (!isfinite(n[i]) || n[i] < 0.0) bad = 1;
+    else N += n[i];
+  }
+  *ndf = na - (d + 1);
+  for (int k = 0; k < 6; ++k) out[k] = NAN;
+  if (na == 0) { *status = O_NO_ACTIVE; return; }
+  if (bad) { *status = O_BAD_INPUT; return; }
+  if (!(N > 0.0)) { *status = O_EMPTY; return; }
+  o_cfg C;
+  memset(&C, 0, sizeof(C));
+  C.stat = S->stat;
+  C.l_floor = S->l_floor;
+  C.v_floor = S->v_floor;
+  double p[3] = {0.0, 0.0, S->z_start};
+  if (S->start == 2 && seed) {
+    p[0] = seed[0]; p[1] = seed[1];
+    if (d == 3) p[2] = seed[2];
+  } else if (S->start == 1) {
+    int best = -1;
+    for (int i = 0; i < ns; ++i)
+      if (L->active[i] && (best < 0 || n[i] > n[best])) best = i;
+    p[0] = L->sxy[2 * best]; p[1] = L->sxy[2 * best + 1];
+  } else {
+    double sw = 0.0, sx = 0.0, sy = 0.0;
+    for (int i = 0; i < ns; ++i) {
+      if (!L->active[i]) continue;
+      double w = n[i] / L->gain[i];
+      sw += w; sx += L->sxy[2 * i] * w; sy += L->sxy[2 * i + 1] * w;
+    }
+    p[0] = sx / sw; p[1] = sy / sw;
+  }
+  int nev = 0, it = 0;
+  double f = o_vm_f(L, &C, n, N, p, &nev);
+  double g[3], d2[3], V[3][3];
+  if (isfinite(f) && o_vm_grad(L, &C, n, N, p, f, d, S->h, g, d2, &nev)) {
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) V[a][b] = 0.0;
+    for (int a = 0; a < d; ++a)
+      V[a][a] = (d2[a] > 0.0 && isfinite(d2[a])) ? 1.0 / d2[a] : S->step0[a] * S->step0[a];
+    while (it < S->max_iter) {
+      /* EDM = g^T V g / 2, direction -V g, slope g^T dir */
+      double Vg[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) Vg[a] += V[a][b] * g[b];
+      double edm = 0.0;
+      for (int a = 0; a < d; ++a) edm += g[a] * Vg[a];
+      edm = 0.5 * edm;
+      if (edm < S->edm_tol) break;
+      double dir[3] = {0.0, 0.0, 0.0}, slope = 0.0;
+      for (int a = 0; a < d; ++a) { dir[a] = -Vg[a]; slope += g[a] * dir[a]; }
+      if (!(slope < 0.0)) {
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b) V[a][b] = (a == b) ? S->step0[a] * S->step0[a] : 0.0;
+        slope = 0.0;
+        for (int a = 0; a < d; ++a) { dir[a] = -(V[a][a] * g[a]); slope += g[a] * dir[a]; }
+        if (!(slope < 0.0)) break;
+      }
+      double alpha = 1.0, pt[3] = {p[0], p[1], p[2]}, ft = INFINITY;
+      int ok = 0;
+      for (int ls = 0; ls <= 20; ++ls) {
+        for (int a = 0; a < d; ++a) pt[a] = p[a] + alpha * dir[a];
+        ft = o_vm_f(L, &C, n, N, pt, &nev);
+        if (ft <= f + 1e-4 * alpha * slope) { ok = 1; break; }
+        alpha = 0.5 * alpha;
+      }
+      if (!ok) break;
+      double gn[3], d2n[3];
+      const int gok = o_vm_grad(L, &C, n, N, pt, ft, d, S->h, gn, d2n, &nev);
+      double sv[3] = {0.0, 0.0, 0.0}, yv[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < d; ++a) { sv[a] = pt[a] - p[a]; yv[a] = gn[a] - g[a]; }
+      for (int a = 0; a < 3; ++a) p[a] = pt[a];
+      f = ft;
+      ++it;
+      if (!gok) break;
+      double sy = 0.0;
+      for (int a = 0; a < d; ++a) sy += sv[a] * yv[a];
+      if (sy > 0.0) {
+        double Vy[3] = {0.0, 0.0, 0.0}, yVy = 0.0;
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b) Vy[a] += V[a][b] * yv[b];
+        for (int a = 0; a < d; ++a) yVy += yv[a] * Vy[a];
+        const double c1 = (sy + yVy) / (sy * sy);
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b)
+            V[a][b] = (V[a][b] + c1 * (sv[a] * sv[b])) - (Vy[a] * sv[b] + sv[a] * Vy[b]) / sy;
+      }
+      for (int a = 0; a < 3; ++a) g[a] = gn[a];
+    }
+  }
+  *iters = it;
+  *evals = nev;
+  o_node fin = o_node_eval(L, &C, n, N, p[0], p[1], p[2]);
+  out[0] = p[0]; out[1] = p[1]; out[2] = p[2];
+  out[3] = fin.A; out[4] = fin.lnl; out[5] = fin.chi2;
+  if (!isfinite(f) || !(fin.S > 0.0)) *status |= O_NO_VALID_NODE;
+}
+
+void o_reconstruct_migrad(const o_lrf* L, const o_vcfg* S, int64_t n_ev, const double* sig,
+                          const double* seeds, double* out6, int* ndf, int* status, int* iters,
+                          int* evals, int n_threads) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+  for (int64_t e = 0; e < n_ev; ++e)
+    o_migrad_event(L, S, sig + e * L->n_sensors, seeds ? seeds + 4 * e : NULL, out6 + 6 * e,
+                   ndf + e, status + e, iters + e, evals + e);
+}
+
+/* ------------------------------------------------------------------ */
 /* k-NN reconstruction (Sec. 5.1.4): each event is a point whose        */
 /* coordinates are the normalised signals of the sensors; the position  */
 /* is the centroid of the known positions of the k calibration events   */

@@ -162,6 +162,23 @@ class SimplexCfg:
 
 
 @dataclass
+class MigradCfg:
+    """Variable-metric (Migrad-style) search settings: searched axes,
+    statistic, start, per-axis scale (fallback curvature), central-difference
+    step, EDM tolerance, iteration cap."""
+    dims: int = 2              # 2: x, y; 3: x, y, z
+    stat: int = 0              # 0 ML, 1 chi2
+    start: int = 0             # 0 CoG, 1 strongest sensor, 2 seed
+    step0: tuple = (7.5, 7.5, 0.0)
+    z_start: float = 0.0
+    h: float = 1e-3            # mm
+    edm_tol: float = 1e-6      # statistic units
+    max_iter: int = 100
+    l_floor: float = 1e-9
+    v_floor: float = 1.0
+
+
+@dataclass
 class EventRecipe:
     region: str                # "disc" or "square"
     extent: float              # disc radius or square half-width (mm)

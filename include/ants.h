@@ -292,6 +292,44 @@ ants_status ants_reconstruct_simplex(ants_lrfset* set, const ants_simplex_cfg* c
                                      void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Variable-metric search (Sec. 5.1.2.1: the Minuit2 Migrad minimiser,  */
+/* a variable-metric method with numerical derivatives), over x, y or   */
+/* x, y, z from the centroid, the strongest sensor or a seed, on the    */
+/* grid's statistic.  Steps: gradient g by central differences with     */
+/* step h per searched axis; initial inverse curvature V diagonal, 1 /  */
+/* the central second difference at the start, or step0[a]^2 where that  */
+/* is not positive; EDM = g^T V g / 2, stop when EDM < edm_tol or after */
+/* max_iter accepted steps; direction -V g (V reset to diag(step0^2)    */
+/* when it is not a descent direction); step length 1 halved (at most  */
+/* 20 times) until F decreases by at least 1e-4 of the linear          */
+/* prediction; BFGS update of V when s^T y > 0.  Coordinates that are  */
+/* spline arguments (z of r-z and sliced LRFs, x and y of XY and sliced */
+/* LRFs) are limited to the spline's domain [lo, hi] as Minuit limits  */
+/* parameters: the search runs in u, position lo + (hi - lo)(sin u + 1)/2,*/
+/* with h and step0 divided by (hi - lo) / 2.  A non-finite gradient   */
+/* ends the search at the current point; a start with a non-finite     */
+/* statistic gives ANTS_EV_NO_VALID_NODE.  Everything is FP64.  Outputs */
+/* and d_iters / out.n_fp64 (accepted steps / evaluations) as for the   */
+/* simplex search.                                                      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t dims;          /* 2: x, y;  3: x, y, z (r-z and sliced LRFs only)  */
+  int32_t stat;          /* ants_stat                                        */
+  int32_t start;         /* ants_start; SEED reads d_seeds [n][4] (x, y, z, -) */
+  double step0[3];       /* per-axis scale, mm (> 0): the fallback curvature */
+  double z_start;        /* start z (also the output z of 2-D searches)      */
+  double h;              /* central-difference step, mm (> 0)               */
+  double edm_tol;        /* EDM stop, statistic units (> 0)                  */
+  int32_t max_iter;      /* cap on accepted steps, 0 .. 100000              */
+  double l_floor, v_floor;
+} ants_migrad_cfg;
+
+ants_status ants_reconstruct_migrad(ants_lrfset* set, const ants_migrad_cfg* cfg,
+                                    int64_t n_events, const float* d_signals,
+                                    const float* d_seeds, ants_out out, int32_t* d_iters,
+                                    void* hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* k-NN reconstruction (Sec. 5.1.4): an event is the point of its       */
 /* normalised active-sensor signals n_i / N (N = sum over the active    */
 /* sensors; divided in double, rounded to single precision); its        */

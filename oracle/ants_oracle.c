@@ -921,7 +921,16 @@ void o_reconstruct_simplex(const o_lrf* L, const o_scfg* S, int64_t n_ev, const 
 /*           - (V y s^T + s y^T V) / (s^T y);                             */
 /*  - a start where F is not finite gives NO_VALID_NODE (the start is    */
 /*    reported); a non-finite gradient ends the search at the current    */
-/*    point (at the start, before any step).                              */
+/*    point (at the start, before any step);                              */
+/*  - coordinates that are arguments of the LRF's splines are limited to */
+/*    the spline's domain [lo, hi] as Minuit limits parameters: the       */
+/*    search runs in an internal coordinate u with the position            */
+/*    lo + (hi - lo) (sin u + 1) / 2 (z for r-z and sliced LRFs, x and y  */
+/*    for XY and sliced LRFs); the start enters as u = asin(2 (p - lo) /   */
+/*    (hi - lo) - 1) (clamped into the domain), the difference step and   */
+/*    the fallback scale are divided by (hi - lo) / 2.  Beyond such a     */
+/*    wall the statistic jumps to infinity; in u the wall is a smooth     */
+/*    turning point, so searches that end against it stop reproducibly.  */
 /* An iteration is one accepted step.  Arithmetic as written (no fused   */
 /* multiply-add), sums in axis order.                                    */
 /* ------------------------------------------------------------------ */
@@ -944,22 +953,51 @@ static double o_vm_f(const o_lrf* L, const o_cfg* C, const double* n, double N, 
   return isfinite(f) ? f : INFINITY;
 }
 
-/* central-difference gradient and curvature estimates at p (F(p) = f);
- * returns 0 when a value is not finite */
-static int o_vm_grad(const o_lrf* L, const o_cfg* C, const double* n, double N, const double p[3],
-                     double f, int d, double h, double g[3], double d2[3], int* nev) {
+/* central-difference gradient and curvature estimates at internal point u
+ * (statistic f there), steps hs per axis; returns 0 when a value is not
+ * finite */
+static void o_vm_ext(const o_lrf* L, int d, const double u[3], const double z_start, double p[3]);
+static int o_vm_grad(const o_lrf* L, const o_cfg* C, const double* n, double N, const double u[3],
+                     double f, int d, const double hs[3], double z_start, double g[3],
+                     double d2[3], int* nev) {
   for (int a = 0; a < 3; ++a) { g[a] = 0.0; d2[a] = 0.0; }
   for (int a = 0; a < d; ++a) {
-    double q[3] = {p[0], p[1], p[2]};
-    q[a] = p[a] + h;
-    const double fp = o_vm_f(L, C, n, N, q, nev);
-    q[a] = p[a] - h;
-    const double fm = o_vm_f(L, C, n, N, q, nev);
+    double q[3] = {u[0], u[1], u[2]}, x[3];
+    q[a] = u[a] + hs[a];
+    o_vm_ext(L, d, q, z_start, x);
+    const double fp = o_vm_f(L, C, n, N, x, nev);
+    q[a] = u[a] - hs[a];
+    o_vm_ext(L, d, q, z_start, x);
+    const double fm = o_vm_f(L, C, n, N, x, nev);
     if (!isfinite(fp) || !isfinite(fm)) return 0;
-    g[a] = (fp - fm) / (2.0 * h);
-    d2[a] = ((fp - 2.0 * f) + fm) / (h * h);
+    g[a] = (fp - fm) / (2.0 * hs[a]);
+    d2[a] = ((fp - 2.0 * f) + fm) / (hs[a] * hs[a]);
   }
   return 1;
+}
+
+/* limits of searched axis a (0 x, 1 y, 2 z) from the LRF's spline domain */
+static int o_vm_limit(const o_lrf* L, int a, double* lo, double* hi) {
+  if (a == 2 && (L->kind == 3 || L->kind == 5)) {
+    *lo = L->kind == 3 ? L->lo[1] : L->z_lo;
+    *hi = L->kind == 3 ? L->hi[1] : L->z_hi;
+    return 1;
+  }
+  if (a < 2 && (L->kind == 2 || L->kind == 5)) {
+    *lo = L->lo[a];
+    *hi = L->hi[a];
+    return 1;
+  }
+  return 0;
+}
+
+/* position of internal point u (limited axes transformed) */
+static void o_vm_ext(const o_lrf* L, int d, const double u[3], const double z_start, double p[3]) {
+  p[0] = u[0]; p[1] = u[1]; p[2] = d == 3 ? u[2] : z_start;
+  for (int a = 0; a < d; ++a) {
+    double lo, hi;
+    if (o_vm_limit(L, a, &lo, &hi)) p[a] = lo + (0.5 * (hi - lo)) * (sin(u[a]) + 1.0);
+  }
 }
 
 void o_migrad_event(const o_lrf* L, const o_vcfg* S, const double* n, const double* seed,
@@ -1003,14 +1041,29 @@ void o_migrad_event(const o_lrf* L, const o_vcfg* S, const double* n, const doub
     }
     p[0] = sx / sw; p[1] = sy / sw;
   }
+  /* internal coordinates, difference steps and fallback scales */
+  double u[3] = {p[0], p[1], p[2]}, hs[3], s0[3];
+  for (int a = 0; a < 3; ++a) { hs[a] = S->h; s0[a] = S->step0[a]; }
+  for (int a = 0; a < d; ++a) {
+    double lo, hi;
+    if (!o_vm_limit(L, a, &lo, &hi)) continue;
+    const double half = 0.5 * (hi - lo);
+    double w = (p[a] - lo) / half - 1.0;
+    w = w < -1.0 ? -1.0 : w > 1.0 ? 1.0 : w;
+    u[a] = asin(w);
+    hs[a] = S->h / half;
+    s0[a] = S->step0[a] / half;
+  }
   int nev = 0, it = 0;
-  double f = o_vm_f(L, &C, n, N, p, &nev);
+  double q[3];
+  o_vm_ext(L, d, u, S->z_start, q);
+  double f = o_vm_f(L, &C, n, N, q, &nev);
   double g[3], d2[3], V[3][3];
-  if (isfinite(f) && o_vm_grad(L, &C, n, N, p, f, d, S->h, g, d2, &nev)) {
+  if (isfinite(f) && o_vm_grad(L, &C, n, N, u, f, d, hs, S->z_start, g, d2, &nev)) {
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) V[a][b] = 0.0;
     for (int a = 0; a < d; ++a)
-      V[a][a] = (d2[a] > 0.0 && isfinite(d2[a])) ? 1.0 / d2[a] : S->step0[a] * S->step0[a];
+      V[a][a] = (d2[a] > 0.0 && isfinite(d2[a])) ? 1.0 / d2[a] : s0[a] * s0[a];
     while (it < S->max_iter) {
       /* EDM = g^T V g / 2, direction -V g, slope g^T dir */
       double Vg[3] = {0.0, 0.0, 0.0};
@@ -1024,25 +1077,26 @@ void o_migrad_event(const o_lrf* L, const o_vcfg* S, const double* n, const doub
       for (int a = 0; a < d; ++a) { dir[a] = -Vg[a]; slope += g[a] * dir[a]; }
       if (!(slope < 0.0)) {
         for (int a = 0; a < d; ++a)
-          for (int b = 0; b < d; ++b) V[a][b] = (a == b) ? S->step0[a] * S->step0[a] : 0.0;
+          for (int b = 0; b < d; ++b) V[a][b] = (a == b) ? s0[a] * s0[a] : 0.0;
         slope = 0.0;
         for (int a = 0; a < d; ++a) { dir[a] = -(V[a][a] * g[a]); slope += g[a] * dir[a]; }
         if (!(slope < 0.0)) break;
       }
-      double alpha = 1.0, pt[3] = {p[0], p[1], p[2]}, ft = INFINITY;
+      double alpha = 1.0, ut[3] = {u[0], u[1], u[2]}, ft = INFINITY;
       int ok = 0;
       for (int ls = 0; ls <= 20; ++ls) {
-        for (int a = 0; a < d; ++a) pt[a] = p[a] + alpha * dir[a];
-        ft = o_vm_f(L, &C, n, N, pt, &nev);
+        for (int a = 0; a < d; ++a) ut[a] = u[a] + alpha * dir[a];
+        o_vm_ext(L, d, ut, S->z_start, q);
+        ft = o_vm_f(L, &C, n, N, q, &nev);
         if (ft <= f + 1e-4 * alpha * slope) { ok = 1; break; }
         alpha = 0.5 * alpha;
       }
       if (!ok) break;
       double gn[3], d2n[3];
-      const int gok = o_vm_grad(L, &C, n, N, pt, ft, d, S->h, gn, d2n, &nev);
+      const int gok = o_vm_grad(L, &C, n, N, ut, ft, d, hs, S->z_start, gn, d2n, &nev);
       double sv[3] = {0.0, 0.0, 0.0}, yv[3] = {0.0, 0.0, 0.0};
-      for (int a = 0; a < d; ++a) { sv[a] = pt[a] - p[a]; yv[a] = gn[a] - g[a]; }
-      for (int a = 0; a < 3; ++a) p[a] = pt[a];
+      for (int a = 0; a < d; ++a) { sv[a] = ut[a] - u[a]; yv[a] = gn[a] - g[a]; }
+      for (int a = 0; a < 3; ++a) u[a] = ut[a];
       f = ft;
       ++it;
       if (!gok) break;
@@ -1061,6 +1115,7 @@ void o_migrad_event(const o_lrf* L, const o_vcfg* S, const double* n, const doub
       for (int a = 0; a < 3; ++a) g[a] = gn[a];
     }
   }
+  o_vm_ext(L, d, u, S->z_start, p);
   *iters = it;
   *evals = nev;
   o_node fin = o_node_eval(L, &C, n, N, p[0], p[1], p[2]);

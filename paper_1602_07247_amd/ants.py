@@ -92,6 +92,13 @@ class GridPlan(C.Structure):
                 ("screen", C.c_int32)]
 
 
+class MigradCfg(C.Structure):
+    _fields_ = [("dims", C.c_int32), ("stat", C.c_int32), ("start", C.c_int32),
+                ("step0", C.c_double * 3), ("z_start", C.c_double), ("h", C.c_double),
+                ("edm_tol", C.c_double), ("max_iter", C.c_int32), ("l_floor", C.c_double),
+                ("v_floor", C.c_double)]
+
+
 class SimplexCfg(C.Structure):
     _fields_ = [("dims", C.c_int32), ("stat", C.c_int32), ("start", C.c_int32),
                 ("step0", C.c_double * 3), ("z_start", C.c_double), ("tol", C.c_double),
@@ -151,6 +158,8 @@ _lib.ants_autotune.argtypes = [_vp, C.POINTER(GridCfg), C.c_int64, _vp, _vp, Out
 _lib.ants_set_plan.argtypes = [_vp, C.POINTER(GridCfg), C.POINTER(GridPlan)]
 _lib.ants_reconstruct_simplex.argtypes = [_vp, C.POINTER(SimplexCfg), C.c_int64, _vp, _vp, Out,
                                           _vp, _vp]
+_lib.ants_reconstruct_migrad.argtypes = [_vp, C.POINTER(MigradCfg), C.c_int64, _vp, _vp, Out,
+                                          _vp, _vp]
 
 _lib.ants_knn_create.argtypes = [_vp, C.c_int64, _vp, _vp, C.POINTER(_vp), _vp]
 _lib.ants_knn_destroy.argtypes = [_vp]
@@ -173,7 +182,7 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load",
             "ants_reconstruct_simplex", "ants_knn_create", "ants_knn_destroy",
             "ants_knn_reconstruct", "ants_autotune", "ants_set_plan",
-            "ants_fit_axial_lrf_grouped", "ants_fit_axial_gains")
+            "ants_fit_axial_lrf_grouped", "ants_fit_axial_gains", "ants_reconstruct_migrad")
 
 
 def _check(code):
@@ -377,6 +386,44 @@ def reconstruct_simplex(lrfset: LrfSet, cfg: SimplexCfg, signals, seeds=None, ou
     it = out["iters"].data_ptr() if "iters" in out else None
     _check(_lib.ants_reconstruct_simplex(lrfset.handle, C.byref(cfg), n, signals.data_ptr(), sp,
                                          _out_struct(out), it, _stream_handle(stream)))
+    return out
+
+
+def migrad_cfg(g) -> MigradCfg:
+    """MigradCfg from an object with dims, stat, start, step0, z_start, h,
+    edm_tol, max_iter, l_floor, v_floor (see workloads.MigradCfg)."""
+    c = MigradCfg()
+    c.dims, c.stat, c.start = int(g.dims), int(g.stat), int(g.start)
+    for k in range(3):
+        c.step0[k] = float(g.step0[k])
+    c.z_start, c.h, c.edm_tol = float(g.z_start), float(g.h), float(g.edm_tol)
+    c.max_iter = int(g.max_iter)
+    c.l_floor, c.v_floor = float(g.l_floor), float(g.v_floor)
+    return c
+
+
+def reconstruct_migrad(lrfset: LrfSet, cfg: MigradCfg, signals, seeds=None, out=None,
+                       stream=None, iters=True, n_eval=False):
+    """Variable-metric search per event (ants_reconstruct_migrad).  Returns
+    the dict of output tensors, with "iters" (accepted steps per event) when
+    iters=True and "n_fp64" (statistic evaluations) when n_eval=True
+    (asynchronous)."""
+    import torch
+    assert signals.dtype == torch.float32 and signals.is_cuda and signals.is_contiguous()
+    n = signals.shape[0]
+    assert signals.dim() == 2 and signals.shape[1] == lrfset.n_sensors, signals.shape
+    if out is None:
+        out = alloc_out(n, 0, signals.device, n_fp64=n_eval)
+    if iters and "iters" not in out:
+        out["iters"] = torch.empty(n, dtype=torch.int32, device=signals.device)
+    sp = None
+    if seeds is not None:
+        assert seeds.dtype == torch.float32 and seeds.is_cuda and seeds.is_contiguous()
+        assert seeds.shape == (n, 4)
+        sp = seeds.data_ptr()
+    it = out["iters"].data_ptr() if "iters" in out else None
+    _check(_lib.ants_reconstruct_migrad(lrfset.handle, C.byref(cfg), n, signals.data_ptr(), sp,
+                                        _out_struct(out), it, _stream_handle(stream)))
     return out
 
 

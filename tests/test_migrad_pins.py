@@ -121,3 +121,38 @@ def test_iteration_cap_zero_and_status():
     r = oracle.reconstruct_migrad(wl.lrf, _cfg(), bad)
     np.testing.assert_array_equal(r["status"][:3], g["status"][:3])
     assert np.isnan(r["x"][:3]).all() and r["status"][3] == 0
+
+
+def test_limits_keep_the_search_in_the_domain_and_match_scipy_in_internal_coordinates():
+    # z of an r-z LRF is limited to the spline's domain [0, 50] as Minuit
+    # limits a parameter: z = lo + (hi - lo) (sin u + 1) / 2.  SciPy's BFGS
+    # on the same objective written in (x, y, u) reaches the same minimiser,
+    # also for events whose minimum lies against a wall of the domain.
+    wl, sig, truth = _events(300, 11)
+    mc = _cfg(edm_tol=1e-10)
+    r = oracle.reconstruct_migrad(wl.lrf, mc, sig)
+    lo, hi = wl.lrf.lo[1], wl.lrf.hi[1]
+    assert ((r["z"] >= lo) & (r["z"] <= hi)).all()
+    start = oracle.reconstruct(wl.lrf, W.GridCfg(iterations=0), sig)
+    half = 0.5 * (hi - lo)
+    agree = clean = walls = 0
+    for e in range(len(sig)):
+        f = _f(wl, mc, sig[e])
+
+        def fu(v):
+            return f([v[0], v[1], lo + half * (np.sin(v[2]) + 1.0)])
+        u0 = np.array([start["x"][e], start["y"][e],
+                       np.arcsin(np.clip((mc.z_start - lo) / half - 1.0, -1.0, 1.0))])
+        s = scipy_opt.minimize(fu, u0, method="BFGS", jac="3-point",
+                               options={"gtol": 1e-4, "maxiter": 400})
+        zs = lo + half * (np.sin(s.x[2]) + 1.0)
+        got = np.array([r["x"][e], r["y"][e], r["z"][e]])
+        if s.status != 0:
+            continue
+        clean += 1
+        walls += zs < lo + 0.5 or zs > hi - 0.5
+        same = np.max(np.abs(np.array([s.x[0], s.x[1], zs]) - got)) < 2e-3 or \
+            abs(s.fun - f(got)) < 1e-8 * abs(s.fun)
+        agree += same
+    assert clean >= 0.8 * len(sig) and walls >= 3, (clean, walls)
+    assert agree >= 0.95 * clean, (agree, clean)

@@ -86,8 +86,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="rz",
-                    choices=["rz", "mixed", "lrf_fit", "simplex", "migrad", "knn", "xy",
-                             "train"],
+                    choices=["rz", "axial", "mixed", "lrf_fit", "simplex", "migrad", "knn",
+                             "xy", "train"],
                     help="rz: the headline comparison; mixed: 19/61/127-sensor stream in one "
                          "persistent launch; lrf_fit: one step of the iterative LRF "
                          "reconstruction (reconstruct + refit) on the 61-sensor detector; "
@@ -506,6 +506,57 @@ def knn_step(args):
     print(json.dumps(rec), flush=True)
 
 
+def axial_step(args):
+    """The 19-sensor hexagonal detector with one axial LRF (pitch 30 mm,
+    20-knot cubic B-spline on [0, 150] mm), events uniform in r < 60 mm:
+    the 9 x 9 grid x 6 iterations (shrink 0.5) from the centroid, ML, over
+    10 M events (the 10 k-event configuration of the oracle is the parity
+    sample)."""
+    import torch
+    import workloads as W
+    from paper_1602_07247_amd import ants
+    wl = W.workload(0)
+    n = args.events
+    stream = torch.cuda.current_stream()
+    lrf = ants.LrfSet(wl.lrf)
+    g = ants.grid_cfg(wl.grid)
+    sig, truth = ants.generate(lrf, ants.gen_cfg(wl.events), n, args.seed)
+    nt = min(n, 1_000_000)
+    if args.no_tune:
+        plan, cand = ants.GridPlan(4, 0, 0), []
+    else:
+        plan, cand = ants.autotune(lrf, g, sig[:nt].contiguous(), stream=stream)
+    out = ants.alloc_out(n)
+    wall, ev = timed(lambda: ants.reconstruct(lrf, g, sig, out=out, stream=stream),
+                     args.steps, args.warmup, stream)
+    sx = sigma_xy(out, truth)
+    evals = int(np.prod(wl.grid.nodes)) * 19 * wl.grid.iterations
+    flops = n * evals * FLOP_PER_EVAL_AXIAL_ML
+    ach = flops / (ev * 1e-3) / 1e12
+    rec = {"metric": "events/s reconstructed, 19-sensor hex array with one axial LRF, 1 MI355X",
+           "value": n / wall, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * wall, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic (events drawn on the GPU from the LRF model)",
+           "config": {"workload": "hex19 axial LRF, %d events, 9x9 grid x 6 iterations, shrink "
+                                  "0.5, centroid start, ML" % n, "events": n},
+           "sigma_xy_mm": sx[0],
+           "plan": {"waves_per_block": plan.waves_per_block, "blocks_per_cu": plan.blocks_per_cu,
+                    "screen": plan.screen,
+                    "candidate_ms": [round(float(v), 4) for v in cand if v > 0]},
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                        "kernel": "cg_kernel<AXIAL,ML,NT=2,SL=1>", "kernel_ms": ev,
+                        "flop_per_launch": flops, "flop_per_eval": FLOP_PER_EVAL_AXIAL_ML}}
+    if args.cpu_sample > 0:
+        rec_cpu, ref = cpu_baseline(wl, sig[:min(n, 10_000)].cpu().numpy().astype(np.float64))
+        rec["cpu_baseline"] = rec_cpu
+        m = len(ref["x"])
+        got = {k: v[:m].cpu().numpy() for k, v in out.items()}
+        rec["parity"] = {"grid": parity_record(ref, got, sig[:m].cpu().numpy(), three_d=False)}
+    print(json.dumps(rec), flush=True)
+
+
 def xy_step(args):
     """The 8 x 8 square array (pitch 6 mm) with per-sensor bicubic XY LRFs
     (34 x 34 coefficients each, 296 KB in FP32) and gains U[0.8, 1.2]: 1M
@@ -847,6 +898,9 @@ def main():
         return
     if args.workload == "xy":
         xy_step(args)
+        return
+    if args.workload == "axial":
+        axial_step(args)
         return
     if args.workload == "train":
         train_step(args)

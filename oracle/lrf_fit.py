@@ -184,3 +184,95 @@ def fit_gains(sxy, active, signals, x, y, E, use, nb, lo, hi, tables, table_of, 
         if pairs[i] > 0 and den > 0.0:
             gains[i] = float(np.sum(t * L)) / den
     return gains, pairs
+
+
+# ---- two-dimensional LRFs: r-z (Sec. 6.1.1, r and depth) and XY (Sec.
+# 6.1.1, per-sensor bicubic in the detector plane)
+#
+# Readings: the same least squares as the axial fit, on the tensor-product
+# cubic B-spline of the reconstruction (coefficient (j1, j0) centred on
+# breakpoints (j1 - 1, j0 - 1), table [nb1 + 2][nb0 + 2]); a pair enters when
+# both spline arguments lie in their domains (relative slack 1e-9); the
+# arguments are (r, z) for "rz" and (x, y) for "xy"; a ridge of `ridge`
+# times the mean diagonal; groups, shifts and the event filter as above.
+
+def _args2d(kind, sx, sy, xe, ye, ze):
+    if kind == "rz":
+        return np.sqrt((xe - sx) ** 2 + (ye - sy) ** 2), ze
+    return xe, ye
+
+
+def _locate(u, nb, lo, hi):
+    d = (hi - lo) / (nb - 1)
+    tol = 1e-9 * (hi - lo)
+    inside = (u >= lo - tol) & (u <= hi + tol)
+    v = (u - lo) / d
+    m = np.clip(np.floor(v).astype(np.int64), 0, nb - 2)
+    return inside, m, v - m
+
+
+def normal_equations_2d(kind, sxy, gain, active, signals, x, y, z, E, use, nb, lo, hi,
+                        members=None, shift=None):
+    """Normal matrix [nc][nc], right side [nc] (nc = (nb0 + 2)(nb1 + 2),
+    coefficient (j1, j0) at index j1 (nb0 + 2) + j0) and pair count of the
+    least-squares fit of a 2-D LRF over the pairs of the sensors in
+    `members` (default: every active sensor)."""
+    nc0, nc1 = nb[0] + 2, nb[1] + 2
+    nc = nc0 * nc1
+    M = np.zeros((nc, nc))
+    v = np.zeros(nc)
+    sig = np.asarray(signals, np.float64)[use]
+    xe, ye = _positions(x, y, use, shift)
+    ze = np.asarray(z, np.float64)[use]
+    Ee = np.asarray(E, np.float64)[use]
+    npairs = 0
+    if members is None:
+        members = range(len(sxy))
+    for i in members:
+        if not active[i]:
+            continue
+        u, w = _args2d(kind, sxy[i][0], sxy[i][1], xe, ye, ze)
+        in0, m0, t0 = _locate(u, nb[0], lo[0], hi[0])
+        in1, m1, t1 = _locate(w, nb[1], lo[1], hi[1])
+        ok = in0 & in1
+        b0 = bspline_weights(t0[ok])
+        b1 = bspline_weights(t1[ok])
+        m0, m1 = m0[ok], m1[ok]
+        target = sig[ok, i] / (Ee[ok] * gain[i])
+        idx = [(m1 + q) * nc0 + (m0 + p) for q in range(4) for p in range(4)]
+        wts = [b1[:, q] * b0[:, p] for q in range(4) for p in range(4)]
+        for a in range(16):
+            np.add.at(v, idx[a], wts[a] * target)
+            for b in range(16):
+                np.add.at(M, (idx[a], idx[b]), wts[a] * wts[b])
+        npairs += int(ok.sum())
+    return M, v, npairs
+
+
+def fit_2d_grouped(kind, sxy, gain, active, signals, x, y, z, E, use, nb, lo, hi, groups,
+                   ridge=1e-9, shift=None):
+    """One 2-D table per sensor group: coefficients [G][nb1 + 2][nb0 + 2]
+    (NaN for groups without pairs) and pair counts [G]."""
+    groups = np.asarray(groups, np.int64)
+    G = int(groups.max()) + 1 if len(groups) and groups.max() >= 0 else 0
+    nc0, nc1 = nb[0] + 2, nb[1] + 2
+    coef = np.full((G, nc1, nc0), np.nan)
+    pairs = np.zeros(G, np.int64)
+    for g in range(G):
+        members = [i for i in range(len(sxy)) if groups[i] == g and active[i]]
+        M, v, npairs = normal_equations_2d(kind, sxy, gain, active, signals, x, y, z, E, use,
+                                           nb, lo, hi, members, shift)
+        pairs[g] = npairs
+        if npairs > 0:
+            coef[g] = _solve(M, v, ridge).reshape(nc1, nc0)
+    return coef, pairs
+
+
+def value_2d(coef, nb, lo, hi, u, w):
+    """The reconstruction's 2-D LRF max(spline, 0) at (u, w), 0 outside."""
+    coef = np.asarray(coef, np.float64)
+    in0, m0, t0 = _locate(np.asarray(u, np.float64), nb[0], lo[0], hi[0])
+    in1, m1, t1 = _locate(np.asarray(w, np.float64), nb[1], lo[1], hi[1])
+    b0, b1 = bspline_weights(t0), bspline_weights(t1)
+    val = sum(b1[..., q] * b0[..., p] * coef[m1 + q, m0 + p] for q in range(4) for p in range(4))
+    return np.where(in0 & in1, np.maximum(val, 0.0), 0.0)

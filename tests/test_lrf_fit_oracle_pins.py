@@ -247,3 +247,95 @@ def test_gains_within_groups_recover_true_gains():
                         np.ones(len(sig), bool), model.nb[0], model.lo[0], model.hi[0],
                         2.0 * tabs, ring)
     np.testing.assert_allclose(g2[act], 0.5 * gains[act], rtol=1e-13)
+
+
+# ---- two-dimensional LRFs (r-z and XY)
+
+def test_2d_value_equals_c_oracle_lrf():
+    for k, kind in ((2, "rz"), (1, "xy")):
+        wl = W.workload(k)
+        m = wl.lrf
+        rng = np.random.default_rng(20 + k)
+        pos = np.zeros((200, 3))
+        pos[:, :2] = rng.uniform(-100, 100, (200, 2)) if k == 2 else rng.uniform(-26, 26, (200, 2))
+        pos[:, 2] = rng.uniform(-5, 55, 200)
+        ref = oracle.lrf_values(m, pos)
+        coef = np.asarray(m.coef, np.float64)
+        for i in (0, 5, 17):
+            t = 0 if m.shared else i
+            u, w = (np.hypot(pos[:, 0] - m.sxy[i, 0], pos[:, 1] - m.sxy[i, 1]), pos[:, 2]) \
+                if kind == "rz" else (pos[:, 0], pos[:, 1])
+            got = F.value_2d(coef[t], m.nb, m.lo, m.hi, u, w)
+            np.testing.assert_allclose(got, ref[:, i], rtol=1e-12, atol=1e-15)
+
+
+def test_2d_design_matches_brute_force_lstsq():
+    rng = np.random.default_rng(5)
+    # events reach every part of the (r, z) domain: a well-posed system
+    nb, lo, hi = (5, 4), (0.0, 0.0), (25.0, 20.0)
+    sxy = rng.uniform(-10, 10, (5, 2))
+    gain = rng.uniform(0.8, 1.2, 5)
+    active = np.ones(5, np.uint8)
+    n_ev = 600
+    x, y = rng.uniform(-15, 15, n_ev), rng.uniform(-15, 15, n_ev)
+    z = rng.uniform(-1, 21, n_ev)
+    E = rng.uniform(100, 300, n_ev)
+    sig = rng.uniform(0, 50, (n_ev, 5))
+    nc = (nb[0] + 2) * (nb[1] + 2)
+    rows, rhs = [], []
+    for e in range(n_ev):
+        for i in range(5):
+            r = np.hypot(x[e] - sxy[i, 0], y[e] - sxy[i, 1])
+            if not (0.0 <= r <= 25.0 and 0.0 <= z[e] <= 20.0):
+                continue
+            rows.append([oracle.spline2(np.eye(nc)[j].reshape(nb[1] + 2, nb[0] + 2), nb, lo, hi,
+                                        r, z[e])[0] for j in range(nc)])
+            rhs.append(sig[e, i] / (E[e] * gain[i]))
+    A = np.array(rows)
+    use = np.ones(n_ev, bool)
+    M, v, npairs = F.normal_equations_2d("rz", sxy, gain, active, sig, x, y, z, E, use, nb, lo, hi)
+    np.testing.assert_allclose(M, A.T @ A, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(v, A.T @ np.array(rhs), rtol=1e-12, atol=1e-12)
+    assert npairs == len(rows)
+    ref = np.linalg.lstsq(A, np.array(rhs), rcond=None)[0]
+    got, _ = F.fit_2d_grouped("rz", sxy, gain, active, sig, x, y, z, E, use, nb, lo, hi,
+                              np.zeros(5, np.int64), ridge=0.0)
+    assert np.linalg.cond(A) < 1e6
+    np.testing.assert_allclose(got[0].reshape(-1), ref, rtol=1e-8, atol=1e-10)
+
+
+def test_rz_shared_fit_recovers_the_lrf_where_events_reach():
+    wl = W.workload(2)
+    sig, truth = oracle.generate(wl.lrf, 0, wl.events.extent, wl.events.z_lo, wl.events.z_hi,
+                                 wl.events.e_lo, wl.events.e_hi, 3000, 41, noiseless=True)
+    S = oracle.lrf_values(wl.lrf, truth[:, :3]) @ np.asarray(wl.lrf.gain, np.float64)
+    m = wl.lrf
+    use = np.ones(len(sig), bool)
+    coef, pairs = F.fit_2d_grouped("rz", m.sxy, m.gain, m.active, sig, truth[:, 0], truth[:, 1],
+                                   truth[:, 2], truth[:, 3] / S, use, m.nb, m.lo, m.hi,
+                                   np.zeros(m.n_sensors, np.int64), ridge=1e-12)
+    # the fitted LRF equals the true one wherever the events probe it
+    ref = oracle.lrf_values(m, truth[:, :3])
+    for i in (0, 9, 30):
+        r = np.hypot(truth[:, 0] - m.sxy[i, 0], truth[:, 1] - m.sxy[i, 1])
+        got = F.value_2d(coef[0], m.nb, m.lo, m.hi, r, truth[:, 2])
+        assert np.max(np.abs(got - ref[:, i])) < 1e-7 * np.max(ref[:, i]), i
+
+
+def test_xy_individual_fits_recover_each_sensors_lrf():
+    wl = W.workload(1)
+    m = wl.lrf
+    sig, truth = oracle.generate(m, 1, wl.events.extent, 0.0, 0.0, wl.events.e_lo,
+                                 wl.events.e_hi, 6000, 42, noiseless=True)
+    S = oracle.lrf_values(m, truth[:, :3]) @ np.asarray(m.gain, np.float64)
+    use = np.ones(len(sig), bool)
+    ind = np.arange(m.n_sensors)
+    ind[ind >= 8] = -1                                  # the first row of sensors only
+    coef, pairs = F.fit_2d_grouped("xy", m.sxy, m.gain, m.active, sig, truth[:, 0], truth[:, 1],
+                                   truth[:, 2], truth[:, 3] / S, use, m.nb, m.lo, m.hi, ind,
+                                   ridge=1e-12)
+    assert coef.shape[0] == 8 and (pairs > 0).all()
+    ref = oracle.lrf_values(m, truth[:, :3])
+    for i in range(8):
+        got = F.value_2d(coef[i], m.nb, m.lo, m.hi, truth[:, 0], truth[:, 1])
+        assert np.max(np.abs(got - ref[:, i])) < 1e-7 * np.max(ref[:, i]), i

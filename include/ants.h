@@ -561,8 +561,9 @@ ants_status ants_reconstruct_seeded_noalloc(ants_lrfset* set, ants_mlp* mlp,
 /* e, active sensor i) pair with lo <= r_ie <= hi (relative slack 1e-9  */
 /* of the span), all weighted 1; ridge * (mean diagonal) is added to    */
 /* the diagonal of the normal matrix.  An event enters when its status  */
-/* is 0, 0 < E < inf and, if chi2ndf_max > 0, ndf > 0 and               */
-/* chi2 / ndf <= chi2ndf_max.                                           */
+/* has none of the bits EMPTY, BAD_INPUT, NO_ACTIVE, NO_VALID_NODE (TIE */
+/* and FALLBACK only describe how a valid position was found), 0 < E <  */
+/* inf and, if chi2ndf_max > 0, ndf > 0 and chi2 / ndf <= chi2ndf_max. */
 /* ------------------------------------------------------------------ */
 typedef struct {
   int32_t nb;           /* breakpoints of the fitted spline, 4..62           */
@@ -606,6 +607,36 @@ ants_status ants_fit_axial_lrf_grouped(ants_lrfset* set, const ants_fit_cfg* cfg
                                        int64_t n_events, const float* d_signals, int64_t ld,
                                        ants_out rec, const float* d_shift, double* d_coef,
                                        int64_t* d_counts, void* hip_stream);
+
+/* Two-dimensional LRF fits (Sec. 6: LRFs from signals and positions; r-z
+ * LRFs in r and depth and per-sensor XY LRFs, Sec. 6.1.1; groups, Sec.
+ * 6.2): least squares on n / (E g) against the reconstruction's
+ * tensor-product cubic B-spline (table [nb[1] + 2][nb[0] + 2]), one table
+ * per group, from the pairs whose arguments (r, z) (kind r-z; z from
+ * rec.z) or (x, y) (kind XY) lie in the domains (relative slack 1e-9);
+ * ridge * mean diagonal on the diagonal; the event filter, groups
+ * (d_group by sensor index, -1 left out) and shifts as for
+ * ants_fit_axial_lrf_grouped.  Writes d_coef [n_groups][nb[1] + 2][nb[0] +
+ * 2] FP64 (NaN tables for groups without a positive definite system) and
+ * d_counts [n_groups][2] (events used, pairs) when not NULL.  The normal
+ * equations are summed with FP64 atomic adds in global memory: results
+ * agree with an FP64 reference to rounding but may differ in the last
+ * bits from call to call.  nb 4..64 per axis, 1..1024 groups; workspace
+ * 8 ((nb[0] + 2)(nb[1] + 2)(3 nb[0] + 10) + 2 (nb[0] + 2)(nb[1] + 2))
+ * bytes per group, kept in the set.  Asynchronous on hip_stream. */
+typedef struct {
+  int32_t kind;         /* ANTS_LRF_RZ or ANTS_LRF_XY                       */
+  int32_t nb[2];        /* breakpoints per axis (u = r or x, w = z or y)     */
+  double lo[2], hi[2];  /* domains in mm (r-z: lo[0] >= 0)                  */
+  double ridge;         /* relative ridge, >= 0                              */
+  double chi2ndf_max;   /* event filter; <= 0: no chi2 cut                   */
+} ants_fit2d_cfg;
+
+ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d_cfg* cfg,
+                                   int32_t n_groups, const int32_t* d_group, int64_t n_events,
+                                   const float* d_signals, int64_t ld, ants_out rec,
+                                   const float* d_shift, double* d_coef, int64_t* d_counts,
+                                   void* hip_stream);
 
 /* Relative gains re-calculated within fixed groups (Sec. 6.3), the LRF
  * profiles unchanged: for each active sensor i with d_table_of[i] in

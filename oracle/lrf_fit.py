@@ -22,8 +22,10 @@ Readings (the paper prints no fit formula):
     signals and gain scaled together leave the fit unchanged);
   * a ridge of `ridge` times the mean diagonal of the normal matrix keeps
     coefficients without data defined (they go to zero);
-  * events enter when their reconstruction status is 0, E > 0 and finite,
-    and chi2/ndf <= chi2ndf_max (when given);
+  * events enter when their reconstruction status has none of the failure
+    bits (empty, bad input, no active sensor, no valid node: 1|2|4|8; the
+    tie and fallback bits describe how a valid position was found), E > 0
+    and finite, and chi2/ndf <= chi2ndf_max (when given);
   * groups: one table per group, fitted to the pairs of its member sensors
     only; a group without pairs has no solution (NaN);
   * shift: the fit reads (x + dx, y + dy) for each event, the shift drawn
@@ -35,6 +37,10 @@ Readings (the paper prints no fit formula):
 from __future__ import annotations
 
 import numpy as np
+
+# reconstruction status bits that mark a failed event: empty, bad input,
+# no active sensor, no valid node
+FAILED = 1 | 2 | 4 | 8
 
 
 def bspline_weights(t):
@@ -53,7 +59,7 @@ def event_mask(E, status=None, chi2=None, ndf=None, chi2ndf_max=None):
     E = np.asarray(E, np.float64)
     use = np.isfinite(E) & (E > 0.0)
     if status is not None:
-        use &= np.asarray(status) == 0
+        use &= (np.asarray(status) & FAILED) == 0
     if chi2ndf_max is not None and chi2ndf_max > 0:
         c = np.asarray(chi2, np.float64)
         d = np.asarray(ndf, np.float64)

@@ -92,6 +92,11 @@ class GridPlan(C.Structure):
                 ("screen", C.c_int32)]
 
 
+class Fit2dCfg(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nb", C.c_int32 * 2), ("lo", C.c_double * 2),
+                ("hi", C.c_double * 2), ("ridge", C.c_double), ("chi2ndf_max", C.c_double)]
+
+
 class MigradCfg(C.Structure):
     _fields_ = [("dims", C.c_int32), ("stat", C.c_int32), ("start", C.c_int32),
                 ("step0", C.c_double * 3), ("z_start", C.c_double), ("h", C.c_double),
@@ -169,6 +174,8 @@ _lib.ants_fit_axial_lrf.argtypes = [_vp, C.POINTER(FitCfg), C.c_int64, _vp, C.c_
                                     _vp, _vp]
 _lib.ants_fit_axial_lrf_grouped.argtypes = [_vp, C.POINTER(FitCfg), C.c_int32, _vp, C.c_int64,
                                             _vp, C.c_int64, Out, _vp, _vp, _vp, _vp]
+_lib.ants_fit_lrf2d_grouped.argtypes = [_vp, C.POINTER(Fit2dCfg), C.c_int32, _vp, C.c_int64, _vp,
+                                        C.c_int64, Out, _vp, _vp, _vp, _vp]
 _lib.ants_fit_axial_gains.argtypes = [_vp, C.POINTER(FitCfg), C.c_int32, _vp, _vp, C.c_int64,
                                       _vp, C.c_int64, Out, _vp, _vp, _vp, _vp]
 
@@ -182,7 +189,8 @@ EXPORTED = ("ants_last_error", "ants_version", "ants_lrfset_create", "ants_lrfse
             "ants_lrf_write", "ants_lrfset_save", "ants_lrfset_load",
             "ants_reconstruct_simplex", "ants_knn_create", "ants_knn_destroy",
             "ants_knn_reconstruct", "ants_autotune", "ants_set_plan",
-            "ants_fit_axial_lrf_grouped", "ants_fit_axial_gains", "ants_reconstruct_migrad")
+            "ants_fit_axial_lrf_grouped", "ants_fit_axial_gains", "ants_reconstruct_migrad",
+            "ants_fit_lrf2d_grouped")
 
 
 def _check(code):
@@ -746,6 +754,40 @@ def fit_axial_lrf_grouped(lrfset: LrfSet, cfg: FitCfg, groups, signals, rec, shi
     return coef, counts
 
 
+def fit2d_cfg(kind, nb, lo, hi, ridge=1e-9, chi2ndf_max=0.0) -> Fit2dCfg:
+    """Fit2dCfg for an r-z (kind 3) or XY (kind 2) LRF fit."""
+    c = Fit2dCfg()
+    c.kind = int(kind)
+    for a in range(2):
+        c.nb[a], c.lo[a], c.hi[a] = int(nb[a]), float(lo[a]), float(hi[a])
+    c.ridge, c.chi2ndf_max = float(ridge), float(chi2ndf_max)
+    return c
+
+
+def fit_lrf2d_grouped(lrfset: LrfSet, cfg: Fit2dCfg, groups, signals, rec, shift=None,
+                      stream=None):
+    """One 2-D (r-z or XY) table per sensor group.  Returns (coefficients
+    [G][nb1+2][nb0+2] float64, counts [G][2] int64), device tensors
+    (asynchronous)."""
+    import torch
+    assert signals.dtype == torch.float32 and signals.is_cuda and signals.dim() == 2
+    assert signals.stride(1) == 1 and signals.shape[1] == lrfset.n_sensors
+    n = signals.shape[0]
+    g = _dev_i32(groups, signals.device)
+    assert g.numel() == lrfset.n_sensors
+    G = int(g.max().item()) + 1
+    assert G >= 1
+    sh = _shift_arg(shift, n)
+    coef = torch.empty((G, cfg.nb[1] + 2, cfg.nb[0] + 2), dtype=torch.float64,
+                       device=signals.device)
+    counts = torch.empty((G, 2), dtype=torch.int64, device=signals.device)
+    _check(_lib.ants_fit_lrf2d_grouped(
+        lrfset.handle, C.byref(cfg), G, g.data_ptr(), n, signals.data_ptr(), signals.stride(0),
+        _out_struct(rec), sh.data_ptr() if sh is not None else None, coef.data_ptr(),
+        counts.data_ptr(), _stream_handle(stream)))
+    return coef, counts
+
+
 def fit_axial_gains(lrfset: LrfSet, cfg: FitCfg, tables, table_of, signals, rec, shift=None,
                     stream=None):
     """Relative gains re-calculated within fixed groups (Sec. 6.3): `tables`
@@ -856,6 +898,87 @@ class AxialModel:
     def with_active(self, active):
         return AxialModel(self.sxy, self.gain, active, self.nb[0], self.lo[0], self.hi[0],
                           self.tables, self.table_of)
+
+
+class Lrf2dModel:
+    """Detector model with 2-D LRFs (kind 3 r-z or 2 XY): `tables`
+    [T][nb1+2][nb0+2] and the table of each sensor (`table_of`, default one
+    shared table); the fields LrfSet reads."""
+
+    def __init__(self, kind, sxy, gain, active, nb, lo, hi, tables, table_of=None):
+        self.kind = int(kind)
+        self.sxy = np.ascontiguousarray(sxy, np.float64)
+        self.gain = np.ascontiguousarray(gain, np.float64)
+        self.active = np.ascontiguousarray(active, np.uint8)
+        self.nb = (int(nb[0]), int(nb[1]))
+        self.lo, self.hi = (float(lo[0]), float(lo[1])), (float(hi[0]), float(hi[1]))
+        self.tables = np.ascontiguousarray(tables, np.float64).reshape(
+            -1, self.nb[1] + 2, self.nb[0] + 2)
+        n = len(self.sxy)
+        self.table_of = (np.zeros(n, np.int32) if table_of is None
+                         else np.ascontiguousarray(table_of, np.int32))
+        if len(self.tables) == 1 and (self.table_of == 0).all():
+            self.shared = 1
+            self.coef = self.tables
+        else:
+            self.shared = 0
+            self.coef = self.tables[np.maximum(self.table_of, 0)]
+
+    def with_active(self, active):
+        return Lrf2dModel(self.kind, self.sxy, self.gain, active, self.nb, self.lo, self.hi,
+                          self.tables, self.table_of)
+
+
+def iterate_lrf2d(model, grid: GridCfg, signals, iterations, ridge=1e-9, chi2ndf_max=0.0,
+                  stream=None, groups=None, shift_sigma=0.0, shift_iterations=0, shift_seed=0,
+                  disable=None):
+    """Iterative LRF reconstruction (Sec. 8) for r-z or XY models: as
+    iterate_axial_lrf, with the 2-D fits (groups: None for one shared table,
+    an array, or a function of the fit index).  Returns the models and the
+    last reconstruction."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    models = [model]
+    n = signals.shape[0]
+    for k in range(iterations + 1):
+        cur = models[-1]
+        act = np.asarray(cur.active, np.uint8).copy()
+        if disable and k in disable:
+            act[np.asarray(disable[k], np.int64)] = 0
+        ls = LrfSet(cur.with_active(act))
+        rec = reconstruct(ls, grid, signals, stream=st)
+        if k == iterations:
+            st.synchronize()
+            ls.close()
+            break
+        fs = LrfSet(cur) if disable and k in disable else ls
+        g = groups(k) if callable(groups) else groups
+        ns = len(cur.sxy)
+        g = groups_all(ns) if g is None else np.asarray(g, np.int32)
+        shift = None
+        if shift_sigma > 0.0 and k < shift_iterations:
+            gen = torch.Generator(device=signals.device).manual_seed(int(shift_seed) + k)
+            shift = torch.randn((n, 2), generator=gen, device=signals.device,
+                                dtype=torch.float32) * float(shift_sigma)
+        cfg = fit2d_cfg(cur.kind, cur.nb, cur.lo, cur.hi, ridge, chi2ndf_max)
+        coef, _ = fit_lrf2d_grouped(fs, cfg, g, signals, rec, shift, st)
+        st.synchronize()
+        coef = coef.cpu().numpy()
+        new = cur.tables[np.maximum(cur.table_of, 0)].copy()
+        for i in range(ns):
+            if 0 <= g[i] < len(coef) and np.isfinite(coef[g[i]]).all():
+                new[i] = coef[g[i]]
+        if fs is not ls:
+            fs.close()
+        ls.close()
+        if (g == 0).all() and np.isfinite(coef[0]).all():
+            nxt = Lrf2dModel(cur.kind, cur.sxy, cur.gain, cur.active, cur.nb, cur.lo, cur.hi,
+                             coef[0])
+        else:
+            nxt = Lrf2dModel(cur.kind, cur.sxy, cur.gain, cur.active, cur.nb, cur.lo, cur.hi,
+                             new, np.arange(ns))
+        models.append(nxt)
+    return models, rec
 
 
 def iterate_axial_lrf(model, grid: GridCfg, signals, iterations, ridge=1e-9, chi2ndf_max=0.0,

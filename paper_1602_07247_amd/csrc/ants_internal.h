@@ -11,6 +11,10 @@
 
 namespace ants {
 
+// status bits of a failed event (EMPTY | BAD_INPUT | NO_ACTIVE | NO_VALID_NODE);
+// TIE and FALLBACK describe how a valid position was found
+constexpr int kEvFailed = ANTS_EV_EMPTY | ANTS_EV_BAD_INPUT | ANTS_EV_NO_ACTIVE |
+                          ANTS_EV_NO_VALID_NODE;
 constexpr int kMaxSensors = 256;     // row length limit (4 sensor slots per lane)
 constexpr int kSlots = kMaxSensors / 64;
 constexpr int kMaxNodes = 512;       // 8 tiles of 64 nodes
@@ -340,4 +344,6 @@ struct ants_lrfset {
   // workspace of the LRF fit (per-wave partial normal equations)
   void* ws_fit = nullptr;
   size_t ws_fit_bytes = 0;
+  void* ws_fit2 = nullptr;       // two-dimensional LRF fits
+  size_t ws_fit2_bytes = 0;
 };

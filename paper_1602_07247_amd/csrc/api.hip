@@ -315,6 +315,7 @@ ants_status ants_lrfset_destroy(ants_lrfset* set) {
   }
   if (set->ms_host) (void)hipHostFree(set->ms_host);
   if (set->ws_fit) (void)hipFree(set->ws_fit);
+  if (set->ws_fit2) (void)hipFree(set->ws_fit2);
   delete set;
   return ANTS_OK;
 }

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(64 * kFitWaves) fit_accum_kernel(FitP P) {
     const int64_t e = gw + (k0 + slot) * nw;
     if (!live || e >= P.n) continue;
     const float Ef = P.E[e];
-    bool ok = P.status[e] == 0 && Ef > 0.f && Ef < __builtin_huge_valf();
+    bool ok = (P.status[e] & kEvFailed) == 0 && Ef > 0.f && Ef < __builtin_huge_valf();
     if (P.chi2ndf_max > 0.0) {
       const int d = P.ndf[e];
       ok = ok && d > 0 && (double)P.chi2[e] / (double)d <= P.chi2ndf_max;

@@ -94,6 +94,11 @@ def test_event_filter():
     got = F.event_mask(E, st, chi2, ndf, chi2ndf_max=2.0)
     assert got.tolist() == [True, False, False, False, False, False]
     assert F.event_mask(E, st).tolist() == [True, False, False, True, False, True]
+    # each status bit alone: the four failure bits drop the event, the tie
+    # (32) and fallback (16) bits describe a valid position and keep it
+    st = np.array([0, 1, 2, 4, 8, 16, 32, 48, 40])
+    got = F.event_mask(np.full(9, 100.0), st)
+    assert got.tolist() == [True, False, False, False, False, True, True, True, False]
 
 
 def test_iterations_converge_from_a_wrong_lrf():

@@ -86,11 +86,13 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="rz",
-                    choices=["rz", "axial", "mixed", "lrf_fit", "simplex", "migrad", "knn",
-                             "xy", "train"],
+                    choices=["rz", "axial", "mixed", "lrf_fit", "lrf_fit2d", "simplex", "migrad",
+                             "knn", "xy", "train"],
                     help="rz: the headline comparison; mixed: 19/61/127-sensor stream in one "
                          "persistent launch; lrf_fit: one step of the iterative LRF "
                          "reconstruction (reconstruct + refit) on the 61-sensor detector; "
+                         "lrf_fit2d: the same with the shared r-z table of the 37-sensor "
+                         "detector; "
                          "simplex: the simplex search against the plain grid on the r-z "
                          "events; knn: k-NN reconstruction of r-z events against a "
                          "calibration set; xy: the 8x8 array with per-sensor bicubic "
@@ -191,6 +193,11 @@ def mixed_stream(args):
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 FLOP_PER_FIT_PAIR = 60   # FP64: distance 6, interval 4, B-spline weights 20, target 2, sums 28
+# FP64 per (event, sensor) pair of a 2-D fit: distance 6, two intervals 8,
+# two sets of B-spline weights 24, target 2, 16 tensor weights, 16 right-side
+# products and sums 32, 136 band products and sums 272
+FLOP_PER_FIT2D_PAIR = 360
+ATOMICS_PER_FIT2D_PAIR = 152
 
 
 def lrf_fit_step(args):
@@ -270,6 +277,85 @@ def lrf_fit_step(args):
         rec_["cpu_baseline"] = {"value": m / dt, "unit": "events/s", "cores": 1,
                                 "kind": "oracle", "sample": "LRF fit of the first %d events "
                                 "(NumPy FP64, one thread)" % m}
+    print(json.dumps(rec_), flush=True)
+
+
+def lrf_fit2d_step(args):
+    """Iterative LRF reconstruction (Sec. 8) with the shared r-z table of the
+    37-sensor detector (Sec. 6.1.2): each step reconstructs every event on the
+    7x7x7 grid and refits the table (24 x 16 breakpoints) to the signals,
+    positions and energies.  Starts from the fit at the true positions of the
+    first 200 k events (the simulation-data start)."""
+    import torch
+    import workloads as W
+    from paper_1602_07247_amd import ants
+    n = args.events if args.events != 10_000_000 else 2_000_000
+    wl = W.workload(2)
+    true_lrf = wl.lrf
+    Lt = ants.LrfSet(true_lrf)
+    sig, truth = ants.generate(Lt, ants.gen_cfg(wl.events), n, args.seed)
+    grid = ants.grid_cfg(wl.grid)
+    cfg = ants.fit2d_cfg(true_lrf.kind, true_lrf.nb, true_lrf.lo, true_lrf.hi, 1e-9)
+    groups = np.zeros(true_lrf.sxy.shape[0], np.int32)
+    stream = torch.cuda.current_stream()
+    # simulation-data start: the true LRF's reconstruction of the first 200 k
+    # events stands in for the known positions
+    m0 = min(n, 200_000)
+    o0 = ants.reconstruct(Lt, grid, sig[:m0], stream=stream)
+    c0, _ = ants.fit_lrf2d_grouped(Lt, cfg, groups, sig[:m0], o0, None, stream)
+    torch.cuda.synchronize()
+    model = ants.Lrf2dModel(true_lrf.kind, true_lrf.sxy, true_lrf.gain, true_lrf.active,
+                            true_lrf.nb, true_lrf.lo, true_lrf.hi, c0.cpu().numpy()[0])
+    L = ants.LrfSet(model)
+    out = ants.alloc_out(n)
+    holder = {}
+
+    def step():
+        ants.reconstruct(L, grid, sig, out=out, stream=stream)
+        holder["coef"], holder["counts"] = ants.fit_lrf2d_grouped(L, cfg, groups, sig, out,
+                                                                  None, stream)
+
+    wall, ev = timed(step, args.steps, args.warmup, stream)
+    wall_f, ev_f = timed(lambda: ants.fit_lrf2d_grouped(L, cfg, groups, sig, out, None, stream),
+                         args.steps, args.warmup, stream)
+    torch.cuda.synchronize()
+    used, pairs = holder["counts"].cpu().numpy()[0].tolist()
+    flops = pairs * FLOP_PER_FIT2D_PAIR
+    bytes_ = n * (true_lrf.sxy.shape[0] * 4 + 24)
+    achieved = flops / (ev_f * 1e-3) / 1e12
+    rec_ = {"metric": "events/s through one iterative-LRF step (reconstruct + r-z refit), "
+                      "37-sensor hex detector",
+            "value": n / wall, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * wall, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic (flood-field events drawn on the GPU from the LRF model)",
+            "config": {"workload": "hex37 r-z LRF (24 x 16 breakpoints), %d events, 7x7x7 grid "
+                                   "x 8 iterations, refit of the shared table" % n,
+                       "events": n},
+            "fit": {"events_per_s": n / (ev_f * 1e-3), "ms": ev_f, "events_used": used,
+                    "pairs": pairs, "fp64_atomics_per_s": pairs * ATOMICS_PER_FIT2D_PAIR /
+                    (ev_f * 1e-3), "hbm_gb_s": bytes_ / (ev_f * 1e-3) / 1e9,
+                    "hbm_frac": bytes_ / (ev_f * 1e-3) / 1e9 / PEAK_HBM_GBS},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                         "kernel": "fit2_zero, fit2_rows, fit2_chunks, fit2_assemble, fit2_solve kernels "
+                                   "(FP64)", "kernel_ms": ev_f, "flop_per_launch": flops,
+                         "flop_per_pair": FLOP_PER_FIT2D_PAIR}}
+    if args.cpu_sample > 0:
+        from oracle import lrf_fit as F
+        m = min(2 * args.cpu_sample, n)
+        xs = {k: out[k][:m].cpu().numpy().astype(np.float64) for k in ("x", "y", "z", "E")}
+        use = F.event_mask(xs["E"], out["status"][:m].cpu().numpy())
+        s_h = sig[:m].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        F.fit_2d_grouped("rz", model.sxy, model.gain, model.active, s_h, xs["x"], xs["y"],
+                         xs["z"], xs["E"], use, model.nb, model.lo, model.hi, groups)
+        dt = time.perf_counter() - t0
+        rec_["cpu_baseline"] = {"value": m / dt, "unit": "events/s", "cores": 1,
+                                "kind": "oracle", "sample": "r-z LRF fit of the first %d "
+                                "events (NumPy FP64, one thread)" % m}
+    L.close()
+    Lt.close()
     print(json.dumps(rec_), flush=True)
 
 
@@ -886,6 +972,9 @@ def main():
         return
     if args.workload == "lrf_fit":
         lrf_fit_step(args)
+        return
+    if args.workload == "lrf_fit2d":
+        lrf_fit2d_step(args)
         return
     if args.workload == "simplex":
         simplex_vs_grid(args)

@@ -282,11 +282,20 @@ def _dev2d(r):
     return d
 
 
-@pytest.mark.parametrize("k,kind,grouping,shift", [(2, "rz", "shared", False),
-                                                   (2, "rz", "ring", True),
-                                                   (1, "xy", "first_row", False)])
-def test_2d_fit_matches_oracle(ants, k, kind, grouping, shift):
-    lrf, sig, r = _inputs2d(k, 20_000 if kind == "rz" else 30_000, 90 + k)
+# one group: per-row LDS sums (repeatable bits; four waves per block, or
+# two for the 48-breakpoint r axis); many groups: global atomics.  The band
+# solve runs in an LDS window up to about 43 breakpoints on the first axis, from
+# global memory beyond (48)
+@pytest.mark.parametrize("k,kind,grouping,shift,nb", [(2, "rz", "shared", False, None),
+                                                      (2, "rz", "shared", True, None),
+                                                      (2, "rz", "shared", False, (48, 8)),
+                                                      (2, "rz", "ring", True, None),
+                                                      (1, "xy", "first_row", False, None),
+                                                      (1, "xy", "shared", True, None)])
+def test_2d_fit_matches_oracle(ants, k, kind, grouping, shift, nb):
+    n = 20_000 if kind == "rz" else (8_000 if grouping == "shared" else 30_000)
+    lrf, sig, r = _inputs2d(k, n, 90 + k)
+    nb = lrf.nb if nb is None else nb
     ns = lrf.sxy.shape[0]
     print(f"[gpu] 2-D LRF fit {kind} {grouping} shift {shift}", flush=True)
     if grouping == "shared":
@@ -299,14 +308,18 @@ def test_2d_fit_matches_oracle(ants, k, kind, grouping, shift):
     n = len(sig)
     sh = np.random.default_rng(k).normal(0.0, 1.0, (n, 2)).astype(np.float32) if shift else None
     L = ants.LrfSet(lrf)
-    cfg = ants.fit2d_cfg(3 if kind == "rz" else 2, lrf.nb, lrf.lo, lrf.hi, 1e-9)
-    coef, counts = ants.fit_lrf2d_grouped(L, cfg, groups, torch.from_numpy(sig).cuda(),
-                                          _dev2d(r), torch.from_numpy(sh).cuda() if shift else None)
+    cfg = ants.fit2d_cfg(3 if kind == "rz" else 2, nb, lrf.lo, lrf.hi, 1e-9)
+    dsig, drec = torch.from_numpy(sig).cuda(), _dev2d(r)
+    dsh = torch.from_numpy(sh).cuda() if shift else None
+    coef, counts = ants.fit_lrf2d_grouped(L, cfg, groups, dsig, drec, dsh)
+    again, _ = ants.fit_lrf2d_grouped(L, cfg, groups, dsig, drec, dsh)
     torch.cuda.synchronize()
+    if grouping == "shared":
+        np.testing.assert_array_equal(again.cpu().numpy(), coef.cpu().numpy())
     use = F.event_mask(r["E"], r["status"])
     x64 = {kk: r[kk].astype(np.float64) for kk in ("x", "y", "z", "E")}
     ref, pairs = F.fit_2d_grouped(kind, lrf.sxy, lrf.gain, lrf.active, sig.astype(np.float64),
-                                  x64["x"], x64["y"], x64["z"], x64["E"], use, lrf.nb, lrf.lo,
+                                  x64["x"], x64["y"], x64["z"], x64["E"], use, nb, lrf.lo,
                                   lrf.hi, groups, ridge=1e-9,
                                   shift=sh.astype(np.float64) if shift else None)
     got = coef.cpu().numpy()
@@ -314,8 +327,8 @@ def test_2d_fit_matches_oracle(ants, k, kind, grouping, shift):
     assert got.shape == ref.shape
     np.testing.assert_array_equal(c[:, 1], pairs)
     assert (c[:, 0] == int(use.sum())).all()
-    # FP64 sums in another order (atomic adds): the fitted LRFs agree far
-    # below the fit's noise, at the points the data probe and on the tables
+    # FP64 sums in another order: the fitted LRFs agree far below the
+    # fit's noise, at the points the data probe and on the tables
     for g in range(len(ref)):
         scale = np.max(np.abs(ref[g]))
         assert np.max(np.abs(got[g] - ref[g])) <= 1e-7 * scale, (g, np.max(np.abs(got[g] - ref[g])) / scale)

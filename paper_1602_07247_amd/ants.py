@@ -929,14 +929,23 @@ class Lrf2dModel:
                           self.tables, self.table_of)
 
 
+def _check_rz_groups(kind, g):
+    if kind == LRF_RZ and g is not None and not (np.asarray(g) == 0).all():
+        raise ValueError("r-z LRF sets share one table: fit them with one group")
+
+
 def iterate_lrf2d(model, grid: GridCfg, signals, iterations, ridge=1e-9, chi2ndf_max=0.0,
                   stream=None, groups=None, shift_sigma=0.0, shift_iterations=0, shift_seed=0,
                   disable=None):
     """Iterative LRF reconstruction (Sec. 8) for r-z or XY models: as
     iterate_axial_lrf, with the 2-D fits (groups: None for one shared table,
-    an array, or a function of the fit index).  Returns the models and the
-    last reconstruction."""
+    an array, or a function of the fit index).  r-z sets hold one table
+    shared by every sensor, so r-z models take only the shared fit.  A group
+    whose fit fails (no pairs) keeps its previous tables.  Returns the models
+    and the last reconstruction."""
     import torch
+    if not callable(groups):
+        _check_rz_groups(model.kind, groups)
     st = stream if stream is not None else torch.cuda.current_stream()
     models = [model]
     n = signals.shape[0]
@@ -955,6 +964,7 @@ def iterate_lrf2d(model, grid: GridCfg, signals, iterations, ridge=1e-9, chi2ndf
         g = groups(k) if callable(groups) else groups
         ns = len(cur.sxy)
         g = groups_all(ns) if g is None else np.asarray(g, np.int32)
+        _check_rz_groups(cur.kind, g)
         shift = None
         if shift_sigma > 0.0 and k < shift_iterations:
             gen = torch.Generator(device=signals.device).manual_seed(int(shift_seed) + k)
@@ -971,9 +981,9 @@ def iterate_lrf2d(model, grid: GridCfg, signals, iterations, ridge=1e-9, chi2ndf
         if fs is not ls:
             fs.close()
         ls.close()
-        if (g == 0).all() and np.isfinite(coef[0]).all():
-            nxt = Lrf2dModel(cur.kind, cur.sxy, cur.gain, cur.active, cur.nb, cur.lo, cur.hi,
-                             coef[0])
+        if (g == 0).all():
+            nxt = (Lrf2dModel(cur.kind, cur.sxy, cur.gain, cur.active, cur.nb, cur.lo, cur.hi,
+                              coef[0]) if np.isfinite(coef[0]).all() else cur)
         else:
             nxt = Lrf2dModel(cur.kind, cur.sxy, cur.gain, cur.active, cur.nb, cur.lo, cur.hi,
                              new, np.arange(ns))

@@ -213,3 +213,16 @@ def test_grouping_helpers():
     sq = W.square_array(8, 6.0)
     s4 = A.groups_by_symmetry(sq, 4)
     assert s4.max() + 1 == 10 and sorted(np.bincount(s4).tolist()) == [4] * 4 + [8] * 6
+
+
+def test_rz_loop_takes_one_group():
+    # r-z sets share one table, so the r-z reconstruct-refit loop refuses a
+    # grouping before any GPU work
+    import workloads as W
+    from paper_1602_07247_amd import ants as A
+    lrf = W.workload(2).lrf
+    m = A.Lrf2dModel(lrf.kind, lrf.sxy, lrf.gain, lrf.active, lrf.nb, lrf.lo, lrf.hi,
+                     np.asarray(lrf.coef)[0])
+    with pytest.raises(ValueError):
+        A.iterate_lrf2d(m, None, None, 1, groups=np.arange(len(lrf.sxy), dtype=np.int32))
+    assert m.shared == 1 and m.coef.shape == (1, lrf.nb[1] + 2, lrf.nb[0] + 2)

@@ -32,7 +32,12 @@ Readings (the paper prints no fit formula):
     by the caller;
   * gains within groups: the least-squares scale of n_ie / E_e against the
     group's fixed L(r_ie) over the sensor's pairs in the domain,
-    g_i = sum (n/E) L / sum L^2.
+    g_i = sum (n/E) L / sum L^2;
+  * composite LRFs (Sec. 6.1.1: an axial LRF shared by every sensor plus an
+    XY residual per sensor or shared; the LRF is max(axial + residual, 0),
+    each part 0 outside its own domain) are fitted in two stages: the
+    shared axial fit above, then the XY residual fitted to the estimates
+    n_ie / (E_e g_i) minus the fitted axial spline at r_ie (not clamped).
 """
 from __future__ import annotations
 
@@ -202,6 +207,21 @@ def fit_gains(sxy, active, signals, x, y, E, use, nb, lo, hi, tables, table_of, 
 # arguments are (r, z) for "rz" and (x, y) for "xy"; a ridge of `ridge`
 # times the mean diagonal; groups, shifts and the event filter as above.
 
+def axial_spline(coef, nb, lo, hi, r):
+    """The axial spline at distances r inside [lo, hi] (relative slack
+    1e-9), not clamped, 0 outside: the axial part of a composite LRF."""
+    r = np.asarray(r, np.float64)
+    d = (hi - lo) / (nb - 1)
+    tol = 1e-9 * (hi - lo)
+    inside = (r >= lo - tol) & (r <= hi + tol)
+    u = (np.clip(r, lo, hi) - lo) / d
+    m = np.clip(np.floor(u).astype(np.int64), 0, nb - 2)
+    b = bspline_weights(u - m)
+    c = np.asarray(coef, np.float64)
+    val = sum(b[..., k] * c[m + k] for k in range(4))
+    return np.where(inside, val, 0.0)
+
+
 def _args2d(kind, sx, sy, xe, ye, ze):
     if kind == "rz":
         return np.sqrt((xe - sx) ** 2 + (ye - sy) ** 2), ze
@@ -218,11 +238,13 @@ def _locate(u, nb, lo, hi):
 
 
 def normal_equations_2d(kind, sxy, gain, active, signals, x, y, z, E, use, nb, lo, hi,
-                        members=None, shift=None):
+                        members=None, shift=None, base=None):
     """Normal matrix [nc][nc], right side [nc] (nc = (nb0 + 2)(nb1 + 2),
     coefficient (j1, j0) at index j1 (nb0 + 2) + j0) and pair count of the
     least-squares fit of a 2-D LRF over the pairs of the sensors in
-    `members` (default: every active sensor)."""
+    `members` (default: every active sensor).  base = (coef, nb, lo, hi) of
+    an axial spline subtracted from every estimate at the pair's distance
+    (the residual of a composite LRF), or None."""
     nc0, nc1 = nb[0] + 2, nb[1] + 2
     nc = nc0 * nc1
     M = np.zeros((nc, nc))
@@ -245,6 +267,9 @@ def normal_equations_2d(kind, sxy, gain, active, signals, x, y, z, E, use, nb, l
         b1 = bspline_weights(t1[ok])
         m0, m1 = m0[ok], m1[ok]
         target = sig[ok, i] / (Ee[ok] * gain[i])
+        if base is not None:
+            r = np.sqrt((xe[ok] - sxy[i][0]) ** 2 + (ye[ok] - sxy[i][1]) ** 2)
+            target = target - axial_spline(base[0], base[1], base[2], base[3], r)
         idx = [(m1 + q) * nc0 + (m0 + p) for q in range(4) for p in range(4)]
         wts = [b1[:, q] * b0[:, p] for q in range(4) for p in range(4)]
         for a in range(16):
@@ -256,7 +281,7 @@ def normal_equations_2d(kind, sxy, gain, active, signals, x, y, z, E, use, nb, l
 
 
 def fit_2d_grouped(kind, sxy, gain, active, signals, x, y, z, E, use, nb, lo, hi, groups,
-                   ridge=1e-9, shift=None):
+                   ridge=1e-9, shift=None, base=None):
     """One 2-D table per sensor group: coefficients [G][nb1 + 2][nb0 + 2]
     (NaN for groups without pairs) and pair counts [G]."""
     groups = np.asarray(groups, np.int64)
@@ -267,7 +292,7 @@ def fit_2d_grouped(kind, sxy, gain, active, signals, x, y, z, E, use, nb, lo, hi
     for g in range(G):
         members = [i for i in range(len(sxy)) if groups[i] == g and active[i]]
         M, v, npairs = normal_equations_2d(kind, sxy, gain, active, signals, x, y, z, E, use,
-                                           nb, lo, hi, members, shift)
+                                           nb, lo, hi, members, shift, base)
         pairs[g] = npairs
         if npairs > 0:
             coef[g] = _solve(M, v, ridge).reshape(nc1, nc0)
@@ -282,3 +307,37 @@ def value_2d(coef, nb, lo, hi, u, w):
     b0, b1 = bspline_weights(t0), bspline_weights(t1)
     val = sum(b1[..., q] * b0[..., p] * coef[m1 + q, m0 + p] for q in range(4) for p in range(4))
     return np.where(in0 & in1, np.maximum(val, 0.0), 0.0)
+
+
+def spline_2d(coef, nb, lo, hi, u, w):
+    """A 2-D spline at (u, w) inside its domain, not clamped, 0 outside: the
+    XY residual of a composite LRF."""
+    coef = np.asarray(coef, np.float64)
+    in0, m0, t0 = _locate(np.asarray(u, np.float64), nb[0], lo[0], hi[0])
+    in1, m1, t1 = _locate(np.asarray(w, np.float64), nb[1], lo[1], hi[1])
+    b0, b1 = bspline_weights(t0), bspline_weights(t1)
+    val = sum(b1[..., q] * b0[..., p] * coef[m1 + q, m0 + p] for q in range(4) for p in range(4))
+    return np.where(in0 & in1, val, 0.0)
+
+
+def composite_value(axial_coef, nb, lo, hi, xy_coef, xy_nb, xy_lo, xy_hi, r, x, y):
+    """A composite LRF max(axial(r) + residual(x, y), 0), each part 0
+    outside its own domain."""
+    return np.maximum(axial_spline(axial_coef, nb, lo, hi, r)
+                      + spline_2d(xy_coef, xy_nb, xy_lo, xy_hi, x, y), 0.0)
+
+
+def fit_composite(sxy, gain, active, signals, x, y, E, use, nb, lo, hi, xy_nb, xy_lo, xy_hi,
+                  xy_groups, ridge=1e-9, shift=None):
+    """Two-stage composite fit: the shared axial table [nb + 2], then one XY
+    residual table per group of xy_groups [G][xy_nb1 + 2][xy_nb0 + 2]
+    fitted to the estimates minus that axial spline; (axial, residuals,
+    residual pair counts)."""
+    members = [i for i in range(len(sxy)) if active[i]]
+    M, v, _ = normal_equations(sxy, gain, active, signals, x, y, E, use, nb, lo, hi, members,
+                               shift)
+    axial = _solve(M, v, ridge)
+    z = np.zeros(len(np.asarray(x)))
+    res, pairs = fit_2d_grouped("xy", sxy, gain, active, signals, x, y, z, E, use, xy_nb, xy_lo,
+                                xy_hi, xy_groups, ridge, shift, (axial, nb, lo, hi))
+    return axial, res, pairs

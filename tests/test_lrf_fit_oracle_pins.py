@@ -344,3 +344,75 @@ def test_xy_individual_fits_recover_each_sensors_lrf():
     for i in range(8):
         got = F.value_2d(coef[i], m.nb, m.lo, m.hi, truth[:, 0], truth[:, 1])
         assert np.max(np.abs(got - ref[:, i])) < 1e-7 * np.max(ref[:, i]), i
+
+
+# ---- composite LRFs (Sec. 6.1.1): axial part + XY residual
+
+def _composite_shared_residual(xy_nb=12):
+    sxy = W.hex_array(2, 30.0)
+    comp = W.composite_lrf(sxy, xy_nb=xy_nb)
+    return W.LRFSet(comp.kind, comp.sxy, comp.gain, comp.active, 1, comp.nb, comp.lo, comp.hi,
+                    comp.coef, xy_nb=comp.xy_nb, xy_lo=comp.xy_lo, xy_hi=comp.xy_hi,
+                    xy_coef=np.asarray(comp.xy_coef)[9:10], xy_shared=1)
+
+
+def test_composite_value_equals_c_oracle_lrf():
+    lrf = W.composite_lrf(W.hex_array(2, 30.0))
+    rng = np.random.default_rng(4)
+    pos = np.zeros((500, 3))
+    pos[:, :2] = rng.uniform(-110.0, 110.0, (500, 2))
+    ref = oracle.lrf_values(lrf, pos)
+    ax = np.asarray(lrf.coef).reshape(-1)
+    for i, (X, Y) in enumerate(lrf.sxy):
+        r = np.hypot(pos[:, 0] - X, pos[:, 1] - Y)
+        got = F.composite_value(ax, lrf.nb[0], lrf.lo[0], lrf.hi[0], lrf.xy_coef[i], lrf.xy_nb,
+                                lrf.xy_lo, lrf.xy_hi, r, pos[:, 0], pos[:, 1])
+        np.testing.assert_allclose(got, ref[:, i], rtol=1e-12, atol=1e-15)
+
+
+def test_residual_fit_on_the_true_axial_recovers_a_shared_residual():
+    # noiseless events of a composite LRF with one residual for all sensors:
+    # with the true axial spline subtracted, every estimate is the residual
+    # at the event, and the fit returns its table
+    lrf = _composite_shared_residual()
+    sig, truth = oracle.generate(lrf, 1, 90.0, 0.0, 0.0, 500.0, 2000.0, 3000, 52,
+                                 noiseless=True)
+    L = oracle.lrf_values(lrf, truth[:, :3])
+    ax = np.asarray(lrf.coef).reshape(-1)
+    base = (ax, lrf.nb[0], lrf.lo[0], lrf.hi[0])
+    for i, (X, Y) in enumerate(lrf.sxy):   # no pair is clamped at 0
+        r = np.hypot(truth[:, 0] - X, truth[:, 1] - Y)
+        assert (F.axial_spline(*base, r) + F.spline_2d(lrf.xy_coef[0], lrf.xy_nb, lrf.xy_lo,
+                                                       lrf.xy_hi, truth[:, 0], truth[:, 1]) > 0).all()
+    E = truth[:, 3] / (L @ np.asarray(lrf.gain, np.float64))
+    use = np.ones(len(sig), bool)
+    res, pairs = F.fit_2d_grouped("xy", lrf.sxy, lrf.gain, lrf.active, sig, truth[:, 0],
+                                  truth[:, 1], np.zeros(len(sig)), E, use, lrf.xy_nb, lrf.xy_lo,
+                                  lrf.xy_hi, np.zeros(19, np.int64), ridge=1e-12, base=base)
+    assert pairs[0] == 19 * len(sig)
+    ref = np.asarray(lrf.xy_coef[0])
+    np.testing.assert_allclose(res[0], ref, rtol=0, atol=1e-7 * np.abs(ref).max())
+    # without the subtraction the fit is not the residual
+    off, _ = F.fit_2d_grouped("xy", lrf.sxy, lrf.gain, lrf.active, sig, truth[:, 0], truth[:, 1],
+                              np.zeros(len(sig)), E, use, lrf.xy_nb, lrf.xy_lo, lrf.xy_hi,
+                              np.zeros(19, np.int64), ridge=1e-12)
+    assert np.abs(off[0] - ref).max() > 0.1 * np.abs(ref).max()
+
+
+def test_two_stage_fit_of_an_axial_truth_leaves_no_residual():
+    # purely axial noiseless events: the first stage returns the true axial
+    # spline and every per-sensor residual vanishes (to the ridge's pull on
+    # the last coefficient, whose support the events barely reach)
+    sxy = W.hex_array(2, 30.0)
+    lrf = W.axial_lrf(sxy)
+    sig, truth = oracle.generate(lrf, 1, 90.0, 0.0, 0.0, 500.0, 2000.0, 2000, 53,
+                                 noiseless=True)
+    E = truth[:, 3] / (oracle.lrf_values(lrf, truth[:, :3]) @ np.asarray(lrf.gain, np.float64))
+    use = np.ones(len(sig), bool)
+    ax, res, pairs = F.fit_composite(lrf.sxy, lrf.gain, lrf.active, sig, truth[:, 0], truth[:, 1],
+                                     E, use, lrf.nb[0], lrf.lo[0], lrf.hi[0], (8, 8),
+                                     (-90.0, -90.0), (90.0, 90.0), np.arange(19), ridge=1e-12)
+    true_ax = np.asarray(lrf.coef).reshape(-1)
+    np.testing.assert_allclose(ax, true_ax, rtol=0, atol=1e-7 * np.abs(true_ax).max())
+    assert (pairs == len(sig)).all()
+    assert np.abs(res).max() <= 1e-7 * np.abs(true_ax).max()

@@ -635,6 +635,13 @@ typedef struct {
   double lo[2], hi[2];  /* domains in mm (r-z: lo[0] >= 0)                  */
   double ridge;         /* relative ridge, >= 0                              */
   double chi2ndf_max;   /* event filter; <= 0: no chi2 cut                   */
+  /* Residual of a composite LRF (Sec. 6.1.1; kind XY only): an axial
+   * spline, its value at the pair's distance r from the sensor (not
+   * clamped, 0 outside [base_lo, base_hi]) subtracted from every estimate.
+   * d_base [base_nb + 2] FP64, device memory, caller-owned; NULL: none.  */
+  const double* d_base;
+  int32_t base_nb;      /* 2..256                                            */
+  double base_lo, base_hi;   /* 0 <= base_lo < base_hi, mm                  */
 } ants_fit2d_cfg;
 
 ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d_cfg* cfg,

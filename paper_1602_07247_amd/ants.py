@@ -94,7 +94,9 @@ class GridPlan(C.Structure):
 
 class Fit2dCfg(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nb", C.c_int32 * 2), ("lo", C.c_double * 2),
-                ("hi", C.c_double * 2), ("ridge", C.c_double), ("chi2ndf_max", C.c_double)]
+                ("hi", C.c_double * 2), ("ridge", C.c_double), ("chi2ndf_max", C.c_double),
+                ("d_base", C.c_void_p), ("base_nb", C.c_int32), ("base_lo", C.c_double),
+                ("base_hi", C.c_double)]
 
 
 class MigradCfg(C.Structure):
@@ -754,13 +756,22 @@ def fit_axial_lrf_grouped(lrfset: LrfSet, cfg: FitCfg, groups, signals, rec, shi
     return coef, counts
 
 
-def fit2d_cfg(kind, nb, lo, hi, ridge=1e-9, chi2ndf_max=0.0) -> Fit2dCfg:
-    """Fit2dCfg for an r-z (kind 3) or XY (kind 2) LRF fit."""
+def fit2d_cfg(kind, nb, lo, hi, ridge=1e-9, chi2ndf_max=0.0, base=None) -> Fit2dCfg:
+    """Fit2dCfg for an r-z (kind 3) or XY (kind 2) LRF fit.  base =
+    (coefficients [nb_b + 2] float64 on the GPU, nb_b, lo_b, hi_b): the axial
+    part of a composite LRF, subtracted from every estimate (XY residual
+    fits); the config keeps a reference to the tensor."""
     c = Fit2dCfg()
     c.kind = int(kind)
     for a in range(2):
         c.nb[a], c.lo[a], c.hi[a] = int(nb[a]), float(lo[a]), float(hi[a])
     c.ridge, c.chi2ndf_max = float(ridge), float(chi2ndf_max)
+    if base is not None:
+        t, bnb, blo, bhi = base
+        assert t.is_cuda and t.dtype.is_floating_point and t.numel() == int(bnb) + 2
+        t = t.to(dtype=__import__("torch").float64).contiguous()
+        c._base = t
+        c.d_base, c.base_nb, c.base_lo, c.base_hi = t.data_ptr(), int(bnb), float(blo), float(bhi)
     return c
 
 
@@ -786,6 +797,21 @@ def fit_lrf2d_grouped(lrfset: LrfSet, cfg: Fit2dCfg, groups, signals, rec, shift
         _out_struct(rec), sh.data_ptr() if sh is not None else None, coef.data_ptr(),
         counts.data_ptr(), _stream_handle(stream)))
     return coef, counts
+
+
+def fit_composite(lrfset: LrfSet, nb, lo, hi, xy_nb, xy_lo, xy_hi, xy_groups, signals, rec,
+                  shift=None, ridge=1e-9, chi2ndf_max=0.0, stream=None):
+    """Composite LRF fit (Sec. 6.1.1) in two stages: the shared axial table
+    (nb, lo, hi), then one XY residual table per group of xy_groups fitted to
+    the estimates minus that axial spline.  Returns (axial [nb + 2], residuals
+    [G][xy_nb1 + 2][xy_nb0 + 2], residual counts [G][2]), device tensors
+    (asynchronous).  A shift, when given, applies to both stages."""
+    ax, _ = fit_axial_lrf_grouped(lrfset, fit_cfg(nb, lo, hi, ridge, chi2ndf_max),
+                                  groups_all(lrfset.n_sensors), signals, rec, shift, stream)
+    ax = ax[0]
+    cfg = fit2d_cfg(LRF_XY, xy_nb, xy_lo, xy_hi, ridge, chi2ndf_max, base=(ax, nb, lo, hi))
+    res, counts = fit_lrf2d_grouped(lrfset, cfg, xy_groups, signals, rec, shift, stream)
+    return ax, res, counts
 
 
 def fit_axial_gains(lrfset: LrfSet, cfg: FitCfg, tables, table_of, signals, rec, shift=None,
@@ -927,6 +953,101 @@ class Lrf2dModel:
     def with_active(self, active):
         return Lrf2dModel(self.kind, self.sxy, self.gain, active, self.nb, self.lo, self.hi,
                           self.tables, self.table_of)
+
+
+class CompositeModel:
+    """Detector model with a composite LRF (Sec. 6.1.1): the shared axial
+    table `axial` [nb + 2] on [lo, hi] plus XY residual tables `xy_tables`
+    [T][xy_nb1 + 2][xy_nb0 + 2] (`xy_table_of`: the table of each sensor,
+    default one shared table); the fields LrfSet reads."""
+
+    def __init__(self, sxy, gain, active, nb, lo, hi, axial, xy_nb, xy_lo, xy_hi, xy_tables,
+                 xy_table_of=None):
+        self.kind = LRF_COMPOSITE
+        self.shared = 1
+        self.sxy = np.ascontiguousarray(sxy, np.float64)
+        self.gain = np.ascontiguousarray(gain, np.float64)
+        self.active = np.ascontiguousarray(active, np.uint8)
+        self.nb, self.lo, self.hi = (int(nb), 1), (float(lo), 0.0), (float(hi), 0.0)
+        self.axial = np.ascontiguousarray(axial, np.float64).reshape(-1)
+        self.coef = self.axial.reshape(1, 1, -1)
+        self.xy_nb = (int(xy_nb[0]), int(xy_nb[1]))
+        self.xy_lo = (float(xy_lo[0]), float(xy_lo[1]))
+        self.xy_hi = (float(xy_hi[0]), float(xy_hi[1]))
+        self.xy_tables = np.ascontiguousarray(xy_tables, np.float64).reshape(
+            -1, self.xy_nb[1] + 2, self.xy_nb[0] + 2)
+        n = len(self.sxy)
+        self.xy_table_of = (np.zeros(n, np.int32) if xy_table_of is None
+                            else np.ascontiguousarray(xy_table_of, np.int32))
+        if len(self.xy_tables) == 1 and (self.xy_table_of == 0).all():
+            self.xy_shared = 1
+            self.xy_coef = self.xy_tables
+        else:
+            self.xy_shared = 0
+            self.xy_coef = self.xy_tables[np.maximum(self.xy_table_of, 0)]
+
+    def with_active(self, active):
+        return CompositeModel(self.sxy, self.gain, active, self.nb[0], self.lo[0], self.hi[0],
+                              self.axial, self.xy_nb, self.xy_lo, self.xy_hi, self.xy_tables,
+                              self.xy_table_of)
+
+
+def iterate_composite(model, grid: GridCfg, signals, iterations, xy_groups=None, ridge=1e-9,
+                      chi2ndf_max=0.0, stream=None, shift_sigma=0.0, shift_iterations=0,
+                      shift_seed=0, disable=None):
+    """Iterative LRF reconstruction (Sec. 8) for composite models: each fit
+    is the two-stage composite fit (the shared axial table, then the XY
+    residuals per group of xy_groups: None for one residual per sensor, an
+    array, or a function of the fit index).  Shifts and disabled sensors as
+    in iterate_axial_lrf; a residual group whose fit fails keeps its
+    previous tables, and a failed axial fit keeps the model.  Returns the
+    models and the last reconstruction."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    models = [model]
+    n = signals.shape[0]
+    for k in range(iterations + 1):
+        cur = models[-1]
+        act = np.asarray(cur.active, np.uint8).copy()
+        if disable and k in disable:
+            act[np.asarray(disable[k], np.int64)] = 0
+        ls = LrfSet(cur.with_active(act))
+        rec = reconstruct(ls, grid, signals, stream=st)
+        if k == iterations:
+            st.synchronize()
+            ls.close()
+            break
+        fs = LrfSet(cur) if disable and k in disable else ls
+        ns = len(cur.sxy)
+        g = xy_groups(k) if callable(xy_groups) else xy_groups
+        g = groups_individual(ns) if g is None else np.asarray(g, np.int32)
+        shift = None
+        if shift_sigma > 0.0 and k < shift_iterations:
+            gen = torch.Generator(device=signals.device).manual_seed(int(shift_seed) + k)
+            shift = torch.randn((n, 2), generator=gen, device=signals.device,
+                                dtype=torch.float32) * float(shift_sigma)
+        ax, res, _ = fit_composite(fs, cur.nb[0], cur.lo[0], cur.hi[0], cur.xy_nb, cur.xy_lo,
+                                   cur.xy_hi, g, signals, rec, shift, ridge, chi2ndf_max, st)
+        st.synchronize()
+        ax, res = ax.cpu().numpy(), res.cpu().numpy()
+        if fs is not ls:
+            fs.close()
+        ls.close()
+        if not np.isfinite(ax).all():
+            models.append(cur)
+            continue
+        new = cur.xy_tables[np.maximum(cur.xy_table_of, 0)].copy()
+        for i in range(ns):
+            if 0 <= g[i] < len(res) and np.isfinite(res[g[i]]).all():
+                new[i] = res[g[i]]
+        if (g == 0).all() and np.isfinite(res[0]).all():
+            nxt = CompositeModel(cur.sxy, cur.gain, cur.active, cur.nb[0], cur.lo[0], cur.hi[0],
+                                 ax, cur.xy_nb, cur.xy_lo, cur.xy_hi, res[0])
+        else:
+            nxt = CompositeModel(cur.sxy, cur.gain, cur.active, cur.nb[0], cur.lo[0], cur.hi[0],
+                                 ax, cur.xy_nb, cur.xy_lo, cur.xy_hi, new, np.arange(ns))
+        models.append(nxt)
+    return models, rec
 
 
 def _check_rz_groups(kind, g):

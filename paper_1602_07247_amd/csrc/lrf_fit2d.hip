@@ -51,6 +51,9 @@ struct Fit2P {
   const int32_t *ndf, *status;
   const float* shift;
   double chi2ndf_max;
+  const double* base;  // composite residual: axial spline subtracted at r, or NULL
+  int base_nb;
+  double base_lo, base_hi, base_inv;
   int rz;              // 1: arguments (r, z); 0: (x, y)
   int nb0, nb1, nc0, nc, bw;
   double lo0, hi0, lo1, hi1, inv_d0, inv_d1;
@@ -65,6 +68,18 @@ struct Fit2P {
   int64_t chunk_len;
   double* part;        // [chunks][rows][groups * no * kFit2Terms]
 };
+
+// the composite's axial part at distance r: the spline, not clamped, 0
+// outside its domain
+__device__ __forceinline__ double base_value(const Fit2P& P, double r) {
+  int m;
+  double t;
+  if (!locate64(r, P.base_nb, P.base_lo, P.base_hi, P.base_inv, m, t)) return 0.0;
+  double b[4];
+  bweights64(t, b);
+  const double* c = P.base + m;
+  return b[0] * c[0] + b[1] * c[1] + b[2] * c[2] + b[3] * c[3];
+}
 
 // the event's filter (status failure bits, energy, chi2/ndf)
 __device__ __forceinline__ bool fit2_keep(const Fit2P& P, int64_t e) {
@@ -119,7 +134,11 @@ __global__ void __launch_bounds__(256) fit2_accum_kernel(Fit2P P) {
       double b0[4], b1[4];
       bweights64(t0, b0);
       bweights64(t1, b1);
-      const double tg = (double)row[P.col[a]] / (Ee * P.g[a]);
+      double tg = (double)row[P.col[a]] / (Ee * P.g[a]);
+      if (P.base) {
+        const double dx = xe - P.X[a], dy = ye - P.Y[a];
+        tg -= base_value(P, sqrt(dx * dx + dy * dy));
+      }
       double* band = P.band + (int64_t)gr * P.nc * (bw + 1);
       double* rhs = P.rhs + (int64_t)gr * P.nc;
       int idx[16];
@@ -248,7 +267,11 @@ __global__ void __launch_bounds__(256) fit2_rows_kernel(Fit2P P) {
           if (!locate64(u, P.nb0, P.lo0, P.hi0, P.inv_d0, m0, t0)) continue;
           double b0[4];
           bweights64(t0, b0);
-          const double tg = (double)sv[c][q] / (Ee[c] * sg[q]);
+          double tg = (double)sv[c][q] / (Ee[c] * sg[q]);
+          if (P.base) {
+            const double dx = xe[c] - sX[q], dy = ye[c] - sY[q];
+            tg -= base_value(P, sqrt(dx * dx + dy * dy));
+          }
           double wt[16];
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq)
@@ -538,6 +561,15 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
   }
   if (cfg->kind == ANTS_LRF_RZ && cfg->lo[0] < 0.0)
     return set_error(ANTS_E_ARG, "%s: an r domain starts at r >= 0", who);
+  if (cfg->d_base) {
+    if (cfg->kind != ANTS_LRF_XY)
+      return set_error(ANTS_E_ARG, "%s: an axial base is for XY residual fits", who);
+    if (cfg->base_nb < 2 || cfg->base_nb > 256)
+      return set_error(ANTS_E_ARG, "%s: base_nb = %d outside 2..256", who, cfg->base_nb);
+    if (!(cfg->base_lo >= 0.0 && cfg->base_hi > cfg->base_lo && isfinite(cfg->base_hi)))
+      return set_error(ANTS_E_ARG, "%s: base domain [%g, %g] invalid", who, cfg->base_lo,
+                       cfg->base_hi);
+  }
   if (!(cfg->ridge >= 0.0 && cfg->ridge < 1e300))
     return set_error(ANTS_E_ARG, "%s: ridge %g invalid", who, cfg->ridge);
   if (n_groups < 1 || n_groups > kFit2MaxGroups)
@@ -608,6 +640,11 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
     P.status = rec.status;
     P.shift = d_shift;
     P.chi2ndf_max = cfg->chi2ndf_max;
+    P.base = cfg->d_base;
+    P.base_nb = cfg->base_nb;
+    P.base_lo = cfg->base_lo;
+    P.base_hi = cfg->base_hi;
+    P.base_inv = cfg->d_base ? (double)(cfg->base_nb - 1) / (cfg->base_hi - cfg->base_lo) : 0.0;
     P.rz = cfg->kind == ANTS_LRF_RZ;
     P.nb0 = cfg->nb[0];
     P.nb1 = cfg->nb[1];

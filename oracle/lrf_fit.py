@@ -37,7 +37,12 @@ Readings (the paper prints no fit formula):
     XY residual per sensor or shared; the LRF is max(axial + residual, 0),
     each part 0 outside its own domain) are fitted in two stages: the
     shared axial fit above, then the XY residual fitted to the estimates
-    n_ie / (E_e g_i) minus the fitted axial spline at r_ie (not clamped).
+    n_ie / (E_e g_i) minus the fitted axial spline at r_ie (not clamped);
+  * sliced LRFs (Sec. 6.1.2: XY LRFs on n_planes z planes, interpolated
+    linearly between the two closest): each plane's tables are fitted as
+    XY LRFs to the events whose reconstructed z is nearest that plane,
+    z in [z_p - d/2, z_p + d/2) for plane spacing d (the first plane's
+    window open below, the last's open above).
 """
 from __future__ import annotations
 
@@ -341,3 +346,27 @@ def fit_composite(sxy, gain, active, signals, x, y, E, use, nb, lo, hi, xy_nb, x
     res, pairs = fit_2d_grouped("xy", sxy, gain, active, signals, x, y, z, E, use, xy_nb, xy_lo,
                                 xy_hi, xy_groups, ridge, shift, (axial, nb, lo, hi))
     return axial, res, pairs
+
+
+def slice_windows(n_planes, z_lo, z_hi):
+    """Depth window [a, b) of each plane: the events nearest that plane."""
+    d = (z_hi - z_lo) / (n_planes - 1)
+    cuts = [z_lo + (p + 0.5) * d for p in range(n_planes - 1)]
+    lows = [-np.inf] + cuts
+    highs = cuts + [np.inf]
+    return list(zip(lows, highs))
+
+
+def fit_sliced(sxy, gain, active, signals, x, y, z, E, use, nb, lo, hi, n_planes, z_lo, z_hi,
+               groups, ridge=1e-9, shift=None):
+    """Per-plane XY fits of a sliced LRF: tables [G][n_planes][nb1 + 2]
+    [nb0 + 2] and pair counts [n_planes][G]."""
+    zz = np.asarray(z, np.float64)
+    tabs, pairs = [], []
+    for a, b in slice_windows(n_planes, z_lo, z_hi):
+        u = np.asarray(use, bool) & (zz >= a) & (zz < b)
+        c, n = fit_2d_grouped("xy", sxy, gain, active, signals, x, y, z, E, u, nb, lo, hi,
+                              groups, ridge, shift)
+        tabs.append(c)
+        pairs.append(n)
+    return np.stack(tabs, 1), np.stack(pairs)

@@ -416,3 +416,51 @@ def test_two_stage_fit_of_an_axial_truth_leaves_no_residual():
     np.testing.assert_allclose(ax, true_ax, rtol=0, atol=1e-7 * np.abs(true_ax).max())
     assert (pairs == len(sig)).all()
     assert np.abs(res).max() <= 1e-7 * np.abs(true_ax).max()
+
+
+# ---- sliced LRFs (Sec. 6.1.2): XY tables on z planes
+
+def test_slice_windows_cover_every_depth_once():
+    w = F.slice_windows(6, 0.0, 50.0)
+    z = np.linspace(-20.0, 70.0, 9001)
+    hits = sum((z >= a) & (z < b) for a, b in w)
+    assert (hits == 1).all()
+    # each plane's own depth lies in its window, halfway cuts between planes
+    for p, (a, b) in enumerate(w):
+        assert a <= 10.0 * p < b
+    assert w[1] == (5.0, 15.0)
+
+
+def test_sliced_fit_recovers_each_planes_tables():
+    # noiseless events exactly on the planes: each plane's per-sensor fit
+    # reproduces that plane's tables wherever the plane's events probe them
+    sxy = W.hex_array(2, 30.0)
+    lrf = W.sliced_lrf(sxy, n_planes=3, nb=20)
+    zp = np.linspace(lrf.z_lo, lrf.z_hi, lrf.n_planes)
+    parts = [oracle.generate(lrf, 1, 130.0, z, z, 500.0, 2000.0, 2000, 60 + p, noiseless=True)
+             for p, z in enumerate(zp)]
+    sig = np.concatenate([s for s, _ in parts])
+    truth = np.concatenate([t for _, t in parts])
+    E = truth[:, 3] / (oracle.lrf_values(lrf, truth[:, :3]) @ np.asarray(lrf.gain, np.float64))
+    tabs = np.asarray(lrf.coef)
+    for i in (0, 9):   # no pair is clamped at 0
+        for p in range(lrf.n_planes):
+            on = truth[:, 2] == zp[p]
+            assert (F.spline_2d(tabs[i, p], lrf.nb, lrf.lo, lrf.hi, truth[on, 0],
+                                truth[on, 1]) > 0).all()
+    use = np.ones(len(sig), bool)
+    got, pairs = F.fit_sliced(lrf.sxy, lrf.gain, lrf.active, sig, truth[:, 0], truth[:, 1],
+                              truth[:, 2], E, use, lrf.nb, lrf.lo, lrf.hi, lrf.n_planes,
+                              lrf.z_lo, lrf.z_hi, np.arange(19), ridge=1e-12)
+    assert got.shape == tabs.shape
+    assert (pairs == 2000).all()
+    for i in range(19):
+        for p in range(lrf.n_planes):
+            on = truth[:, 2] == zp[p]
+            ref = F.spline_2d(tabs[i, p], lrf.nb, lrf.lo, lrf.hi, truth[on, 0], truth[on, 1])
+            fit = F.spline_2d(got[i, p], lrf.nb, lrf.lo, lrf.hi, truth[on, 0], truth[on, 1])
+            assert np.max(np.abs(fit - ref)) < 1e-7 * np.max(ref), (i, p)
+            # another plane's table does not fit this plane's events
+            q = (p + 1) % lrf.n_planes
+            other = F.spline_2d(tabs[i, q], lrf.nb, lrf.lo, lrf.hi, truth[on, 0], truth[on, 1])
+            assert np.max(np.abs(other - ref)) > 0.01 * np.max(ref)

@@ -642,6 +642,10 @@ typedef struct {
   const double* d_base;
   int32_t base_nb;      /* 2..256                                            */
   double base_lo, base_hi;   /* 0 <= base_lo < base_hi, mm                  */
+  /* Depth window (one plane of a sliced LRF, Sec. 6.1.2): only events with
+   * ev_z_lo <= rec.z < ev_z_hi enter; ev_z_lo >= ev_z_hi: no window.
+   * Infinite bounds are allowed, NaN is not.                              */
+  double ev_z_lo, ev_z_hi;
 } ants_fit2d_cfg;
 
 ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d_cfg* cfg,

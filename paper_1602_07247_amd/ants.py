@@ -8,6 +8,7 @@ missing; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -96,7 +97,7 @@ class Fit2dCfg(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nb", C.c_int32 * 2), ("lo", C.c_double * 2),
                 ("hi", C.c_double * 2), ("ridge", C.c_double), ("chi2ndf_max", C.c_double),
                 ("d_base", C.c_void_p), ("base_nb", C.c_int32), ("base_lo", C.c_double),
-                ("base_hi", C.c_double)]
+                ("base_hi", C.c_double), ("ev_z_lo", C.c_double), ("ev_z_hi", C.c_double)]
 
 
 class MigradCfg(C.Structure):
@@ -756,11 +757,13 @@ def fit_axial_lrf_grouped(lrfset: LrfSet, cfg: FitCfg, groups, signals, rec, shi
     return coef, counts
 
 
-def fit2d_cfg(kind, nb, lo, hi, ridge=1e-9, chi2ndf_max=0.0, base=None) -> Fit2dCfg:
+def fit2d_cfg(kind, nb, lo, hi, ridge=1e-9, chi2ndf_max=0.0, base=None,
+              z_window=None) -> Fit2dCfg:
     """Fit2dCfg for an r-z (kind 3) or XY (kind 2) LRF fit.  base =
     (coefficients [nb_b + 2] float64 on the GPU, nb_b, lo_b, hi_b): the axial
     part of a composite LRF, subtracted from every estimate (XY residual
-    fits); the config keeps a reference to the tensor."""
+    fits); the config keeps a reference to the tensor.  z_window = (a, b):
+    only events with a <= z < b (one plane of a sliced LRF)."""
     c = Fit2dCfg()
     c.kind = int(kind)
     for a in range(2):
@@ -772,6 +775,8 @@ def fit2d_cfg(kind, nb, lo, hi, ridge=1e-9, chi2ndf_max=0.0, base=None) -> Fit2d
         t = t.to(dtype=__import__("torch").float64).contiguous()
         c._base = t
         c.d_base, c.base_nb, c.base_lo, c.base_hi = t.data_ptr(), int(bnb), float(blo), float(bhi)
+    if z_window is not None:
+        c.ev_z_lo, c.ev_z_hi = float(z_window[0]), float(z_window[1])
     return c
 
 
@@ -812,6 +817,30 @@ def fit_composite(lrfset: LrfSet, nb, lo, hi, xy_nb, xy_lo, xy_hi, xy_groups, si
     cfg = fit2d_cfg(LRF_XY, xy_nb, xy_lo, xy_hi, ridge, chi2ndf_max, base=(ax, nb, lo, hi))
     res, counts = fit_lrf2d_grouped(lrfset, cfg, xy_groups, signals, rec, shift, stream)
     return ax, res, counts
+
+
+def slice_windows(n_planes, z_lo, z_hi):
+    """Depth window [a, b) of each plane of a sliced LRF: the events nearest
+    that plane (cuts halfway between planes; the outer windows open)."""
+    d = (z_hi - z_lo) / (n_planes - 1)
+    cuts = [z_lo + (p + 0.5) * d for p in range(n_planes - 1)]
+    return list(zip([-math.inf] + cuts, cuts + [math.inf]))
+
+
+def fit_sliced(lrfset: LrfSet, nb, lo, hi, n_planes, z_lo, z_hi, groups, signals, rec,
+               shift=None, ridge=1e-9, chi2ndf_max=0.0, stream=None):
+    """Sliced LRF fit (Sec. 6.1.2): each plane's XY tables, one per group,
+    fitted to the events nearest that plane.  Returns (tables [G][n_planes]
+    [nb1 + 2][nb0 + 2], counts [n_planes][G][2]), device tensors
+    (asynchronous)."""
+    import torch
+    tabs, counts = [], []
+    for w in slice_windows(n_planes, z_lo, z_hi):
+        cfg = fit2d_cfg(LRF_XY, nb, lo, hi, ridge, chi2ndf_max, z_window=w)
+        c, k = fit_lrf2d_grouped(lrfset, cfg, groups, signals, rec, shift, stream)
+        tabs.append(c)
+        counts.append(k)
+    return torch.stack(tabs, 1), torch.stack(counts)
 
 
 def fit_axial_gains(lrfset: LrfSet, cfg: FitCfg, tables, table_of, signals, rec, shift=None,
@@ -1047,6 +1076,89 @@ def iterate_composite(model, grid: GridCfg, signals, iterations, xy_groups=None,
             nxt = CompositeModel(cur.sxy, cur.gain, cur.active, cur.nb[0], cur.lo[0], cur.hi[0],
                                  ax, cur.xy_nb, cur.xy_lo, cur.xy_hi, new, np.arange(ns))
         models.append(nxt)
+    return models, rec
+
+
+class SlicedModel:
+    """Detector model with a sliced LRF (Sec. 6.1.2): XY tables on n_planes
+    z planes between z_lo and z_hi, `tables` [T][n_planes][nb1 + 2][nb0 + 2]
+    (`table_of`: the table of each sensor, default one per sensor); the
+    fields LrfSet reads."""
+
+    def __init__(self, sxy, gain, active, nb, lo, hi, n_planes, z_lo, z_hi, tables,
+                 table_of=None):
+        self.kind = LRF_SLICED
+        self.sxy = np.ascontiguousarray(sxy, np.float64)
+        self.gain = np.ascontiguousarray(gain, np.float64)
+        self.active = np.ascontiguousarray(active, np.uint8)
+        self.nb = (int(nb[0]), int(nb[1]))
+        self.lo, self.hi = (float(lo[0]), float(lo[1])), (float(hi[0]), float(hi[1]))
+        self.n_planes, self.z_lo, self.z_hi = int(n_planes), float(z_lo), float(z_hi)
+        self.tables = np.ascontiguousarray(tables, np.float64).reshape(
+            -1, self.n_planes, self.nb[1] + 2, self.nb[0] + 2)
+        n = len(self.sxy)
+        self.table_of = (np.arange(n, dtype=np.int32) if table_of is None
+                         else np.ascontiguousarray(table_of, np.int32))
+        if len(self.tables) == 1 and (self.table_of == 0).all():
+            self.shared = 1
+            self.coef = self.tables
+        else:
+            self.shared = 0
+            self.coef = self.tables[np.maximum(self.table_of, 0)]
+
+    def with_active(self, active):
+        return SlicedModel(self.sxy, self.gain, active, self.nb, self.lo, self.hi, self.n_planes,
+                           self.z_lo, self.z_hi, self.tables, self.table_of)
+
+
+def iterate_sliced(model, grid: GridCfg, signals, iterations, groups=None, ridge=1e-9,
+                   chi2ndf_max=0.0, stream=None, shift_sigma=0.0, shift_iterations=0,
+                   shift_seed=0, disable=None):
+    """Iterative LRF reconstruction (Sec. 8) for sliced models: each fit
+    refits every plane's XY tables per group (groups: None for one table per
+    sensor, an array, or a function of the fit index) from the events
+    nearest the plane.  Shifts and disabled sensors as in iterate_axial_lrf;
+    a group or plane whose fit fails keeps its previous tables.  Returns the
+    models and the last reconstruction."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    models = [model]
+    n = signals.shape[0]
+    for k in range(iterations + 1):
+        cur = models[-1]
+        act = np.asarray(cur.active, np.uint8).copy()
+        if disable and k in disable:
+            act[np.asarray(disable[k], np.int64)] = 0
+        ls = LrfSet(cur.with_active(act))
+        rec = reconstruct(ls, grid, signals, stream=st)
+        if k == iterations:
+            st.synchronize()
+            ls.close()
+            break
+        fs = LrfSet(cur) if disable and k in disable else ls
+        ns = len(cur.sxy)
+        g = groups(k) if callable(groups) else groups
+        g = groups_individual(ns) if g is None else np.asarray(g, np.int32)
+        shift = None
+        if shift_sigma > 0.0 and k < shift_iterations:
+            gen = torch.Generator(device=signals.device).manual_seed(int(shift_seed) + k)
+            shift = torch.randn((n, 2), generator=gen, device=signals.device,
+                                dtype=torch.float32) * float(shift_sigma)
+        tabs, _ = fit_sliced(fs, cur.nb, cur.lo, cur.hi, cur.n_planes, cur.z_lo, cur.z_hi, g,
+                             signals, rec, shift, ridge, chi2ndf_max, st)
+        st.synchronize()
+        tabs = tabs.cpu().numpy()
+        if fs is not ls:
+            fs.close()
+        ls.close()
+        new = cur.tables[np.maximum(cur.table_of, 0)].copy()
+        for i in range(ns):
+            if 0 <= g[i] < len(tabs):
+                for p in range(cur.n_planes):
+                    if np.isfinite(tabs[g[i], p]).all():
+                        new[i, p] = tabs[g[i], p]
+        models.append(SlicedModel(cur.sxy, cur.gain, cur.active, cur.nb, cur.lo, cur.hi,
+                                  cur.n_planes, cur.z_lo, cur.z_hi, new, np.arange(ns)))
     return models, rec
 
 

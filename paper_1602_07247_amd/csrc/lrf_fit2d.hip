@@ -54,6 +54,8 @@ struct Fit2P {
   const double* base;  // composite residual: axial spline subtracted at r, or NULL
   int base_nb;
   double base_lo, base_hi, base_inv;
+  int zwin;            // 1: only events with zw_lo <= z < zw_hi
+  double zw_lo, zw_hi;
   int rz;              // 1: arguments (r, z); 0: (x, y)
   int nb0, nb1, nc0, nc, bw;
   double lo0, hi0, lo1, hi1, inv_d0, inv_d1;
@@ -88,6 +90,10 @@ __device__ __forceinline__ bool fit2_keep(const Fit2P& P, int64_t e) {
   if (P.chi2ndf_max > 0.0) {
     const int d = P.ndf[e];
     ok = ok && d > 0 && (double)P.chi2[e] / (double)d <= P.chi2ndf_max;
+  }
+  if (P.zwin) {
+    const double z = P.z[e];
+    ok = ok && z >= P.zw_lo && z < P.zw_hi;
   }
   return ok;
 }
@@ -561,6 +567,8 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
   }
   if (cfg->kind == ANTS_LRF_RZ && cfg->lo[0] < 0.0)
     return set_error(ANTS_E_ARG, "%s: an r domain starts at r >= 0", who);
+  if (isnan(cfg->ev_z_lo) || isnan(cfg->ev_z_hi))
+    return set_error(ANTS_E_ARG, "%s: depth window bound is NaN", who);
   if (cfg->d_base) {
     if (cfg->kind != ANTS_LRF_XY)
       return set_error(ANTS_E_ARG, "%s: an axial base is for XY residual fits", who);
@@ -645,6 +653,9 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
     P.base_lo = cfg->base_lo;
     P.base_hi = cfg->base_hi;
     P.base_inv = cfg->d_base ? (double)(cfg->base_nb - 1) / (cfg->base_hi - cfg->base_lo) : 0.0;
+    P.zwin = cfg->ev_z_lo < cfg->ev_z_hi;
+    P.zw_lo = cfg->ev_z_lo;
+    P.zw_hi = cfg->ev_z_hi;
     P.rz = cfg->kind == ANTS_LRF_RZ;
     P.nb0 = cfg->nb[0];
     P.nb1 = cfg->nb[1];

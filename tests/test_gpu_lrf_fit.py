@@ -515,3 +515,71 @@ def test_iterative_composite_procedure_improves_from_an_axial_start(ants):
     np.testing.assert_array_equal(models[1].axial, ax.cpu().numpy())
     res = res.cpu().numpy()
     np.testing.assert_allclose(models[1].xy_tables, res, rtol=0, atol=1e-9 * np.abs(res).max())
+
+
+# ---- sliced LRFs (Sec. 6.1.2): per-plane XY fits, then the loop
+
+@pytest.mark.parametrize("grouping", ["shared", "individual"])
+def test_sliced_fit_matches_oracle(ants, grouping):
+    lrf = W.sliced_lrf(W.hex_array(2, 30.0))
+    n = 30_000
+    print(f"[gpu] sliced fit {grouping}", flush=True)
+    sig, truth = oracle.generate(lrf, 1, 100.0, lrf.z_lo, lrf.z_hi, 500.0, 2000.0, n, 98)
+    S = oracle.lrf_values(lrf, truth[:, :3]) @ np.asarray(lrf.gain, np.float64)
+    rng = np.random.default_rng(98)
+    r = {"x": truth[:, 0].astype(np.float32), "y": truth[:, 1].astype(np.float32),
+         "z": truth[:, 2].astype(np.float32), "E": (truth[:, 3] / S).astype(np.float32),
+         "chi2": rng.uniform(0.0, 60.0, n).astype(np.float32),
+         "ndf": np.full(n, 15, np.int32), "status": _statuses(rng, n)}
+    groups = np.zeros(19, np.int32) if grouping == "shared" else np.arange(19, dtype=np.int32)
+    L = ants.LrfSet(lrf)
+    tabs, counts = ants.fit_sliced(L, lrf.nb, lrf.lo, lrf.hi, lrf.n_planes, lrf.z_lo, lrf.z_hi,
+                                   groups, torch.from_numpy(sig.astype(np.float32)).cuda(),
+                                   _dev2d(r))
+    torch.cuda.synchronize()
+    L.close()
+    use = F.event_mask(r["E"], r["status"])
+    x64 = {k: r[k].astype(np.float64) for k in ("x", "y", "z", "E")}
+    ref, pairs = F.fit_sliced(lrf.sxy, lrf.gain, lrf.active, sig.astype(np.float32).astype(np.float64),
+                              x64["x"], x64["y"], x64["z"], x64["E"], use, lrf.nb, lrf.lo, lrf.hi,
+                              lrf.n_planes, lrf.z_lo, lrf.z_hi, groups, ridge=1e-9)
+    c = counts.cpu().numpy()
+    np.testing.assert_array_equal(c[:, :, 1], pairs)
+    for p, (a, b) in enumerate(F.slice_windows(lrf.n_planes, lrf.z_lo, lrf.z_hi)):
+        assert (c[p, :, 0] == int((use & (x64["z"] >= a) & (x64["z"] < b)).sum())).all()
+    got = tabs.cpu().numpy()
+    assert got.shape == ref.shape
+    for g in range(len(ref)):
+        for p in range(lrf.n_planes):
+            scale = np.max(np.abs(ref[g, p]))
+            err = np.max(np.abs(got[g, p] - ref[g, p])) / scale
+            assert err <= 1e-7, (g, p, err)
+
+
+def test_iterative_sliced_procedure_from_the_true_lrf(ants):
+    # Sec. 8 with sliced LRFs (6 planes, 19 sensors): two refits of every
+    # plane's per-sensor tables on 100 k events keep sigma_xy near the true
+    # LRF's; the first refit is the per-plane fit of the start's
+    # reconstruction
+    lrf = W.sliced_lrf(W.hex_array(2, 30.0))
+    Lt = ants.LrfSet(lrf)
+    sig, truth = ants.generate(Lt, ants.gen_cfg(W.EventRecipe("square", 80.0, 500.0, 2000.0,
+                                                              0.0, 50.0, True)), 100_000, 23)
+    Lt.close()
+    grid = ants.grid_cfg(W.GridCfg((7, 7, 7), 8, 0.5, (10.0, 10.0, 50.0 / 6.0), 25.0))
+    t = truth.cpu().numpy()
+    inner = (np.abs(t[:, 0]) < 60) & (np.abs(t[:, 1]) < 60)
+    start = ants.SlicedModel(lrf.sxy, lrf.gain, lrf.active, lrf.nb, lrf.lo, lrf.hi, lrf.n_planes,
+                             lrf.z_lo, lrf.z_hi, lrf.coef)
+    models, last = ants.iterate_sliced(start, grid, sig, 2)
+    errs = [_sigma_xy(ants, m, grid, sig, t, inner) for m in models]
+    print("sliced sigma_xy per iteration", np.round(errs, 4).tolist())
+    assert max(errs[1:]) < 1.10 * errs[0], errs
+    L0 = ants.LrfSet(models[0])
+    rec0 = ants.reconstruct(L0, grid, sig)
+    tabs, _ = ants.fit_sliced(L0, lrf.nb, lrf.lo, lrf.hi, lrf.n_planes, lrf.z_lo, lrf.z_hi,
+                              np.arange(19, dtype=np.int32), sig, rec0)
+    torch.cuda.synchronize()
+    L0.close()
+    tabs = tabs.cpu().numpy()
+    np.testing.assert_allclose(models[1].tables, tabs, rtol=0, atol=1e-9 * np.abs(tabs).max())

@@ -341,6 +341,25 @@ def lrf_fit2d_step(args):
                          "kernel": "fit2_zero, fit2_rows, fit2_chunks, fit2_assemble, fit2_solve kernels "
                                    "(FP64)", "kernel_ms": ev_f, "flop_per_launch": flops,
                          "flop_per_pair": FLOP_PER_FIT2D_PAIR}}
+    # groupings of per-sensor XY tables: 1 M events of the 8 x 8 detector
+    # reconstructed with its true LRFs, one fit per grouping (HIP events)
+    wx = W.workload(1)
+    Lx = ants.LrfSet(wx.lrf)
+    sx, _ = ants.generate(Lx, ants.gen_cfg(wx.events), 1_000_000, args.seed + 1)
+    ox = ants.reconstruct(Lx, ants.grid_cfg(wx.grid), sx, stream=stream)
+    cx = ants.fit2d_cfg(wx.lrf.kind, wx.lrf.nb, wx.lrf.lo, wx.lrf.hi, 1e-9)
+    per_group = {}
+    for name, g in (("shared", np.zeros(64, np.int32)),
+                    ("8_groups_of_8", (np.arange(64) // 8).astype(np.int32)),
+                    ("per_sensor", np.arange(64, dtype=np.int32))):
+        _, ev_g = timed(lambda g=g: ants.fit_lrf2d_grouped(Lx, cx, g, sx, ox, None, stream),
+                        args.steps, args.warmup, stream)
+        _, kg = ants.fit_lrf2d_grouped(Lx, cx, g, sx, ox, None, stream)
+        npairs = int(kg[:, 1].sum().item())
+        per_group[name] = {"ms": ev_g, "pairs": npairs, "pairs_per_s": npairs / (ev_g * 1e-3)}
+    torch.cuda.synchronize()
+    Lx.close()
+    rec_["xy64_1M_groupings"] = per_group
     if args.cpu_sample > 0:
         from oracle import lrf_fit as F
         m = min(2 * args.cpu_sample, n)

@@ -618,17 +618,17 @@ ants_status ants_fit_axial_lrf_grouped(ants_lrfset* set, const ants_fit_cfg* cfg
  * (d_group by sensor index, -1 left out) and shifts as for
  * ants_fit_axial_lrf_grouped.  Writes d_coef [n_groups][nb[1] + 2][nb[0] +
  * 2] FP64 (NaN tables for groups without a positive definite system) and
- * d_counts [n_groups][2] (events used, pairs) when not NULL.  When a row
- * of patch origins fits two waves' LDS for every group (n_groups (nb[0] -
- * 1) <= 66), the normal equations are summed per row in LDS and added in a
- * fixed order: results repeat bit for bit.  Otherwise they are summed with
- * FP64 atomic adds in global memory and may differ in the last bits from
- * call to call.  Either way they agree with an FP64 reference to
- * rounding.  nb 4..64 per axis, 1..1024 groups; workspace, kept in the set:
- * 8 (nb[0] + 2)(nb[1] + 2)(3 nb[0] + 12) bytes per group, plus on the row
- * path 1216 n_groups (nb[0] - 1)(nb[1] - 1)(chunks + 1) bytes with about
- * 4 x (compute units) / (nb[1] - 1) chunks (29 MB for one 24 x 16 table on
- * 256 compute units).  Asynchronous on hip_stream. */
+ * d_counts [n_groups][2] (events used, pairs) when not NULL.  The events
+ * are bucketed by the interval of their second coordinate and the normal
+ * equations summed per interval in LDS, then added in a fixed order:
+ * results repeat bit for bit and agree with an FP64 reference to rounding.
+ * nb 4..64 per axis, 1..1024 groups, at most 2^31 - 1 events; workspace,
+ * kept in the set: 8 (nb[0] + 2)(nb[1] + 2)(3 nb[0] + 12) bytes per group,
+ * plus 1216 n_groups (nb[0] - 1)(nb[1] - 1)(segments + 1) bytes with about
+ * 4 x (compute units) / ((nb[1] - 1) x batches of groups) segments (a batch
+ * holds up to about 65 / (nb[0] - 1) groups; 29 MB for one 24 x 16 table
+ * on 256 compute units), plus 4 bytes per event.  Asynchronous on
+ * hip_stream. */
 typedef struct {
   int32_t kind;         /* ANTS_LRF_RZ or ANTS_LRF_XY                       */
   int32_t nb[2];        /* breakpoints per axis (u = r or x, w = z or y)     */

@@ -14,15 +14,15 @@
 // Accumulation.  A pair's contribution is 136 products of its 16 patch
 // weights and 16 right-side terms, all at its patch origin (m0, m1).  The
 // second argument (z for r-z, y for XY) belongs to the event, so every pair
-// of an event has the same m1: blocks own one m1 row and one chunk of
-// events, take the events of their row, and each wave sums its pairs into
-// its own LDS copy of the row's per-origin sums (152 FP64 per origin and
-// group).  The block adds its waves' copies in wave order, a second kernel
-// adds the chunks in chunk order, and one wave per group adds the origins
-// into the band in origin order: the same bits on every call.  When a
-// row's sums for every group do not fit two waves' LDS (many groups), the
-// pairs go straight to the band by FP64 global atomics instead (sums in
-// arrival order: the last bits may differ from call to call).
+// of an event has the same m1 (its row).  The kept events are bucketed by
+// row (a stable counting sort: counts per event chunk, offsets, scatter in
+// event order).  Blocks own one row, one segment of its events and one
+// batch of groups (as many as two waves' LDS copies of the row's
+// per-origin sums hold: 152 FP64 per origin and group); lanes take (event,
+// member sensor) pairs and each wave adds them into its own copy.  The
+// block adds its waves' copies in wave order, a second kernel the segments
+// in segment order, and each band entry is the sum over the origins that
+// hold it, in origin order: the same bits on every call.
 #include <math.h>
 #include <string.h>
 
@@ -66,9 +66,8 @@ struct Fit2P {
   unsigned long long* pairs;   // [groups]
   unsigned long long* used;    // [1]
   // row accumulation: rows = nb1 - 1, no = nb0 - 1 origins per row
-  int rows, no, chunks;
-  int64_t chunk_len;
-  double* part;        // [chunks][rows][groups * no * kFit2Terms]
+  int rows, no;
+  double* part;        // [segments][rows][groups * no * kFit2Terms]
 };
 
 // the composite's axial part at distance r: the spline, not clamped, 0
@@ -104,212 +103,203 @@ __global__ void fit2_zero_kernel(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
-// one wave per event at a time, lanes over the active sensors
-__global__ void __launch_bounds__(256) fit2_accum_kernel(Fit2P P) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const int nc0 = P.nc0, bw = P.bw;
-  for (int64_t e = w0; e < P.n; e += nw) {
-    const float Ef = P.E[e];
-    if (!fit2_keep(P, e)) continue;   // uniform over the wave
-    if (lane == 0) atomicAdd(P.used, 1ull);
-    double xe = P.x[e], ye = P.y[e];
-    if (P.shift) {
-      xe += (double)P.shift[2 * e];
-      ye += (double)P.shift[2 * e + 1];
-    }
-    const double ze = P.z[e], Ee = Ef;
-    const float* row = P.sig + e * P.ld;
-    for (int a = lane; a < P.na; a += 64) {
-      const int gr = P.group[P.col[a]];
-      if (gr < 0 || gr >= P.groups) continue;
-      double u, w;
-      if (P.rz) {
-        const double dx = xe - P.X[a], dy = ye - P.Y[a];
-        u = sqrt(dx * dx + dy * dy);
-        w = ze;
-      } else {
-        u = xe;
-        w = ye;
-      }
-      int m0, m1;
-      double t0, t1;
-      if (!locate64(u, P.nb0, P.lo0, P.hi0, P.inv_d0, m0, t0)) continue;
-      if (!locate64(w, P.nb1, P.lo1, P.hi1, P.inv_d1, m1, t1)) continue;
-      double b0[4], b1[4];
-      bweights64(t0, b0);
-      bweights64(t1, b1);
-      double tg = (double)row[P.col[a]] / (Ee * P.g[a]);
-      if (P.base) {
-        const double dx = xe - P.X[a], dy = ye - P.Y[a];
-        tg -= base_value(P, sqrt(dx * dx + dy * dy));
-      }
-      double* band = P.band + (int64_t)gr * P.nc * (bw + 1);
-      double* rhs = P.rhs + (int64_t)gr * P.nc;
-      int idx[16];
-      double wt[16];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          idx[4 * q + p] = (m1 + q) * nc0 + (m0 + p);
-          wt[4 * q + p] = b1[q] * b0[p];
-        }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        atomicAdd(&rhs[idx[i]], wt[i] * tg);
-#pragma unroll
-        for (int j = i; j < 16; ++j)   // idx increases with (q, p): idx[j] >= idx[i]
-          atomicAdd(&band[(int64_t)idx[i] * (bw + 1) + (idx[j] - idx[i])], wt[i] * wt[j]);
-      }
-      atomicAdd(&P.pairs[gr], 1ull);
+// ---- events bucketed by row (a stable counting sort), then blocks (row,
+// segment of the row's events, batch of groups) with lanes over (event,
+// member sensor) pairs
+
+// the event's row (the interval of its z or y), or -1 when it is not kept
+// or lies outside the second axis' domain
+__device__ __forceinline__ int fit2_event_row(const Fit2P& P, int64_t e, bool& kept) {
+  kept = fit2_keep(P, e);
+  if (!kept) return -1;
+  double w = P.rz ? (double)P.z[e] : (double)P.y[e];
+  if (!P.rz && P.shift) w += (double)P.shift[2 * e + 1];
+  int m1;
+  double t1;
+  return locate64(w, P.nb1, P.lo1, P.hi1, P.inv_d1, m1, t1) ? m1 : -1;
+}
+
+// per event chunk: kept events (added to used) and events per row
+__global__ void __launch_bounds__(256) fit2_rowcount_kernel(Fit2P P, int* cnt, int64_t clen) {
+  __shared__ int h[kFit2MaxKnots];
+  __shared__ unsigned long long kept_sum;
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < P.rows; i += blockDim.x) h[i] = 0;
+  if (threadIdx.x == 0) kept_sum = 0ull;
+  __syncthreads();
+  const int64_t e0 = (int64_t)c * clen, e1 = e0 + clen < P.n ? e0 + clen : P.n;
+  unsigned long long kept_n = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    bool kept;
+    const int r = fit2_event_row(P, e, kept);
+    kept_n += kept ? 1ull : 0ull;
+    if (r >= 0) atomicAdd(&h[r], 1);
+  }
+  atomicAdd(&kept_sum, kept_n);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P.rows; i += blockDim.x) cnt[(int64_t)c * P.rows + i] = h[i];
+  if (threadIdx.x == 0 && kept_sum) atomicAdd(P.used, kept_sum);
+}
+
+// offsets: row r's events start at rstart[r]; chunk c's events of row r at
+// off[c][r] (rows in order, chunks in order within a row)
+__global__ void __launch_bounds__(64) fit2_rowscan_kernel(const int* cnt, int* off, int* rstart,
+                                                          int rows, int cchunks) {
+  __shared__ int tot[kFit2MaxKnots];
+  const int r = threadIdx.x;
+  if (r < rows) {
+    int t = 0;
+    for (int c = 0; c < cchunks; ++c) t += cnt[(int64_t)c * rows + r];
+    tot[r] = t;
+  }
+  __syncthreads();
+  if (r < rows) {
+    int base = 0;
+    for (int q = 0; q < r; ++q) base += tot[q];
+    rstart[r] = base;
+    if (r == rows - 1) rstart[rows] = base + tot[r];
+    for (int c = 0; c < cchunks; ++c) {
+      off[(int64_t)c * rows + r] = base;
+      base += cnt[(int64_t)c * rows + r];
     }
   }
 }
 
-// Row accumulation (see the file comment).  Block (row, chunk); each wave
-// takes 64-event tiles of the chunk in turn, picks the events of its row
-// and adds their pairs (lanes over sensors, slot q holding sensor
-// lane + 64 q) into its LDS copy acc[(group * no + m0) * kFit2Stride + term];
-// after the waves' copies come the block's pair counters, one per group.
-// The signals of up to four picked events are loaded before any of them is
-// summed, so their memory latency overlaps.
-__global__ void __launch_bounds__(256) fit2_rows_kernel(Fit2P P) {
-  constexpr int Q = kMaxSensors / 64;
-  constexpr int B = 4;
+// one wave per event chunk: events to their row's list in event order
+__global__ void __launch_bounds__(64) fit2_rowscatter_kernel(Fit2P P, const int* off,
+                                                             int* sorted, int64_t clen) {
+  __shared__ int run[kFit2MaxKnots];
+  const int lane = threadIdx.x, c = blockIdx.x;
+  for (int i = lane; i < P.rows; i += 64) run[i] = off[(int64_t)c * P.rows + i];
+  __syncthreads();
+  const int64_t e0 = (int64_t)c * clen, e1 = e0 + clen < P.n ? e0 + clen : P.n;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int64_t base = e0; base < e1; base += 64) {
+    const int64_t e = base + lane;
+    int r = -1;
+    if (e < e1) {
+      bool kept;
+      r = fit2_event_row(P, e, kept);
+    }
+    uint64_t left = __ballot(r >= 0);
+    while (left) {
+      const int l = __builtin_ctzll(left);
+      const int r0 = __shfl(r, l);
+      const uint64_t m = __ballot(r == r0);
+      const int b0 = run[r0];
+      if (r == r0) sorted[b0 + __popcll(m & lt)] = (int)e;
+      __syncthreads();
+      if (lane == 0) run[r0] = b0 + __popcll(m);
+      __syncthreads();
+      left &= ~m;
+    }
+  }
+}
+
+// block (row, segment, batch): the batch's members are the active sensors
+// whose group lies in [g0, g0 + gb), in sensor order; the block's waves
+// take consecutive parts of the segment, pairs in member-major order, each
+// wave summing into its own LDS copy
+// acc[((group - g0) * no + m0) * kFit2Stride + term], then the block adds
+// them in wave order to part[seg][row][group][m0][term]
+__global__ void __launch_bounds__(128) fit2_rowsort_kernel(Fit2P P, const int* sorted,
+                                                           const int* rstart, int segs, int gb) {
   extern __shared__ double f2s[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-  const int row = blockIdx.x % P.rows, chunk = blockIdx.x / P.rows;
-  const int per = P.groups * P.no * kFit2Stride;
+  const int row = blockIdx.x % P.rows;
+  const int seg = (blockIdx.x / P.rows) % segs;
+  const int batch = blockIdx.x / (P.rows * segs);
+  const int g0 = batch * gb;
+  const int gn = P.groups - g0 < gb ? P.groups - g0 : gb;
+  const int per = gb * P.no * kFit2Stride;
   double* acc = f2s + (int64_t)wave * per;
   unsigned long long* cnt = (unsigned long long*)(f2s + (int64_t)nwv * per);
+  int* mem = (int*)(cnt + gb);   // [kMaxSensors] member slots
+  __shared__ int nm_s;
   for (int i = lane; i < per; i += 64) acc[i] = 0.0;
-  for (int i = threadIdx.x; i < P.groups; i += blockDim.x) cnt[i] = 0ull;
-  int scol[Q], sgr[Q];
-  double sX[Q], sY[Q], sg[Q];
+  for (int i = threadIdx.x; i < gb; i += blockDim.x) cnt[i] = 0ull;
+  if (threadIdx.x == 0) {
+    int k = 0;
+    for (int a = 0; a < P.na; ++a) {
+      const int gr = P.group[P.col[a]];
+      if (gr >= g0 && gr < g0 + gn) mem[k++] = a;
+    }
+    nm_s = k;
+  }
+  __syncthreads();
+  const int nm = nm_s;
+  const int rs = rstart[row], rl = rstart[row + 1] - rs;
+  const int sl = (rl + segs - 1) / segs;
+  const int s0 = rs + seg * sl;
+  const int s1 = s0 + sl < rs + rl ? s0 + sl : rs + rl;
+  if (nm > 0 && s1 > s0) {
+    const int wl = (s1 - s0 + nwv - 1) / nwv;
+    const int w0 = s0 + wave * wl;
+    const int w1 = w0 + wl < s1 ? w0 + wl : s1;
+    const int ne = w1 > w0 ? w1 - w0 : 0;
+    const int64_t np = (int64_t)ne * nm;
+    // pairs member-major: the lanes of a pass hold different events (their
+    // patch origins differ more often than those of one event's sensors)
+    for (int64_t p = lane; p < np; p += 64) {
+      const int j = (int)(p / ne), i = (int)(p - (int64_t)j * ne);
+      const int64_t ev = sorted[w0 + i];
+      const int a = mem[j];
+      const int col = P.col[a];
+      double xe = P.x[ev], ye = P.y[ev];
+      if (P.shift) {
+        xe += (double)P.shift[2 * ev];
+        ye += (double)P.shift[2 * ev + 1];
+      }
+      const double w = P.rz ? (double)P.z[ev] : ye;
+      double u;
+      if (P.rz) {
+        const double dx = xe - P.X[a], dy = ye - P.Y[a];
+        u = sqrt(dx * dx + dy * dy);
+      } else {
+        u = xe;
+      }
+      int m0, m1;
+      double t0, t1;
+      if (!locate64(u, P.nb0, P.lo0, P.hi0, P.inv_d0, m0, t0)) continue;
+      if (!locate64(w, P.nb1, P.lo1, P.hi1, P.inv_d1, m1, t1)) continue;   // in the row
+      double b0[4], b1[4];
+      bweights64(t0, b0);
+      bweights64(t1, b1);
+      double tg = (double)P.sig[ev * P.ld + col] / ((double)P.E[ev] * P.g[a]);
+      if (P.base) {
+        const double dx = xe - P.X[a], dy = ye - P.Y[a];
+        tg -= base_value(P, sqrt(dx * dx + dy * dy));
+      }
+      double wt[16];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int a = lane + 64 * q;
-    scol[q] = 0;
-    sgr[q] = -1;
-    sX[q] = sY[q] = 0.0;
-    sg[q] = 1.0;
-    if (a < P.na) {
-      scol[q] = P.col[a];
-      const int gr = P.group[scol[q]];
-      sgr[q] = (gr >= 0 && gr < P.groups) ? gr : -1;
-      sX[q] = P.X[a];
-      sY[q] = P.Y[a];
-      sg[q] = P.g[a];
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) wt[4 * q + pp] = b1[q] * b0[pp];
+      const int gl = P.group[col] - g0;
+      double* o = acc + (gl * P.no + m0) * kFit2Stride;
+      int k = 0;
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii)
+#pragma unroll
+        for (int jj = ii; jj < 16; ++jj) atomicAdd(&o[k++], wt[ii] * wt[jj]);
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) atomicAdd(&o[136 + ii], wt[ii] * tg);
+      atomicAdd(&cnt[gl], 1ull);
     }
   }
   __syncthreads();
-  const int64_t e0 = (int64_t)chunk * P.chunk_len;
-  const int64_t e1 = e0 + P.chunk_len < P.n ? e0 + P.chunk_len : P.n;
-  for (int64_t base = e0 + 64 * wave; base < e1; base += 64 * nwv) {
-    const int64_t e = base + lane;
-    bool take = false, ok = false;
-    int m1 = 0;
-    double t1 = 0.0;
-    if (e < e1) {
-      ok = fit2_keep(P, e);
-      double w = P.rz ? (double)P.z[e] : (double)P.y[e];
-      if (!P.rz && P.shift) w += (double)P.shift[2 * e + 1];
-      take = ok && locate64(w, P.nb1, P.lo1, P.hi1, P.inv_d1, m1, t1) && m1 == row;
-    }
-    if (row == 0) {   // every kept event once, from its chunk's row-0 block
-      const uint64_t okm = __ballot(ok);
-      if (lane == 0 && okm) atomicAdd(P.used, (unsigned long long)__popcll(okm));
-    }
-    uint64_t m = __ballot(take);
-    while (m) {
-      int lv[B];
-#pragma unroll
-      for (int c = 0; c < B; ++c) {
-        lv[c] = m ? __builtin_ctzll(m) : -1;
-        m &= m - 1;
-      }
-      float sv[B][Q];
-      double xe[B], ye[B], Ee[B], te[B];
-#pragma unroll
-      for (int c = 0; c < B; ++c) {
-        xe[c] = ye[c] = te[c] = 0.0;
-        Ee[c] = 1.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) sv[c][q] = 0.f;
-        if (lv[c] < 0) continue;   // uniform
-        const int64_t ev = base + lv[c];
-        te[c] = __shfl(t1, lv[c]);
-        xe[c] = P.x[ev];
-        ye[c] = P.y[ev];
-        if (P.shift) {
-          xe[c] += (double)P.shift[2 * ev];
-          ye[c] += (double)P.shift[2 * ev + 1];
-        }
-        Ee[c] = P.E[ev];
-        const float* srow = P.sig + ev * P.ld;
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-          if (sgr[q] >= 0) sv[c][q] = srow[scol[q]];
-      }
-#pragma unroll
-      for (int c = 0; c < B; ++c) {
-        if (lv[c] < 0) continue;   // uniform
-        double b1[4];
-        bweights64(te[c], b1);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          if (sgr[q] < 0) continue;
-          double u;
-          if (P.rz) {
-            const double dx = xe[c] - sX[q], dy = ye[c] - sY[q];
-            u = sqrt(dx * dx + dy * dy);
-          } else {
-            u = xe[c];
-          }
-          int m0;
-          double t0;
-          if (!locate64(u, P.nb0, P.lo0, P.hi0, P.inv_d0, m0, t0)) continue;
-          double b0[4];
-          bweights64(t0, b0);
-          double tg = (double)sv[c][q] / (Ee[c] * sg[q]);
-          if (P.base) {
-            const double dx = xe[c] - sX[q], dy = ye[c] - sY[q];
-            tg -= base_value(P, sqrt(dx * dx + dy * dy));
-          }
-          double wt[16];
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq)
-#pragma unroll
-            for (int p = 0; p < 4; ++p) wt[4 * qq + p] = b1[qq] * b0[p];
-          double* o = acc + (sgr[q] * P.no + m0) * kFit2Stride;
-          int k = 0;
-#pragma unroll
-          for (int i = 0; i < 16; ++i)
-#pragma unroll
-            for (int jj = i; jj < 16; ++jj) atomicAdd(&o[k++], wt[i] * wt[jj]);
-#pragma unroll
-          for (int i = 0; i < 16; ++i) atomicAdd(&o[136 + i], wt[i] * tg);
-          atomicAdd(&cnt[sgr[q]], 1ull);
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // the block's sum over its waves, in wave order, to its chunk's slot
-  const int terms = P.groups * P.no * kFit2Terms;
-  double* dst = P.part + ((int64_t)chunk * P.rows + row) * terms;
-  for (int i = threadIdx.x; i < terms; i += blockDim.x) {
+  const int64_t terms = (int64_t)P.groups * P.no * kFit2Terms;
+  double* dst = P.part + ((int64_t)seg * P.rows + row) * terms + (int64_t)g0 * P.no * kFit2Terms;
+  const int bterms = gn * P.no * kFit2Terms;
+  for (int i = threadIdx.x; i < bterms; i += blockDim.x) {
     const int o = i / kFit2Terms, t = i - o * kFit2Terms;
     const int li = o * kFit2Stride + t;
     double s = f2s[li];
     for (int w = 1; w < nwv; ++w) s += f2s[(int64_t)w * per + li];
     dst[i] = s;
   }
-  // pair counts: integer sums, exact in any order
-  for (int g = threadIdx.x; g < P.groups; g += blockDim.x)
-    if (cnt[g]) atomicAdd(&P.pairs[g], cnt[g]);
+  for (int g = threadIdx.x; g < gn; g += blockDim.x)
+    if (cnt[g]) atomicAdd(&P.pairs[g0 + g], cnt[g]);
 }
 
 // chunk sums in chunk order: sums[row][i] = sum over c of part[c][row][i]
@@ -592,28 +582,35 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
     return set_error(ANTS_E_ARG, "%s: set on another device", who);
   const int nc0 = cfg->nb[0] + 2, nc1 = cfg->nb[1] + 2, nc = nc0 * nc1, bw = 3 * nc0 + 3;
   const int rows = cfg->nb[1] - 1, no = cfg->nb[0] - 1;
-  // row accumulation when two waves' copies of a row's sums fit in LDS
-  const size_t per_wave = (size_t)n_groups * no * kFit2Stride * sizeof(double);
-  const size_t cnt_bytes = (size_t)n_groups * sizeof(unsigned long long);
-  int nwv = 0;
-  for (int w = 4; w >= 2 && !nwv; w >>= 1)
-    if (w * per_wave + cnt_bytes <= (size_t)kFit2LdsBytes) nwv = w;
-  int chunks = 0;
-  int64_t chunk_len = 0;
-  if (nwv && n_events > 0) {
-    const int64_t tile = 64 * nwv;
-    const int64_t want = ((int64_t)num_cu() * 4 + rows - 1) / rows;
-    chunk_len = (n_events + want - 1) / want;
-    chunk_len = (chunk_len + tile - 1) / tile * tile;
-    chunks = (int)((n_events + chunk_len - 1) / chunk_len);
+  // events bucketed by row; batches of gb groups on two waves, segs
+  // segments per row; cchunks event chunks of clen for the bucketing
+  const size_t sort_fixed = kMaxSensors * sizeof(int) + 64;
+  const size_t per_group = (size_t)no * kFit2Stride * sizeof(double);
+  int gb = 0, nbatch = 0, segs = 0, cchunks = 0;
+  int64_t clen = 0;
+  if (n_events > 0) {
+    if (n_events > INT32_MAX)
+      return set_error(ANTS_E_UNSUPPORTED, "%s: more than 2^31 - 1 events", who);
+    gb = (int)(((size_t)kFit2LdsBytes - sort_fixed) / (2 * per_group + sizeof(unsigned long long)));
+    if (gb > n_groups) gb = n_groups;
+    if (gb < 1) return set_error(ANTS_E_UNSUPPORTED, "%s: nb[0] = %d too large", who, cfg->nb[0]);
+    nbatch = (n_groups + gb - 1) / gb;
+    segs = (int)(((int64_t)num_cu() * 4 + (int64_t)rows * nbatch - 1) / ((int64_t)rows * nbatch));
+    segs = segs < 1 ? 1 : (segs > 64 ? 64 : segs);
+    clen = (n_events + 1023) / 1024;
+    clen = clen < 1024 ? 1024 : clen;
+    clen = (clen + 255) / 256 * 256;
+    cchunks = (int)((n_events + clen - 1) / clen);
   }
   const int64_t terms = (int64_t)n_groups * no * kFit2Terms;
   const size_t nband = (size_t)n_groups * nc * (bw + 1), nrhs = (size_t)n_groups * nc;
   const size_t zbytes = (nband + 2 * nrhs) * sizeof(double) +
                         ((size_t)n_groups + 1) * sizeof(unsigned long long);
   const size_t zpad = (zbytes + 255) / 256 * 256;
-  const size_t pbytes = chunks ? (size_t)(chunks + 1) * rows * terms * sizeof(double) : 0;
-  hipError_t e = ensure(&set->ws_fit2, &set->ws_fit2_bytes, zpad + pbytes);
+  const size_t pbytes = segs ? (size_t)(segs + 1) * rows * terms * sizeof(double) : 0;
+  const size_t ibytes = cchunks ? ((size_t)2 * cchunks * rows + rows + 1 + (size_t)n_events) *
+                                      sizeof(int) : 0;
+  hipError_t e = ensure(&set->ws_fit2, &set->ws_fit2_bytes, zpad + pbytes + ibytes);
   if (e != hipSuccess) return hip_error(e, who);
   double* band = (double*)set->ws_fit2;
   double* rhs = band + nband;
@@ -621,7 +618,11 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
   unsigned long long* pairs = (unsigned long long*)(ywork + nrhs);
   unsigned long long* used = pairs + n_groups;
   double* part = (double*)((char*)set->ws_fit2 + zpad);
-  double* sums = part + (size_t)chunks * rows * terms;
+  double* sums = part + (size_t)segs * rows * terms;
+  int* rcnt = (int*)((char*)set->ws_fit2 + zpad + pbytes);
+  int* roff = rcnt + (size_t)cchunks * rows;
+  int* rstart = roff + (size_t)cchunks * rows;
+  int* sorted = rstart + rows + 1;
   hipStream_t s = (hipStream_t)hip_stream;
   const int64_t nz = (int64_t)(zbytes / sizeof(double));
   hipLaunchKernelGGL(fit2_zero_kernel, dim3((unsigned)std::min<int64_t>((nz + 255) / 256, 4096)),
@@ -676,33 +677,38 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
     P.used = used;
     P.rows = rows;
     P.no = no;
-    P.chunks = chunks;
-    P.chunk_len = chunk_len;
     P.part = part;
-    if (nwv) {
-      const size_t smem = nwv * per_wave + cnt_bytes;
-      e = hipFuncSetAttribute((const void*)fit2_rows_kernel,
+    {
+      hipLaunchKernelGGL(fit2_rowcount_kernel, dim3((unsigned)cchunks), dim3(256), 0, s, P, rcnt,
+                         clen);
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_error(e, who);
+      hipLaunchKernelGGL(fit2_rowscan_kernel, dim3(1), dim3(64), 0, s, (const int*)rcnt, roff,
+                         rstart, rows, cchunks);
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_error(e, who);
+      hipLaunchKernelGGL(fit2_rowscatter_kernel, dim3((unsigned)cchunks), dim3(64), 0, s, P,
+                         (const int*)roff, sorted, clen);
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_error(e, who);
+      const size_t smem = 2 * gb * per_group + gb * sizeof(unsigned long long) + sort_fixed;
+      e = hipFuncSetAttribute((const void*)fit2_rowsort_kernel,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
       if (e != hipSuccess) return hip_error(e, who);
-      hipLaunchKernelGGL(fit2_rows_kernel, dim3((unsigned)(rows * chunks)), dim3(64 * nwv), smem,
-                         s, P);
+      hipLaunchKernelGGL(fit2_rowsort_kernel, dim3((unsigned)(rows * segs * nbatch)), dim3(128),
+                         smem, s, P, (const int*)sorted, (const int*)rstart, segs, gb);
       e = hipGetLastError();
       if (e != hipSuccess) return hip_error(e, who);
       const int64_t nsum = (int64_t)rows * terms;
       hipLaunchKernelGGL(fit2_chunks_kernel,
                          dim3((unsigned)std::min<int64_t>((nsum + 255) / 256, 4096)), dim3(256), 0,
-                         s, (const double*)part, sums, chunks, nsum);
+                         s, (const double*)part, sums, segs, nsum);
       e = hipGetLastError();
       if (e != hipSuccess) return hip_error(e, who);
       const int64_t ng = (int64_t)n_groups * nc * (bw + 2);
       hipLaunchKernelGGL(fit2_gather_kernel,
                          dim3((unsigned)std::min<int64_t>((ng + 255) / 256, 4096)), dim3(256), 0,
                          s, (const double*)sums, band, rhs, rows, no, n_groups, nc0, nc, bw);
-    } else {
-      int64_t blocks = (n_events + 3) / 4;
-      const int64_t cap = (int64_t)num_cu() * 8;
-      if (blocks > cap) blocks = cap;
-      hipLaunchKernelGGL(fit2_accum_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, who);

@@ -282,10 +282,10 @@ def _dev2d(r):
     return d
 
 
-# one group: per-row LDS sums (repeatable bits; four waves per block, or
-# two for the 48-breakpoint r axis); many groups: global atomics.  The band
-# solve runs in an LDS window up to about 43 breakpoints on the first axis, from
-# global memory beyond (48)
+# events bucketed by row, per-row LDS sums in batches of groups (one batch
+# for one group; several for rings and the first row); every result repeats
+# bit for bit.  The band solve runs in an LDS window up to about 43
+# breakpoints on the first axis, from global memory beyond (48)
 @pytest.mark.parametrize("k,kind,grouping,shift,nb", [(2, "rz", "shared", False, None),
                                                       (2, "rz", "shared", True, None),
                                                       (2, "rz", "shared", False, (48, 8)),
@@ -314,8 +314,7 @@ def test_2d_fit_matches_oracle(ants, k, kind, grouping, shift, nb):
     coef, counts = ants.fit_lrf2d_grouped(L, cfg, groups, dsig, drec, dsh)
     again, _ = ants.fit_lrf2d_grouped(L, cfg, groups, dsig, drec, dsh)
     torch.cuda.synchronize()
-    if grouping == "shared":
-        np.testing.assert_array_equal(again.cpu().numpy(), coef.cpu().numpy())
+    np.testing.assert_array_equal(again.cpu().numpy(), coef.cpu().numpy())
     use = F.event_mask(r["E"], r["status"])
     x64 = {kk: r[kk].astype(np.float64) for kk in ("x", "y", "z", "E")}
     ref, pairs = F.fit_2d_grouped(kind, lrf.sxy, lrf.gain, lrf.active, sig.astype(np.float64),

@@ -449,12 +449,29 @@ __global__ void __launch_bounds__(64) fit2_solve_lds_kernel(Solve2P P) {
   for (int i = lane; i < nc; i += 64) tr += U[(int64_t)i * W];
   tr = wave_sum(tr);
   const double lam = P.ridge * (tr / nc);
+  // row j of A is read one column ahead (registers), so its memory latency
+  // overlaps the previous column's work
+  constexpr int RA = 4;   // W <= 4 * 64
+  double ra[RA];
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    const int o = lane + 64 * r;
+    ra[r] = o < W ? U[o] : 0.0;
+  }
   int sj = 0;   // j mod W
   for (int j = 0; j < nc; ++j) {
     double* wj = win + sj * W;
-    for (int o = lane; o < W; o += 64) {
-      const double a = U[(int64_t)j * W + o];
-      wj[o] = o == 0 ? a + lam : a;
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int o = lane + 64 * r;
+      if (o < W) wj[o] = o == 0 ? ra[r] + lam : ra[r];
+    }
+    if (j + 1 < nc) {
+#pragma unroll
+      for (int r = 0; r < RA; ++r) {
+        const int o = lane + 64 * r;
+        ra[r] = o < W ? U[(int64_t)(j + 1) * W + o] : 0.0;
+      }
     }
     __syncthreads();
     const int k0 = j - bw > 0 ? j - bw : 0;
@@ -481,10 +498,18 @@ __global__ void __launch_bounds__(64) fit2_solve_lds_kernel(Solve2P P) {
       double t = wj[i - j];
       int sk = s0 + (kb - k0);
       if (sk >= W) sk -= W;
-      for (int k = kb; k < j; ++k) {
-        t -= win[sk * W + (j - k)] * win[sk * W + (i - k)];
-        if (++sk == W) sk = 0;
-      }
+      // k = kb .. j - 1 in order; along k both operands step by W - 1 in
+      // the window until the slot wraps to 0 (two linear runs)
+      const int n = j - kb;
+      const int n1 = n < W - sk ? n : W - sk;
+      const double* pa = win + sk * W + (j - kb);
+      const double* pb = win + sk * W + (i - kb);
+#pragma unroll 8
+      for (int q = 0; q < n1; ++q) t -= pa[q * (W - 1)] * pb[q * (W - 1)];
+      pa = win + (j - kb - n1);
+      pb = win + (i - kb - n1);
+#pragma unroll 8
+      for (int q = 0; q < n - n1; ++q) t -= pa[q * (W - 1)] * pb[q * (W - 1)];
       const double uji = t / d;
       wj[i - j] = uji;
       U[(int64_t)j * W + (i - j)] = uji;

@@ -582,3 +582,34 @@ def test_iterative_sliced_procedure_from_the_true_lrf(ants):
     L0.close()
     tabs = tabs.cpu().numpy()
     np.testing.assert_allclose(models[1].tables, tabs, rtol=0, atol=1e-9 * np.abs(tabs).max())
+
+
+def test_2d_fit_edge_cases(ants):
+    # every event filtered (a depth window past the events): zero counts and
+    # NaN tables; invalid bases and windows are rejected before any launch
+    lrf, sig, r = _inputs2d(2, 2000, 77)
+    L = ants.LrfSet(lrf)
+    dsig, drec = torch.from_numpy(sig).cuda(), _dev2d(r)
+    g = np.zeros(lrf.sxy.shape[0], np.int32)
+    cfg = ants.fit2d_cfg(3, lrf.nb, lrf.lo, lrf.hi, 1e-9, z_window=(1e3, 2e3))
+    coef, counts = ants.fit_lrf2d_grouped(L, cfg, g, dsig, drec)
+    torch.cuda.synchronize()
+    assert (counts.cpu().numpy() == 0).all()
+    assert np.isnan(coef.cpu().numpy()).all()
+    # one event in the window: counted once, its pairs only
+    zs = r["z"].astype(np.float64)
+    k = int(np.argsort(zs)[1000])
+    a, b = zs[k], np.nextafter(zs[k], np.inf)
+    cfg = ants.fit2d_cfg(3, lrf.nb, lrf.lo, lrf.hi, 1e-9, z_window=(a, b))
+    _, counts = ants.fit_lrf2d_grouped(L, cfg, g, dsig, drec)
+    use = F.event_mask(r["E"], r["status"]) & (zs >= a) & (zs < b)
+    assert counts.cpu().numpy()[0, 0] == int(use.sum()) >= 1
+    ax = torch.zeros(lrf.nb[0] + 2, dtype=torch.float64, device="cuda")
+    bad = [ants.fit2d_cfg(3, lrf.nb, lrf.lo, lrf.hi, base=(ax, lrf.nb[0], 0.0, 200.0)),
+           ants.fit2d_cfg(2, lrf.nb, (-50.0, -50.0), (50.0, 50.0), base=(ax, lrf.nb[0], 10.0, 5.0)),
+           ants.fit2d_cfg(3, lrf.nb, lrf.lo, lrf.hi, z_window=(float("nan"), 1.0))]
+    for cfg in bad:
+        with pytest.raises(ants.AntsError) as ei:
+            ants.fit_lrf2d_grouped(L, cfg, g, dsig, drec)
+        assert ei.value.code == ants.E_ARG
+    L.close()

@@ -238,10 +238,18 @@ __global__ void __launch_bounds__(128) fit2_rowsort_kernel(Fit2P P, const int* s
     const int w1 = w0 + wl < s1 ? w0 + wl : s1;
     const int ne = w1 > w0 ? w1 - w0 : 0;
     const int64_t np = (int64_t)ne * nm;
-    // pairs member-major: the lanes of a pass hold different events (their
-    // patch origins differ more often than those of one event's sensors)
+    // XY: pairs member-major, so the lanes of a pass hold different events
+    // (one event's pairs share its origin); r-z: event-major, the sensors
+    // of one event lie at different distances
     for (int64_t p = lane; p < np; p += 64) {
-      const int j = (int)(p / ne), i = (int)(p - (int64_t)j * ne);
+      int i, j;
+      if (P.rz) {
+        i = (int)(p / nm);
+        j = (int)(p - (int64_t)i * nm);
+      } else {
+        j = (int)(p / ne);
+        i = (int)(p - (int64_t)j * ne);
+      }
       const int64_t ev = sorted[w0 + i];
       const int a = mem[j];
       const int col = P.col[a];

@@ -165,8 +165,10 @@ __global__ void gemm_reduce_kernel(GemmP P, int splits) {
 // (L2-resident) straight into the MFMA operand registers, one k-step ahead.  Each product is the
 // same sequence of 16x16x32 MFMAs as in gemm_kernel (FP32 accumulators from
 // zero, k ascending), so hidden activations and outputs equal that path's.
-// Hidden width 256: wave w owns output columns 64w..64w+63 of every layer.
-constexpr int FR = 64, FH = 256, FPITCH = FH + 8;
+// Hidden width 256: wave w owns output columns 64w..64w+63 of every layer,
+// for all FR events (RT row tiles of 16): each weight fragment read from L2
+// feeds RT MFMAs.
+constexpr int FR = 128, FH = 256, FPITCH = FH + 8, RT = FR / 16;
 
 // kernel-argument arrays indexed with constants only (no private copies)
 __device__ __forceinline__ const __bf16* fwd_w(const FwdP& P, int l) {
@@ -176,7 +178,7 @@ __device__ __forceinline__ const float* fwd_b(const FwdP& P, int l) {
   return l == 0 ? P.b[0] : l == 1 ? P.b[1] : l == 2 ? P.b[2] : l == 3 ? P.b[3] : P.b[4];
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 mlp_fwd_kernel(FwdP P) {
   extern __shared__ __align__(16) __bf16 fsm[];
   __bf16* buf = fsm;                     // [FR][FPITCH] activations
@@ -232,9 +234,9 @@ mlp_fwd_kernel(FwdP P) {
   for (int l = 0; l < kFwdMaxLayers; ++l) {
     if (l >= P.layers) break;
     const __bf16* W = fwd_w(P, l);
-    f32x4 acc[4][4];
+    f32x4 acc[RT][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
     bf16x8 b[4], bn[4];
@@ -247,11 +249,11 @@ mlp_fwd_kernel(FwdP P) {
         for (int j = 0; j < 4; ++j)
           bn[j] = *(const bf16x8*)(W + (int64_t)(wave * 64 + j * 16 + fr) * din + k0 + 32 + fk);
       }
-      bf16x8 a[4];
+      bf16x8 a[RT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)(in + (i * 16 + fr) * pitch + k0 + fk);
+      for (int i = 0; i < RT; ++i) a[i] = *(const bf16x8*)(in + (i * 16 + fr) * pitch + k0 + fk);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -266,7 +268,7 @@ mlp_fwd_kernel(FwdP P) {
       const int c = wave * 64 + j * 16 + fr;
       const float bc = bias[c];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           buf[(i * 16 + (lane >> 4) * 4 + r) * FPITCH + c] = to_bf16(fmaxf(acc[i][j][r] + bc, 0.f));
@@ -278,31 +280,35 @@ mlp_fwd_kernel(FwdP P) {
   }
 
   // output layer (4 rows of weights, padded to one 16-column tile): wave w
-  // takes events 16w..16w+15
+  // takes the row tiles w, w + 4, ... (events 16 t..16 t + 15 of tile t)
   {
     const __bf16* W = fwd_w(P, P.layers);
-    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < FH; k0 += 32) {
-      bf16x8 bb;
-      if (fr < 4) {
-        bb = *(const bf16x8*)(W + (int64_t)fr * FH + k0 + fk);
-      } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) bb[q] = (__bf16)0.f;
+    for (int u = 0; u < RT / 4; ++u) {
+      const int t = wave + 4 * u;
+      f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < FH; k0 += 32) {
+        bf16x8 bb;
+        if (fr < 4) {
+          bb = *(const bf16x8*)(W + (int64_t)fr * FH + k0 + fk);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) bb[q] = (__bf16)0.f;
+        }
+        const bf16x8 a = *(const bf16x8*)(in + (t * 16 + fr) * FPITCH + k0 + fk);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
       }
-      const bf16x8 a = *(const bf16x8*)(in + (wave * 16 + fr) * FPITCH + k0 + fk);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
-    }
-    if (fr < 4) {
-      const float bc = fwd_b(P, P.layers)[fr];
-      const float sc = fr == 0 ? P.scale[0] : fr == 1 ? P.scale[1] : P.scale[2];
-      const float of = fr == 0 ? P.offset[0] : fr == 1 ? P.offset[1] : P.offset[2];
+      if (fr < 4) {
+        const float bc = fwd_b(P, P.layers)[fr];
+        const float sc = fr == 0 ? P.scale[0] : fr == 1 ? P.scale[1] : P.scale[2];
+        const float of = fr == 0 ? P.offset[0] : fr == 1 ? P.offset[1] : P.offset[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t e = e0 + wave * 16 + (lane >> 4) * 4 + r;
-        if (e < P.n) {
-          const float y = acc[r] + bc;
-          P.out[e * 4 + fr] = (P.seeds && fr < 3) ? of + sc * y : y;
+        for (int r = 0; r < 4; ++r) {
+          const int64_t e = e0 + t * 16 + (lane >> 4) * 4 + r;
+          if (e < P.n) {
+            const float y = acc[r] + bc;
+            P.out[e * 4 + fr] = (P.seeds && fr < 3) ? of + sc * y : y;
+          }
         }
       }
     }
@@ -492,7 +498,11 @@ hipError_t launch_mlp_fwd(const FwdP& P, hipStream_t s) {
   if (P.kin > FH || P.kin % 32 || P.layers < 1 || P.layers > kFwdMaxLayers || P.na > 64 ||
       P.na > P.kin)
     return hipErrorInvalidValue;
-  const size_t smem = (size_t)FR * FPITCH * sizeof(__bf16);
+  // the activations, or before the first layer the FP32 signal stage
+  // [FR][64] followed by the BF16 inputs [FR][kin + 8], whichever is larger
+  const size_t act = (size_t)FR * FPITCH * sizeof(__bf16);
+  const size_t pre = (size_t)FR * 64 * sizeof(float) + (size_t)FR * (P.kin + 8) * sizeof(__bf16);
+  const size_t smem = act > pre ? act : pre;
   hipError_t e = hipFuncSetAttribute((const void*)mlp_fwd_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;

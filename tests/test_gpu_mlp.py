@@ -78,14 +78,14 @@ def test_forward_matches_reference(ants, det):
 
 
 def test_fused_forward_tails_and_training_path(ants, det):
-    # the fused inference kernel (64 events per block) on ragged sizes, and
+    # the fused inference kernel (128 events per block) on ragged sizes, and
     # against the layer-by-layer path used in training (same MFMA sequence,
     # so the loss from its outputs equals the training path's loss)
     wl, L, sig, truth = det
     lay, net, p = _net(ants, seed=6)
     print("[gpu] fused forward tails", flush=True)
     full = net.forward(L, torch.from_numpy(sig).cuda()).cpu().numpy()
-    for n in (1, 63, 64, 65, 1000):
+    for n in (1, 63, 64, 65, 127, 128, 129, 1000):
         part = net.forward(L, torch.from_numpy(sig[:n].copy()).cuda()).cpu().numpy()
         np.testing.assert_array_equal(part, full[:n])
     ref, _ = R.forward(lay, p, sig[:1000], emulate=True)

@@ -57,12 +57,10 @@ struct Fit2P {
   int zwin;            // 1: only events with zw_lo <= z < zw_hi
   double zw_lo, zw_hi;
   int rz;              // 1: arguments (r, z); 0: (x, y)
-  int nb0, nb1, nc0, nc, bw;
+  int nb0, nb1;
   double lo0, hi0, lo1, hi1, inv_d0, inv_d1;
   const int32_t* group;   // per sensor index
   int groups;
-  double* band;        // [groups][nc][bw + 1]: entry (i, i + k) at [i][k]
-  double* rhs;         // [groups][nc]
   unsigned long long* pairs;   // [groups]
   unsigned long long* used;    // [1]
   // row accumulation: rows = nb1 - 1, no = nb0 - 1 origins per row
@@ -693,9 +691,6 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
     P.rz = cfg->kind == ANTS_LRF_RZ;
     P.nb0 = cfg->nb[0];
     P.nb1 = cfg->nb[1];
-    P.nc0 = nc0;
-    P.nc = nc;
-    P.bw = bw;
     P.lo0 = cfg->lo[0];
     P.hi0 = cfg->hi[0];
     P.lo1 = cfg->lo[1];
@@ -704,8 +699,6 @@ extern "C" ants_status ants_fit_lrf2d_grouped(ants_lrfset* set, const ants_fit2d
     P.inv_d1 = (double)(cfg->nb[1] - 1) / (cfg->hi[1] - cfg->lo[1]);
     P.group = d_group;
     P.groups = n_groups;
-    P.band = band;
-    P.rhs = rhs;
     P.pairs = pairs;
     P.used = used;
     P.rows = rows;
